@@ -1,0 +1,303 @@
+/*
+ * libspmv -- CRS sparse matrix-vector multiplication C = C + A*B on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The operation is the CRS kernel of Schubert, Fehske, Hager and Wellein,
+ * "Hybrid-parallel sparse matrix-vector multiplication with explicit
+ * communication overlap on current multicore-based systems" (2011):
+ *   - storage (Sect. 1.2): val holds the stored entries row by row, row_ptr
+ *     the offset of each row's first entry (N_r + 1 entries), col_idx the
+ *     original column of each entry;
+ *   - kernel (Listing 1): for every row i, C(i) = C(i) + sum over the row's
+ *     entries j of val(j) * B(col_idx(j));
+ *   - split of one process's share (Sect. 3.4): a local part that reads only
+ *     the locally owned RHS elements and a nonlocal part that reads the halo
+ *     elements received from other processes, applied one after the other so
+ *     that the result vector is updated twice.
+ *
+ * Conventions shared by every entry point
+ *   - Every function returns an spmv_status_t; on failure a description is
+ *     available from spmv_last_error() (thread-local, valid until the next
+ *     call from the same thread).  No C++ exception crosses this interface.
+ *   - Host arrays passed to spmv_create_* are deep-copied; the caller may free
+ *     them when the call returns.  All device memory a handle needs is owned
+ *     by the handle and released by spmv_destroy.
+ *   - B, C (and the block arrays) are caller-owned *device* pointers whose
+ *     element type follows the handle's precision (see spmv_precision_t).
+ *     C must not alias B.  The library cannot check that a device pointer is
+ *     large enough: passing short buffers is undefined behaviour.
+ *   - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *     spmv_run / spmv_run_block only enqueue work on it and return; results
+ *     are visible once that stream has reached the enqueued work.
+ *   - Asynchronous device faults surface at the caller's next
+ *     synchronisation, not as a status from the call that enqueued them.
+ *   - Different handles may be used concurrently from different threads; one
+ *     handle must be used by one thread at a time.
+ */
+#ifndef LIBSPMV_SPMV_H
+#define LIBSPMV_SPMV_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct spmv_handle_s *spmv_handle_t;
+
+typedef enum spmv_status {
+    SPMV_OK = 0,
+    SPMV_ERR_INVALID_ARG = -1,     /* bad scalar argument or null pointer */
+    SPMV_ERR_INVALID_MATRIX = -2,  /* CRS arrays violate the format */
+    SPMV_ERR_ALLOC = -3,           /* device or host allocation failed */
+    SPMV_ERR_HIP = -4,             /* a HIP runtime call failed */
+    SPMV_ERR_UNSUPPORTED = -5,     /* valid request this handle cannot serve */
+    SPMV_ERR_STATE = -6            /* destroyed or foreign handle */
+} spmv_status_t;
+
+/*
+ * Storage and arithmetic precision of a handle.  Values are always given to
+ * spmv_create_* as binary64 and rounded once, to nearest with ties to even,
+ * into the storage type (NaN stays NaN, overflow gives +-Inf).
+ *
+ *   mode                    val      B and C   accumulation  bytes per entry
+ *   SPMV_PREC_F64           f64      f64       f64           8 + 4
+ *   SPMV_PREC_F32           f32      f32       f32           4 + 4
+ *   SPMV_PREC_BF16_F32ACC   bfloat16 f32       f32           2 + 4
+ *   SPMV_PREC_F32_F64ACC    f32      f64       f64           4 + 4
+ */
+typedef enum spmv_precision {
+    SPMV_PREC_F64 = 0,
+    SPMV_PREC_F32 = 1,
+    SPMV_PREC_BF16_F32ACC = 2,
+    SPMV_PREC_F32_F64ACC = 3
+} spmv_precision_t;
+
+/* flags for spmv_create_crs / spmv_create_batch */
+#define SPMV_FLAG_ALLOW_PAGEABLE_HALO 0x1u /* accept a pageable B_halo_host (copy then loses overlap) */
+#define SPMV_FLAG_NO_TUNE_CACHE 0x2u       /* ignore the persistent autotuner cache */
+
+/* ---------------------------------------------------------------------------
+ * a1: ingest (Sect. 1.2 storage; the one-time setup of Sect. 3.2)
+ *
+ * spmv_create_crs validates a CRS matrix, shifts it to 0-based indices,
+ * encodes val into the storage precision, records row-length statistics,
+ * picks a kernel plan and uploads the arrays to the current HIP device.
+ *
+ *   n_rows, n_cols  matrix shape, 0 <= n_rows < 2^31 - 1, 0 <= n_cols < 2^31
+ *   nnz             number of stored entries, 0 <= nnz <= INT32_MAX
+ *   row_ptr         host int32[n_rows + 1]; row i holds entries
+ *                   row_ptr[i] - base ... row_ptr[i+1] - base - 1
+ *   col_idx         host int32[nnz], columns in [base, n_cols + base)
+ *   val             host double[nnz]
+ *   index_base      0 or 1 (Listing 1 is written 1-based)
+ *   prec, flags     see above
+ *   out             receives the new handle (set to NULL on failure)
+ *
+ * Unsorted columns, duplicate columns (summed), explicit zeros and empty rows
+ * are allowed.  Errors: SPMV_ERR_INVALID_ARG for bad scalars or null
+ * pointers; SPMV_ERR_INVALID_MATRIX, naming the first offending index, when
+ * row_ptr[0] != base, row_ptr[n_rows] != nnz + base, row_ptr decreases, or a
+ * column lies outside [base, n_cols + base).  Validation happens before any
+ * device call.  SPMV_ERR_ALLOC / SPMV_ERR_HIP for device failures.
+ * ------------------------------------------------------------------------- */
+spmv_status_t spmv_create_crs(int64_t n_rows, int64_t n_cols, int64_t nnz,
+                              const int32_t *row_ptr, const int32_t *col_idx,
+                              const double *val, int32_t index_base,
+                              spmv_precision_t prec, uint32_t flags,
+                              spmv_handle_t *out);
+
+/* ---------------------------------------------------------------------------
+ * a2: local / nonlocal split (Sect. 3.4; bookkeeping done once, Sect. 3.2)
+ *
+ * Builds, on the device, a new handle from plain handle `a` for one process's
+ * share whose locally owned RHS elements are columns [0, halo_begin_col) and
+ * whose halo is the column tail [halo_begin_col, n_cols):
+ *   local part     every entry with column < halo_begin_col, in a CRS with
+ *                  all n_rows rows (row_ptr of n_rows + 1 entries);
+ *   nonlocal part  every entry with column >= halo_begin_col, for the R rows
+ *                  that have one: nl_rows[R] (ascending), nl_ptr[R+1],
+ *                  columns and values.
+ * Entries keep their storage order and global column numbers.  `a` stays
+ * valid and independent; both handles are destroyed separately.
+ * Errors: SPMV_ERR_INVALID_ARG if halo_begin_col is outside [0, n_cols];
+ * SPMV_ERR_UNSUPPORTED if `a` is itself a split or batch handle.
+ * ------------------------------------------------------------------------- */
+spmv_status_t spmv_split_local_nonlocal(spmv_handle_t a, int64_t halo_begin_col,
+                                        spmv_handle_t *out_split);
+
+/* ---------------------------------------------------------------------------
+ * a3-a7, a9: C = C + A*B (Listing 1) on `stream`.
+ *
+ * Plain handle: B has n_cols elements, C n_rows; B_halo_host must be NULL.
+ *
+ * Split handle (a4-a6): B has n_cols elements; its tail [h, n_cols) is the
+ * receive area of the halo.  If B_halo_host is non-NULL it must point to
+ * n_cols - h elements of pinned host memory (hipHostMalloc); they are copied
+ * into B + h on the handle's own copy stream while the local-part kernel runs
+ * on `stream`, and the nonlocal-part kernel runs on `stream` after the copy
+ * has completed (the one-GPU analogue of the explicit overlap of Sect. 3.5).
+ * Pageable memory is rejected with SPMV_ERR_INVALID_ARG unless the handle was
+ * created with SPMV_FLAG_ALLOW_PAGEABLE_HALO, because a copy from pageable
+ * memory does not overlap (nonblocking is not asynchronous, Sect. 3.1).  If
+ * B_halo_host is NULL the tail of B is taken as already resident.  The local
+ * kernel never reads B[h:].
+ *
+ * Batch handle (a9): B and C are the concatenation of every member's vector
+ * in member order (member m's B starts at the sum of the earlier members'
+ * n_cols, its C at the sum of their n_rows); B_halo_host must be NULL.  All
+ * members run in one persistent launch replayed from a HIP graph.
+ * ------------------------------------------------------------------------- */
+spmv_status_t spmv_run(spmv_handle_t h, const void *B, void *C,
+                       const void *B_halo_host, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * a8: block of k right-hand sides, C[:, t] = C[:, t] + A*B[:, t], t < k,
+ * with A streamed once per column tile.  B is row-major [n_cols x ldb], C is
+ * row-major [n_rows x ldc] (element (r, t) at r*ld + t), 1 <= k <= 64,
+ * ldb >= k, ldc >= k.  Plain handles only (SPMV_ERR_UNSUPPORTED otherwise).
+ * ------------------------------------------------------------------------- */
+spmv_status_t spmv_run_block(spmv_handle_t h, int32_t k, const void *B, int64_t ldb,
+                             void *C, int64_t ldc, void *stream);
+
+/* Releases a handle and its device memory after waiting for the handle's
+ * internal copy stream.  spmv_destroy(NULL) is SPMV_OK; a destroyed or
+ * foreign handle gives SPMV_ERR_STATE. */
+spmv_status_t spmv_destroy(spmv_handle_t h);
+
+/* Description of the last failure on the calling thread ("" if none). */
+const char *spmv_last_error(void);
+
+/* ---------------------------------------------------------------------------
+ * a9: batch of independent products C_m = C_m + A_m * B_m (setup).
+ *
+ * count members; member m is given exactly as to spmv_create_crs by
+ * n_rows[m], n_cols[m], nnz[m], row_ptr[m], col_idx[m], val[m].  All members
+ * share index_base, prec and flags.  The members' arrays are pooled in one
+ * device allocation and cut into tiles of bounded nonzero count; spmv_run
+ * walks the tile queue with one persistent launch.  Errors as for
+ * spmv_create_crs, naming the member.
+ * ------------------------------------------------------------------------- */
+spmv_status_t spmv_create_batch(int32_t count, const int64_t *n_rows, const int64_t *n_cols,
+                                const int64_t *nnz, const int32_t *const *row_ptr,
+                                const int32_t *const *col_idx, const double *const *val,
+                                int32_t index_base, spmv_precision_t prec, uint32_t flags,
+                                spmv_handle_t *out);
+
+/* ---------------------------------------------------------------------------
+ * a10: kernel plans and the autotuner.
+ *
+ * A plan says how rows are mapped to the GPU for one part of a handle
+ * (SPMV_PART_MAIN: the whole matrix, the local part of a split handle, or
+ * every member of a batch; SPMV_PART_NONLOCAL: the nonlocal part).
+ *   kernel       SPMV_KERNEL_STREAM: rows are grouped into tiles of at most
+ *                256 * tile_items stored entries; a 256-thread workgroup
+ *                streams a tile's val and col_idx with coalesced loads, forms
+ *                the products in LDS and reduces each row there.
+ *                SPMV_KERNEL_VECTOR: `lanes` lanes of a wavefront share one
+ *                row and reduce it with cross-lane shuffles.
+ *   tile_items   4, 8 or 16 (stream kernel)
+ *   lanes        2, 4, 8, 16, 32 or 64 (vector kernel)
+ *   nontemporal  1: val and col_idx are loaded with the streaming hint so
+ *                they do not displace B from the caches
+ *   xcd_remap    1: consecutive tiles are placed on the same XCD (each of
+ *                MI355X's eight XCDs has its own L2)
+ *   block_kt     columns of B processed per pass by spmv_run_block (4, 8,
+ *                16); 0 lets the library choose
+ * ------------------------------------------------------------------------- */
+#define SPMV_KERNEL_STREAM 1
+#define SPMV_KERNEL_VECTOR 2
+#define SPMV_PART_MAIN 0
+#define SPMV_PART_NONLOCAL 1
+
+typedef struct spmv_plan {
+    int32_t kernel;
+    int32_t tile_items;
+    int32_t lanes;
+    int32_t nontemporal;
+    int32_t xcd_remap;
+    int32_t block_kt;
+} spmv_plan_t;
+
+spmv_status_t spmv_get_plan(spmv_handle_t h, int32_t part, spmv_plan_t *plan);
+spmv_status_t spmv_set_plan(spmv_handle_t h, int32_t part, const spmv_plan_t *plan);
+
+/* Times candidate plans for every part of `h` (block products when k > 1)
+ * on scratch vectors, keeps the fastest, and records it in the persistent
+ * cache (file named by SPMV_TUNE_CACHE, default $HOME/.cache/libspmv_tune.json)
+ * keyed by device, precision, k and the row-length statistics.  Synchronous. */
+spmv_status_t spmv_tune(spmv_handle_t h, int32_t k, void *stream);
+
+/* ---------------------------------------------------------------------------
+ * Introspection (for tests and tools).
+ * ------------------------------------------------------------------------- */
+#define SPMV_KIND_PLAIN 0
+#define SPMV_KIND_SPLIT 1
+#define SPMV_KIND_BATCH 2
+
+typedef struct spmv_info {
+    int32_t kind;          /* SPMV_KIND_* */
+    int32_t precision;     /* spmv_precision_t */
+    int64_t n_rows, n_cols, nnz;
+    int64_t halo_begin;    /* split: first halo column; else n_cols */
+    int64_t nnz_local, nnz_nonlocal, n_nonlocal_rows;
+    int32_t batch_count;   /* batch: members; else 1 */
+    int64_t n_tiles;       /* stream-kernel tiles of the main part */
+    double row_len_mean, row_len_cv;
+    int64_t row_len_max;
+} spmv_info_t;
+
+spmv_status_t spmv_get_info(spmv_handle_t h, spmv_info_t *info);
+
+/* Copies one of the handle's device arrays to host memory `dst` of `bytes`
+ * bytes (synchronous).  If dst is NULL only *size_bytes is set.
+ *   SPMV_ARR_ROW_PTR, _COL, _VAL: the matrix (split: the local part), 0-based,
+ *     val in storage precision (f64, f32 or bfloat16 codes as uint16);
+ *   SPMV_ARR_NL_ROWS, _NL_PTR, _NL_COL, _NL_VAL: the nonlocal part. */
+#define SPMV_ARR_ROW_PTR 0
+#define SPMV_ARR_COL 1
+#define SPMV_ARR_VAL 2
+#define SPMV_ARR_NL_ROWS 3
+#define SPMV_ARR_NL_PTR 4
+#define SPMV_ARR_NL_COL 5
+#define SPMV_ARR_NL_VAL 6
+
+spmv_status_t spmv_export(spmv_handle_t h, int32_t which, void *dst, int64_t bytes,
+                          int64_t *size_bytes);
+
+/* ---------------------------------------------------------------------------
+ * Measurement probes (the GPU stand-ins for the STREAM benchmark of Sect. 2
+ * and the asynchrony test of Listing 2 / Sect. 3.1).
+ *   spmv_probe_copy   dst[i] = src[i] for n doubles
+ *   spmv_probe_triad  a[i] = b[i] + s * c[i] for n doubles
+ *   spmv_probe_spin   one wavefront waits `nanoseconds` on the GPU's constant-rate
+ *                     clock without touching memory (at most 10 s)
+ * ------------------------------------------------------------------------- */
+spmv_status_t spmv_probe_copy(double *dst, const double *src, int64_t n, void *stream);
+spmv_status_t spmv_probe_triad(double *a, const double *b, const double *c, double s,
+                               int64_t n, void *stream);
+spmv_status_t spmv_probe_spin(int64_t nanoseconds, void *stream);
+
+/* Schedule used by spmv_run (for measurement and for callers that need it).
+ * Split handles:
+ *   SPMV_SCHEDULE_OVERLAP       halo copy on the copy stream beside the local
+ *                               kernel (default)
+ *   SPMV_SCHEDULE_SERIAL        halo copy, local and nonlocal kernels in order
+ *                               on `stream` (split without asynchrony)
+ * Batch handles:
+ *   SPMV_SCHEDULE_BATCH_GRAPH   counter reset + persistent launch replayed from
+ *                               a HIP graph captured per (B, C) (default)
+ *   SPMV_SCHEDULE_BATCH_DIRECT  the same two launches without a graph
+ *   SPMV_SCHEDULE_BATCH_FLAT    one workgroup per tile, no counter */
+#define SPMV_SCHEDULE_OVERLAP 0
+#define SPMV_SCHEDULE_SERIAL 1
+#define SPMV_SCHEDULE_BATCH_GRAPH 0
+#define SPMV_SCHEDULE_BATCH_DIRECT 2
+#define SPMV_SCHEDULE_BATCH_FLAT 3
+spmv_status_t spmv_set_schedule(spmv_handle_t h, int32_t schedule);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* LIBSPMV_SPMV_H */

@@ -1,0 +1,614 @@
+// gfx950 kernels of the CRS product C = C + A*B (the kernel of Listing 1 of
+// Schubert, Fehske, Hager, Wellein 2011, with the storage of Sect. 1.2).
+//
+// The loop is bound by memory bandwidth (code balance of Eq. (1): at least
+// 6 bytes per flop in FP64), so nothing here uses the matrix cores; the
+// kernels are organised around moving val / col_idx at full HBM rate:
+//   * stream kernel: the planner cuts the rows into tiles of at most
+//     256 * E stored entries; a 256-thread workgroup reads its tile's val and
+//     col_idx with fully coalesced loads (E per lane, all issued before the
+//     gathers of B), writes the products to LDS and reduces each row there
+//     with L lanes per row (L chosen per tile from its row count).
+//   * vector kernel: L lanes of a wavefront share a row, stride through it
+//     and combine their partial sums with cross-lane shuffles.
+//   * block kernel: k right-hand sides; a tile's col_idx / val are staged in
+//     LDS once and each row is handled by KT/VW lanes holding VW columns.
+//   * batch kernels: many matrices; tiles of all members form one queue that
+//     a persistent grid drains through an atomic counter.
+// val and col_idx are read with the nontemporal hint so the single-use
+// matrix stream does not evict B from L2 / MALL.  Tile numbers can be
+// remapped so that each of the eight XCDs (each with a private L2) gets a
+// contiguous range of rows and therefore a compact window of B.
+//
+// Accumulators start at -0.0, the additive identity of IEEE arithmetic, so a
+// row whose products are all -0.0 keeps the sign the sequential loop gives;
+// rows without entries leave C untouched.
+#include <hip/hip_runtime.h>
+
+#include "spmv_internal.h"
+
+namespace spmv {
+namespace {
+
+constexpr int WG = 256;
+constexpr int NXCD = 8;
+
+template <int P> struct Ty;
+template <> struct Ty<P_F64> { using V = double;   using X = double; };
+template <> struct Ty<P_F32> { using V = float;    using X = float;  };
+template <> struct Ty<P_BF16> { using V = uint16_t; using X = float;  };
+template <> struct Ty<P_F32_F64> { using V = float; using X = double; };
+// In every mode the accumulator has the type of B and C.
+
+template <class T, bool NT>
+__device__ __forceinline__ T ld(const T *p) {
+  if constexpr (NT) return __builtin_nontemporal_load(p);
+  else return *p;
+}
+
+template <class X, class V>
+__device__ __forceinline__ X widen(V v) { return static_cast<X>(v); }
+template <>
+__device__ __forceinline__ float widen<float, uint16_t>(uint16_t v) {
+  return __uint_as_float(static_cast<uint32_t>(v) << 16);
+}
+
+template <class X> __device__ __forceinline__ X neg_zero() { return static_cast<X>(-0.0); }
+
+// Tile `bid` of `n` -> the tile it processes.  Workgroups are handed to the
+// XCDs round-robin (bid % 8); XCD x receives the contiguous range of tiles
+// starting at x*q + min(x, r).  A bijection of [0, n).
+__device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t n, int remap) {
+  if (!remap) return bid;
+  const int64_t x = bid % NXCD, i = bid / NXCD;
+  const int64_t q = n / NXCD, r = n % NXCD;
+  return x * q + (x < r ? x : r) + i;
+}
+
+__device__ __forceinline__ int floor_pow2(int v) { return 1 << (31 - __builtin_clz(v)); }
+
+// ---------------------------------------------------------------------------
+// One tile of the stream kernel: rows [r0, r1) of a CRS part.
+// ---------------------------------------------------------------------------
+template <int P, int E, bool NT>
+__device__ __forceinline__ void stream_tile(const int32_t *__restrict__ rp,
+                                            const int32_t *__restrict__ col,
+                                            const typename Ty<P>::V *__restrict__ val,
+                                            const int32_t *__restrict__ row_ids, int r0, int r1,
+                                            const typename Ty<P>::X *__restrict__ x,
+                                            typename Ty<P>::X *__restrict__ y,
+                                            typename Ty<P>::X *s_prod) {
+  using V = typename Ty<P>::V;
+  using X = typename Ty<P>::X;
+  constexpr int TILE = WG * E;
+  const int tid = threadIdx.x;
+  const int p0 = rp[r0];
+  const int p1 = rp[r1];
+  const int nnz = p1 - p0;
+
+  if (nnz > TILE) {
+    // A row longer than a tile; the planner gives such a row a tile of its own.
+    X acc = neg_zero<X>();
+    for (int j = p0 + tid; j < p1; j += WG)
+      acc += widen<X>(ld<V, NT>(val + j)) * x[ld<int32_t, NT>(col + j)];
+    s_prod[tid] = acc;
+    __syncthreads();
+    for (int off = WG / 2; off > 0; off >>= 1) {
+      if (tid < off) s_prod[tid] += s_prod[tid + off];
+      __syncthreads();
+    }
+    if (tid == 0) {
+      const int64_t o = row_ids ? row_ids[r0] : r0;
+      y[o] = y[o] + s_prod[0];
+    }
+    return;
+  }
+
+  // Phase 1: coalesced loads of the tile's col_idx and val, all in flight
+  // before the gathers of B, products into LDS.
+  int c[E];
+  V v[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = e * WG + tid;
+    if (k < nnz) {
+      c[e] = ld<int32_t, NT>(col + p0 + k);
+      v[e] = ld<V, NT>(val + p0 + k);
+    }
+  }
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = e * WG + tid;
+    if (k < nnz) s_prod[k] = widen<X>(v[e]) * x[c[e]];
+  }
+  __syncthreads();
+
+  // Phase 2: per-row sums out of LDS.
+  const int nrows = r1 - r0;
+  if (nrows <= WG) {
+    const int L = min(floor_pow2(WG / nrows), 64);
+    const int lg = __builtin_ctz(L);
+    const int row = tid >> lg;
+    const int lane = tid & (L - 1);
+    int a = 0, b = 0;
+    if (row < nrows) {
+      a = rp[r0 + row] - p0;
+      b = rp[r0 + row + 1] - p0;
+    }
+    X acc = neg_zero<X>();
+    for (int j = a + lane; j < b; j += L) acc += s_prod[j];
+    for (int off = L >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0 && b > a) {
+      const int64_t o = row_ids ? row_ids[r0 + row] : (int64_t)(r0 + row);
+      y[o] = y[o] + acc;
+    }
+  } else {
+    for (int row = tid; row < nrows; row += WG) {
+      const int a = rp[r0 + row] - p0;
+      const int b = rp[r0 + row + 1] - p0;
+      if (b > a) {
+        X acc = neg_zero<X>();
+        for (int j = a; j < b; ++j) acc += s_prod[j];
+        const int64_t o = row_ids ? row_ids[r0 + row] : (int64_t)(r0 + row);
+        y[o] = y[o] + acc;
+      }
+    }
+  }
+}
+
+template <int P, int E, bool NT>
+__global__ __launch_bounds__(WG) void k_stream(CsrDev A, const int32_t *__restrict__ tiles,
+                                               int64_t n_tiles, int remap, const void *xv,
+                                               void *yv) {
+  using V = typename Ty<P>::V;
+  using X = typename Ty<P>::X;
+  __shared__ X s_prod[WG * E];
+  const int64_t t = xcd_tile(blockIdx.x, n_tiles, remap);
+  stream_tile<P, E, NT>(A.row_ptr, A.col, static_cast<const V *>(A.val), A.row_ids, tiles[t],
+                        tiles[t + 1], static_cast<const X *>(xv), static_cast<X *>(yv), s_prod);
+}
+
+// ---------------------------------------------------------------------------
+// Vector kernel: L lanes per row, rows_per_wg consecutive rows per workgroup.
+// ---------------------------------------------------------------------------
+template <int P, int L, bool NT>
+__global__ __launch_bounds__(WG) void k_vector(CsrDev A, int64_t rows_per_wg, int64_t n_wg,
+                                               int remap, const void *xv, void *yv) {
+  using V = typename Ty<P>::V;
+  using X = typename Ty<P>::X;
+  constexpr int G = WG / L;
+  const V *__restrict__ val = static_cast<const V *>(A.val);
+  const X *__restrict__ x = static_cast<const X *>(xv);
+  X *__restrict__ y = static_cast<X *>(yv);
+  const int64_t b = xcd_tile(blockIdx.x, n_wg, remap);
+  const int64_t rb = b * rows_per_wg;
+  const int64_t re = min(rb + rows_per_wg, A.n_rows);
+  const int g = threadIdx.x / L;
+  const int lane = threadIdx.x % L;
+  for (int64_t base = rb; base < re; base += G) {
+    const int64_t r = base + g;
+    int a = 0, e = 0;
+    if (r < re) {
+      a = A.row_ptr[r];
+      e = A.row_ptr[r + 1];
+    }
+    X acc = neg_zero<X>();
+    for (int j = a + lane; j < e; j += L)
+      acc += widen<X>(ld<V, NT>(val + j)) * x[ld<int32_t, NT>(A.col + j)];
+    for (int off = L >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0 && e > a) {
+      const int64_t o = A.row_ids ? A.row_ids[r] : r;
+      y[o] = y[o] + acc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Block kernel: columns [t0, t0 + KT) of k right-hand sides.  Each row is
+// handled by G = KT / VW lanes; lane l owns columns t0 + l*VW .. + VW - 1.
+// ---------------------------------------------------------------------------
+template <class X, int VW> struct VecT;
+template <> struct VecT<double, 1> { using T = double; };
+template <> struct VecT<double, 2> { using T = double2; };
+template <> struct VecT<float, 1> { using T = float; };
+template <> struct VecT<float, 2> { using T = float2; };
+template <> struct VecT<float, 4> { using T = float4; };
+
+template <class X, int VW>
+__device__ __forceinline__ void load_vec(const X *p, X (&out)[VW]) {
+  if constexpr (VW == 1) {
+    out[0] = *p;
+  } else {
+    using T = typename VecT<X, VW>::T;
+    const T t = *reinterpret_cast<const T *>(p);
+    const X *q = reinterpret_cast<const X *>(&t);
+#pragma unroll
+    for (int i = 0; i < VW; ++i) out[i] = q[i];
+  }
+}
+
+template <int P, int E, int KT, int VW, bool NT>
+__global__ __launch_bounds__(WG) void k_block(CsrDev A, const int32_t *__restrict__ tiles,
+                                              int64_t n_tiles, int remap, int k, int t0,
+                                              const void *Bv, int64_t ldb, void *Cv, int64_t ldc) {
+  using V = typename Ty<P>::V;
+  using X = typename Ty<P>::X;
+  constexpr int TILE = WG * E;
+  constexpr int G = KT / VW;
+  constexpr int NG = WG / G;
+  static_assert(WG * VW <= TILE, "reduction buffer must fit in s_val");
+  __shared__ int32_t s_col[TILE];
+  __shared__ X s_val[TILE];
+  const V *__restrict__ val = static_cast<const V *>(A.val);
+  const X *__restrict__ B = static_cast<const X *>(Bv);
+  X *__restrict__ C = static_cast<X *>(Cv);
+  const int tid = threadIdx.x;
+  const int64_t t = xcd_tile(blockIdx.x, n_tiles, remap);
+  const int r0 = tiles[t], r1 = tiles[t + 1];
+  const int p0 = A.row_ptr[r0], p1 = A.row_ptr[r1];
+  const int nnz = p1 - p0;
+  const int g = tid / G;
+  const int lane = tid % G;
+  const int cb = t0 + lane * VW;
+  const bool active = cb < k;  // VW divides k whenever VW > 1
+
+  if (nnz > TILE) {
+    // One long row: every group takes every NG-th entry, then the groups'
+    // partial sums are combined in LDS in group order.
+    X acc[VW];
+#pragma unroll
+    for (int i = 0; i < VW; ++i) acc[i] = neg_zero<X>();
+    if (active) {
+      for (int j = p0 + g; j < p1; j += NG) {
+        const int c = ld<int32_t, NT>(A.col + j);
+        const X a = widen<X>(ld<V, NT>(val + j));
+        X bv[VW];
+        load_vec<X, VW>(B + (int64_t)c * ldb + cb, bv);
+#pragma unroll
+        for (int i = 0; i < VW; ++i) acc[i] += a * bv[i];
+      }
+    }
+#pragma unroll
+    for (int i = 0; i < VW; ++i) s_val[(g * G + lane) * VW + i] = acc[i];
+    __syncthreads();
+    if (g == 0 && active) {
+      const int64_t o = A.row_ids ? A.row_ids[r0] : r0;
+#pragma unroll
+      for (int i = 0; i < VW; ++i) {
+        X s = neg_zero<X>();
+        for (int q = 0; q < NG; ++q) s += s_val[(q * G + lane) * VW + i];
+        C[o * ldc + cb + i] = C[o * ldc + cb + i] + s;
+      }
+    }
+    return;
+  }
+
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int kk = e * WG + tid;
+    if (kk < nnz) {
+      s_col[kk] = ld<int32_t, NT>(A.col + p0 + kk);
+      s_val[kk] = widen<X>(ld<V, NT>(val + p0 + kk));
+    }
+  }
+  __syncthreads();
+  if (!active) return;
+  const int nrows = r1 - r0;
+  for (int rr = g; rr < nrows; rr += NG) {
+    const int a = A.row_ptr[r0 + rr] - p0;
+    const int b = A.row_ptr[r0 + rr + 1] - p0;
+    if (b == a) continue;
+    X acc[VW];
+#pragma unroll
+    for (int i = 0; i < VW; ++i) acc[i] = neg_zero<X>();
+    int j = a;
+    for (; j + 2 <= b; j += 2) {
+      const int c0 = s_col[j], c1 = s_col[j + 1];
+      const X a0 = s_val[j], a1 = s_val[j + 1];
+      X b0[VW], b1[VW];
+      load_vec<X, VW>(B + (int64_t)c0 * ldb + cb, b0);
+      load_vec<X, VW>(B + (int64_t)c1 * ldb + cb, b1);
+#pragma unroll
+      for (int i = 0; i < VW; ++i) {
+        acc[i] += a0 * b0[i];
+        acc[i] += a1 * b1[i];
+      }
+    }
+    if (j < b) {
+      const int c0 = s_col[j];
+      const X a0 = s_val[j];
+      X b0[VW];
+      load_vec<X, VW>(B + (int64_t)c0 * ldb + cb, b0);
+#pragma unroll
+      for (int i = 0; i < VW; ++i) acc[i] += a0 * b0[i];
+    }
+    const int64_t o = A.row_ids ? A.row_ids[r0 + rr] : (int64_t)(r0 + rr);
+#pragma unroll
+    for (int i = 0; i < VW; ++i) C[o * ldc + cb + i] = C[o * ldc + cb + i] + acc[i];
+  }
+}
+
+// ---------------------------------------------------------------------------
+// Batch kernels: tile t of the queue is (member, r0, r1); member arrays are
+// found through the descriptor table.
+// ---------------------------------------------------------------------------
+template <int P, int E, bool NT>
+__device__ __forceinline__ void batch_tile(const int32_t *rp, const int32_t *col, const void *val,
+                                           const BatchDesc *desc, const BatchTile &T,
+                                           const void *xv, void *yv,
+                                           typename Ty<P>::X *s_prod) {
+  using V = typename Ty<P>::V;
+  using X = typename Ty<P>::X;
+  const BatchDesc D = desc[T.member];
+  stream_tile<P, E, NT>(rp + D.rp_off, col + D.nz_off, static_cast<const V *>(val) + D.nz_off,
+                        nullptr, T.r0, T.r1, static_cast<const X *>(xv) + D.x_off,
+                        static_cast<X *>(yv) + D.y_off, s_prod);
+}
+
+__global__ void k_batch_reset(int32_t *counter) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
+}
+
+// Persistent grid: each workgroup takes the next tile from the counter
+// until the queue is empty; every workgroup reaches the exit test.
+template <int P, int E, bool NT>
+__global__ __launch_bounds__(WG) void k_batch_persistent(const int32_t *__restrict__ rp,
+                                                         const int32_t *__restrict__ col,
+                                                         const void *val, const BatchDesc *desc,
+                                                         const BatchTile *tiles, int64_t n_tiles,
+                                                         int32_t *counter, const void *xv,
+                                                         void *yv) {
+  using X = typename Ty<P>::X;
+  __shared__ X s_prod[WG * E];
+  __shared__ int32_t s_t;
+  for (;;) {
+    if (threadIdx.x == 0) s_t = atomicAdd(counter, 1);
+    __syncthreads();
+    const int32_t t = s_t;
+    if (t >= n_tiles) break;
+    const BatchTile T = tiles[t];
+    batch_tile<P, E, NT>(rp, col, val, desc, T, xv, yv, s_prod);
+    __syncthreads();
+  }
+}
+
+// One workgroup per tile (no counter).
+template <int P, int E, bool NT>
+__global__ __launch_bounds__(WG) void k_batch_flat(const int32_t *__restrict__ rp,
+                                                   const int32_t *__restrict__ col,
+                                                   const void *val, const BatchDesc *desc,
+                                                   const BatchTile *tiles, int64_t n_tiles,
+                                                   const void *xv, void *yv) {
+  using X = typename Ty<P>::X;
+  __shared__ X s_prod[WG * E];
+  const int64_t t = xcd_tile(blockIdx.x, n_tiles, 1);
+  const BatchTile T = tiles[t];
+  batch_tile<P, E, NT>(rp, col, val, desc, T, xv, yv, s_prod);
+}
+
+// ---------------------------------------------------------------------------
+// Dispatch helpers
+// ---------------------------------------------------------------------------
+template <int P, int E>
+hipError_t run_stream(const CsrDev &A, const PlanDev &pl, const int32_t *tiles, int64_t n_tiles,
+                      const void *x, void *y, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  if (pl.nontemporal)
+    hipLaunchKernelGGL((k_stream<P, E, true>), dim3((unsigned)n_tiles), dim3(WG), 0, s, A, tiles,
+                       n_tiles, pl.xcd_remap, x, y);
+  else
+    hipLaunchKernelGGL((k_stream<P, E, false>), dim3((unsigned)n_tiles), dim3(WG), 0, s, A, tiles,
+                       n_tiles, pl.xcd_remap, x, y);
+  return hipGetLastError();
+}
+
+template <int P, int L>
+hipError_t run_vector(const CsrDev &A, const PlanDev &pl, const void *x, void *y, hipStream_t s) {
+  if (A.n_rows <= 0) return hipSuccess;
+  const int64_t rows_per_wg = (int64_t)(WG / L) * 8;
+  const int64_t n_wg = (A.n_rows + rows_per_wg - 1) / rows_per_wg;
+  if (pl.nontemporal)
+    hipLaunchKernelGGL((k_vector<P, L, true>), dim3((unsigned)n_wg), dim3(WG), 0, s, A,
+                       rows_per_wg, n_wg, pl.xcd_remap, x, y);
+  else
+    hipLaunchKernelGGL((k_vector<P, L, false>), dim3((unsigned)n_wg), dim3(WG), 0, s, A,
+                       rows_per_wg, n_wg, pl.xcd_remap, x, y);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t dispatch_spmv(const CsrDev &A, const PlanDev &pl, const int32_t *tiles, int64_t n_tiles,
+                         const void *x, void *y, hipStream_t s) {
+  if (pl.kernel == 2) {
+    switch (pl.lanes) {
+      case 2: return run_vector<P, 2>(A, pl, x, y, s);
+      case 4: return run_vector<P, 4>(A, pl, x, y, s);
+      case 8: return run_vector<P, 8>(A, pl, x, y, s);
+      case 16: return run_vector<P, 16>(A, pl, x, y, s);
+      case 32: return run_vector<P, 32>(A, pl, x, y, s);
+      case 64: return run_vector<P, 64>(A, pl, x, y, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (pl.tile_items) {
+    case 4: return run_stream<P, 4>(A, pl, tiles, n_tiles, x, y, s);
+    case 8: return run_stream<P, 8>(A, pl, tiles, n_tiles, x, y, s);
+    case 16: return run_stream<P, 16>(A, pl, tiles, n_tiles, x, y, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int P, int KT, int VW>
+hipError_t run_block_kt(const CsrDev &A, const int32_t *tiles, int64_t n_tiles, int nt, int remap,
+                        int k, int t0, const void *B, int64_t ldb, void *C, int64_t ldc,
+                        hipStream_t s) {
+  if (nt)
+    hipLaunchKernelGGL((k_block<P, 4, KT, VW, true>), dim3((unsigned)n_tiles), dim3(WG), 0, s, A,
+                       tiles, n_tiles, remap, k, t0, B, ldb, C, ldc);
+  else
+    hipLaunchKernelGGL((k_block<P, 4, KT, VW, false>), dim3((unsigned)n_tiles), dim3(WG), 0, s, A,
+                       tiles, n_tiles, remap, k, t0, B, ldb, C, ldc);
+  return hipGetLastError();
+}
+
+template <int P, int VW>
+hipError_t run_block_vw(const CsrDev &A, const int32_t *tiles, int64_t n_tiles, int nt, int remap,
+                        int kt, int k, int t0, const void *B, int64_t ldb, void *C, int64_t ldc,
+                        hipStream_t s) {
+  switch (kt) {
+    case 4: return run_block_kt<P, 4, VW>(A, tiles, n_tiles, nt, remap, k, t0, B, ldb, C, ldc, s);
+    case 8: return run_block_kt<P, 8, VW>(A, tiles, n_tiles, nt, remap, k, t0, B, ldb, C, ldc, s);
+    case 16: return run_block_kt<P, 16, VW>(A, tiles, n_tiles, nt, remap, k, t0, B, ldb, C, ldc, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int P>
+hipError_t dispatch_block(const CsrDev &A, const int32_t *tiles, int64_t n_tiles, int nt, int remap,
+                          int kt, int k, const void *B, int64_t ldb, void *C, int64_t ldc,
+                          hipStream_t s) {
+  using X = typename Ty<P>::X;
+  constexpr int VWIDE = sizeof(X) == 8 ? 2 : 4;
+  // Wide column loads need every lane's first column aligned to VWIDE.
+  const bool wide = (k % VWIDE == 0) && (ldb % VWIDE == 0) && (ldc % VWIDE == 0) &&
+                    (kt % VWIDE == 0) &&
+                    (reinterpret_cast<uintptr_t>(B) % (sizeof(X) * VWIDE) == 0) &&
+                    (reinterpret_cast<uintptr_t>(C) % (sizeof(X) * VWIDE) == 0);
+  for (int t0 = 0; t0 < k; t0 += kt) {
+    hipError_t e = wide ? run_block_vw<P, VWIDE>(A, tiles, n_tiles, nt, remap, kt, k, t0, B, ldb, C,
+                                                 ldc, s)
+                        : run_block_vw<P, 1>(A, tiles, n_tiles, nt, remap, kt, k, t0, B, ldb, C,
+                                             ldc, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <int P, int E>
+hipError_t run_persistent(const int32_t *rp, const int32_t *col, const void *val,
+                          const BatchDesc *desc, const BatchTile *tiles, int64_t n_tiles, int nt,
+                          int32_t *counter, int grid, const void *x, void *y, hipStream_t s) {
+  if (nt)
+    hipLaunchKernelGGL((k_batch_persistent<P, E, true>), dim3(grid), dim3(WG), 0, s, rp, col, val,
+                       desc, tiles, n_tiles, counter, x, y);
+  else
+    hipLaunchKernelGGL((k_batch_persistent<P, E, false>), dim3(grid), dim3(WG), 0, s, rp, col, val,
+                       desc, tiles, n_tiles, counter, x, y);
+  return hipGetLastError();
+}
+
+template <int P, int E>
+hipError_t run_flat(const int32_t *rp, const int32_t *col, const void *val, const BatchDesc *desc,
+                    const BatchTile *tiles, int64_t n_tiles, int nt, const void *x, void *y,
+                    hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  if (nt)
+    hipLaunchKernelGGL((k_batch_flat<P, E, true>), dim3((unsigned)n_tiles), dim3(WG), 0, s, rp, col,
+                       val, desc, tiles, n_tiles, x, y);
+  else
+    hipLaunchKernelGGL((k_batch_flat<P, E, false>), dim3((unsigned)n_tiles), dim3(WG), 0, s, rp,
+                       col, val, desc, tiles, n_tiles, x, y);
+  return hipGetLastError();
+}
+
+template <int P, int E>
+int persistent_grid_for(int device) {
+  int per_cu = 0, n_cu = 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_batch_persistent<P, E, true>, WG,
+                                                   0) != hipSuccess)
+    per_cu = 1;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess)
+    n_cu = 256;
+  return (per_cu < 1 ? 1 : per_cu) * n_cu;
+}
+
+}  // namespace
+
+#define SPMV_PREC_SWITCH(prec, CALL) \
+  switch (prec) {                    \
+    case P_F64: { constexpr int PP = P_F64; return CALL; } \
+    case P_F32: { constexpr int PP = P_F32; return CALL; } \
+    case P_BF16: { constexpr int PP = P_BF16; return CALL; } \
+    case P_F32_F64: { constexpr int PP = P_F32_F64; return CALL; } \
+    default: return hipErrorInvalidValue; \
+  }
+
+hipError_t launch_spmv(int prec, const CsrDev &A, const PlanDev &plan, const int32_t *tiles,
+                       int64_t n_tiles, const void *x, void *y, hipStream_t s) {
+  SPMV_PREC_SWITCH(prec, (dispatch_spmv<PP>(A, plan, tiles, n_tiles, x, y, s)))
+}
+
+hipError_t launch_spmv_block(int prec, const CsrDev &A, const int32_t *tiles, int64_t n_tiles,
+                             int tile_items, int nontemporal, int xcd_remap, int kt, int k,
+                             const void *B, int64_t ldb, void *C, int64_t ldc, hipStream_t s) {
+  if (tile_items != 4) return hipErrorInvalidValue;
+  if (n_tiles <= 0) return hipSuccess;
+  SPMV_PREC_SWITCH(prec, (dispatch_block<PP>(A, tiles, n_tiles, nontemporal, xcd_remap, kt, k, B,
+                                              ldb, C, ldc, s)))
+}
+
+hipError_t launch_batch_reset(int32_t *counter, hipStream_t s) {
+  hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(64), 0, s, counter);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t persistent_e(const int32_t *rp, const int32_t *col, const void *val,
+                               const BatchDesc *desc, const BatchTile *tiles, int64_t n_tiles,
+                               int tile_items, int nt, int32_t *counter, int grid, const void *x,
+                               void *y, hipStream_t s) {
+  switch (tile_items) {
+    case 4: return run_persistent<P, 4>(rp, col, val, desc, tiles, n_tiles, nt, counter, grid, x, y, s);
+    case 8: return run_persistent<P, 8>(rp, col, val, desc, tiles, n_tiles, nt, counter, grid, x, y, s);
+    case 16: return run_persistent<P, 16>(rp, col, val, desc, tiles, n_tiles, nt, counter, grid, x, y, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_batch_persistent(int prec, const int32_t *rp, const int32_t *col, const void *val,
+                                   const BatchDesc *desc, const BatchTile *tiles, int64_t n_tiles,
+                                   int tile_items, int nontemporal, int32_t *counter, int grid,
+                                   const void *x, void *y, hipStream_t s) {
+  SPMV_PREC_SWITCH(prec, (persistent_e<PP>(rp, col, val, desc, tiles, n_tiles, tile_items,
+                                           nontemporal, counter, grid, x, y, s)))
+}
+
+template <int P>
+static hipError_t flat_e(const int32_t *rp, const int32_t *col, const void *val,
+                         const BatchDesc *desc, const BatchTile *tiles, int64_t n_tiles,
+                         int tile_items, int nt, const void *x, void *y, hipStream_t s) {
+  switch (tile_items) {
+    case 4: return run_flat<P, 4>(rp, col, val, desc, tiles, n_tiles, nt, x, y, s);
+    case 8: return run_flat<P, 8>(rp, col, val, desc, tiles, n_tiles, nt, x, y, s);
+    case 16: return run_flat<P, 16>(rp, col, val, desc, tiles, n_tiles, nt, x, y, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_batch_flat(int prec, const int32_t *rp, const int32_t *col, const void *val,
+                             const BatchDesc *desc, const BatchTile *tiles, int64_t n_tiles,
+                             int tile_items, int nontemporal, const void *x, void *y,
+                             hipStream_t s) {
+  SPMV_PREC_SWITCH(prec, (flat_e<PP>(rp, col, val, desc, tiles, n_tiles, tile_items, nontemporal,
+                                     x, y, s)))
+}
+
+template <int P>
+static int grid_e(int tile_items, int device) {
+  switch (tile_items) {
+    case 4: return persistent_grid_for<P, 4>(device);
+    case 8: return persistent_grid_for<P, 8>(device);
+    default: return persistent_grid_for<P, 16>(device);
+  }
+}
+
+int batch_persistent_grid(int prec, int tile_items, int device) {
+  switch (prec) {
+    case P_F64: return grid_e<P_F64>(tile_items, device);
+    case P_F32: return grid_e<P_F32>(tile_items, device);
+    case P_BF16: return grid_e<P_BF16>(tile_items, device);
+    default: return grid_e<P_F32_F64>(tile_items, device);
+  }
+}
+
+}  // namespace spmv

@@ -1,0 +1,103 @@
+// Internal declarations shared by the runtime (api.cpp) and the gfx950
+// kernels (*.hip).  Not part of the public interface.
+#pragma once
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+namespace spmv {
+
+// Element types of the four precision modes: stored value VT, vector XT
+// (B and C), accumulator AT.  bfloat16 values are carried as uint16 codes.
+enum Prec : int { P_F64 = 0, P_F32 = 1, P_BF16 = 2, P_F32_F64 = 3 };
+
+inline int val_bytes(int p) { return p == P_F64 ? 8 : (p == P_BF16 ? 2 : 4); }
+inline int vec_bytes(int p) { return (p == P_F64 || p == P_F32_F64) ? 8 : 4; }
+
+// One CRS part on the device.  Row r of the part holds entries
+// row_ptr[r] .. row_ptr[r+1]-1 and adds into C[row_ids ? row_ids[r] : r].
+struct CsrDev {
+  const int32_t *row_ptr;
+  const int32_t *col;
+  const void *val;
+  const int32_t *row_ids;
+  int64_t n_rows;
+};
+
+struct PlanDev {
+  int kernel;       // 1 stream, 2 vector
+  int tile_items;   // stream: products per thread (tile = 256 * tile_items)
+  int lanes;        // vector: lanes per row
+  int nontemporal;  // streaming hint on val / col
+  int xcd_remap;    // place consecutive tiles on one XCD
+};
+
+// Per-member descriptor of a batch: offsets into the pooled arrays.
+struct BatchDesc {
+  int64_t rp_off;   // first row_ptr entry of the member (local row_ptr values)
+  int64_t nz_off;   // first col / val entry
+  int64_t x_off;    // first element of the member's B
+  int64_t y_off;    // first element of the member's C
+};
+
+// Tile of a batch: member and row range [r0, r1) of that member.
+struct BatchTile {
+  int32_t member;
+  int32_t r0;
+  int32_t r1;
+  int32_t pad;
+};
+
+// ---- launchers (kernels.hip) -------------------------------------------------
+// All return hipSuccess or the launch error.  `tiles` (stream kernel) holds
+// n_tiles + 1 row starts of the tiles of `A`.
+hipError_t launch_spmv(int prec, const CsrDev &A, const PlanDev &plan, const int32_t *tiles,
+                       int64_t n_tiles, const void *x, void *y, hipStream_t s);
+
+hipError_t launch_spmv_block(int prec, const CsrDev &A, const int32_t *tiles, int64_t n_tiles,
+                             int tile_items, int nontemporal, int xcd_remap, int kt, int k,
+                             const void *B, int64_t ldb, void *C, int64_t ldc, hipStream_t s);
+
+hipError_t launch_batch_reset(int32_t *counter, hipStream_t s);
+
+hipError_t launch_batch_persistent(int prec, const int32_t *rp, const int32_t *col, const void *val,
+                                   const BatchDesc *desc, const BatchTile *tiles, int64_t n_tiles,
+                                   int tile_items, int nontemporal, int32_t *counter, int grid,
+                                   const void *x, void *y, hipStream_t s);
+
+hipError_t launch_batch_flat(int prec, const int32_t *rp, const int32_t *col, const void *val,
+                             const BatchDesc *desc, const BatchTile *tiles, int64_t n_tiles,
+                             int tile_items, int nontemporal, const void *x, void *y, hipStream_t s);
+
+int batch_persistent_grid(int prec, int tile_items, int device);
+
+// ---- split bookkeeping (split.hip) -------------------------------------------
+struct SplitOut {
+  int32_t *loc_row_ptr;  // [n_rows + 1]
+  int32_t *loc_col;      // [nnz_loc]
+  void *loc_val;         // [nnz_loc]
+  int32_t *nl_rows;      // [R]
+  int32_t *nl_ptr;       // [R + 1]
+  int32_t *nl_col;       // [nnz_nl]
+  void *nl_val;          // [nnz_nl]
+};
+
+// First pass: per-row counts and their exclusive scans into `work`
+// (3 * (n_rows + 1) int32 plus scan scratch); returns the totals.
+hipError_t split_count(const int32_t *row_ptr, const int32_t *col, int64_t n_rows, int32_t h,
+                       int32_t *work, int32_t *scan_tmp, int64_t *nnz_loc, int64_t *nnz_nl,
+                       int64_t *n_nl_rows, hipStream_t s);
+int64_t split_work_elems(int64_t n_rows);
+int64_t scan_tmp_elems(int64_t n);
+
+hipError_t split_fill(int prec, const int32_t *row_ptr, const int32_t *col, const void *val,
+                      int64_t n_rows, int32_t h, const int32_t *work, int64_t nnz_nl, int64_t R,
+                      const SplitOut &out, hipStream_t s);
+
+// ---- probes (probes.hip) -------------------------------------------------------
+hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t s);
+hipError_t launch_triad(double *a, const double *b, const double *c, double sc, int64_t n,
+                        hipStream_t s);
+hipError_t launch_spin(int64_t cycles, hipStream_t s);
+
+}  // namespace spmv

@@ -1,0 +1,592 @@
+"""GPU path against the oracle, element by element, through the C interface.
+
+Sizes here keep the oracle to seconds while spanning many tiles and a ragged
+tail; the benchmark sizes are covered in test_gpu_fullsize.py."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import (FP64_TOL, assert_close, gpu_spmv, oracle_ref, prec_bounds, rounded_inputs,
+                      to_dev)
+from paper_1106_5908_amd import spmv
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+NOTUNE = spmv.SPMV_FLAG_NO_TUNE_CACHE
+
+
+def _matrices():
+    A27, x27 = gen.workload_c2(n=30)          # 27000 rows, 27-point, perturbed
+    A3, x3 = gen.workload_c3(N=100_000)       # irregular symmetric
+    return {"27pt": (A27, x27), "irregular": (A3, x3)}
+
+
+MATS = None
+
+
+def mats():
+    global MATS
+    if MATS is None:
+        MATS = _matrices()
+    return MATS
+
+
+PLANS = ([dict(kernel=1, tile_items=e, nontemporal=nt, xcd_remap=rm)
+          for e in (4, 8, 16) for nt in (0, 1) for rm in (0, 1)] +
+         [dict(kernel=2, lanes=l) for l in (2, 4, 8, 16, 32, 64)])
+
+
+def _pid(p):
+    return "-".join(f"{k}{v}" for k, v in p.items())
+
+
+# ---------------------------------------------------------------------------- a3
+
+def test_small_laplacian():
+    A, x = gen.workload_c1()
+    ref, den = oracle_ref(A, x)
+    got = gpu_spmv(A, x)
+    assert_close(got, ref, den, FP64_TOL, "2D 5-point 64x64")
+    xi = gen.integer_vector(A.n_cols, gen.rng_for(1, 9))
+    assert np.array_equal(gpu_spmv(A, xi), oracle.spmv(A.row_ptr, A.col_idx, A.val, xi))
+
+
+@pytest.mark.parametrize("plan", PLANS, ids=_pid)
+@pytest.mark.parametrize("name", ["27pt", "irregular"])
+def test_plans(name, plan):
+    A, x = mats()[name]
+    c0 = gen.uniform_vector(A.n_rows, gen.rng_for(7, 2))
+    ref, den = oracle_ref(A, x, c0)
+    got = gpu_spmv(A, x, c0, plan=plan)
+    assert_close(got, ref, den, FP64_TOL, f"{name} {plan}")
+
+
+@pytest.mark.parametrize("plan", PLANS, ids=_pid)
+def test_integer_inputs_bit_exact(plan):
+    rng = gen.rng_for(8, 0)
+    A = gen.random_crs(5000, 4000, rng, max_len=40, integer_values=True)
+    x = gen.integer_vector(A.n_cols, rng)
+    c0 = gen.integer_vector(A.n_rows, rng)
+    got = gpu_spmv(A, x, c0, plan=plan)
+    assert np.array_equal(got, oracle.spmv(A.row_ptr, A.col_idx, A.val, x, c0))
+
+
+def _long_row_matrix(long_len, n_short=300, n_cols=20000, seed=3):
+    rng = gen.rng_for(10, seed)
+    counts = np.concatenate([rng.integers(0, 30, size=n_short // 2), [long_len],
+                             rng.integers(0, 30, size=n_short - n_short // 2)])
+    cols = rng.integers(0, n_cols, size=int(counts.sum()))
+    vals = rng.standard_normal(cols.size)
+    return gen._finish(counts.size, n_cols, counts, cols, vals)
+
+
+@pytest.mark.parametrize("long_len", [1023, 1024, 1025, 2048, 2049, 4096, 4097, 50_000])
+@pytest.mark.parametrize("plan", [dict(kernel=1, tile_items=e) for e in (4, 8, 16)] +
+                         [dict(kernel=2, lanes=64)], ids=_pid)
+def test_long_rows(long_len, plan):
+    A = _long_row_matrix(long_len)
+    x = gen.uniform_vector(A.n_cols, gen.rng_for(10, 5))
+    ref, den = oracle_ref(A, x)
+    assert_close(gpu_spmv(A, x, plan=plan), ref, den, FP64_TOL, f"long row {long_len}")
+
+
+def test_edge_shapes():
+    rng = gen.rng_for(11, 0)
+    import torch
+    # no rows
+    A = gen.CRS(0, 5, np.zeros(1, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    assert gpu_spmv(A, np.ones(5)).size == 0
+    # no columns: every row empty, C untouched (signs of zero included)
+    c0 = np.array([1.5, -0.0, 0.0, -2.0])
+    A = gen.CRS(4, 0, np.zeros(5, np.int32), np.zeros(0, np.int32), np.zeros(0))
+    got = gpu_spmv(A, np.zeros(0), c0)
+    assert np.array_equal(got, c0) and np.array_equal(np.signbit(got), np.signbit(c0))
+    # rectangular, both ways, with empty rows, duplicates and unsorted columns
+    for (m, n) in ((1000, 3000), (3000, 10), (1, 70000), (70000, 1)):
+        A = gen.random_crs(m, n, rng, max_len=12)
+        x = gen.uniform_vector(n, rng)
+        c0 = gen.uniform_vector(m, rng)
+        ref, den = oracle_ref(A, x, c0)
+        assert_close(gpu_spmv(A, x, c0), ref, den, FP64_TOL, f"{m}x{n}")
+    # 1-based input gives the same product
+    A = gen.random_crs(2000, 2000, rng, max_len=20)
+    x = gen.uniform_vector(2000, rng)
+    assert np.array_equal(gpu_spmv(A, x, base=1), gpu_spmv(A, x, base=0))
+    del torch
+
+
+def test_signed_zero_and_special_values():
+    # products that are all -0.0 keep C0 = -0.0 negative, as the sequential loop does
+    A = gen.CRS(3, 2, np.array([0, 2, 3, 3], np.int32), np.array([0, 1, 0], np.int32),
+                np.array([-1.0, -1.0, 2.0]))
+    x = np.array([0.0, 0.0])
+    c0 = np.array([-0.0, -0.0, -0.0])
+    got = gpu_spmv(A, x, c0)
+    ref = oracle.spmv(A.row_ptr, A.col_idx, A.val, x, c0)
+    assert np.array_equal(np.signbit(got), np.signbit(ref))
+    # Inf and NaN propagate like the oracle
+    rng = gen.rng_for(12, 0)
+    A = gen.random_crs(3000, 3000, rng, max_len=10)
+    A.val[::97] = np.inf
+    A.val[::89] = -np.inf
+    x = gen.uniform_vector(3000, rng)
+    x[::500] = np.nan
+    ref, den = oracle_ref(A, x)
+    got = gpu_spmv(A, x)
+    assert np.array_equal(np.isnan(got), np.isnan(ref))
+    fin = np.isfinite(ref)
+    assert np.array_equal(got[~fin & ~np.isnan(ref)], ref[~fin & ~np.isnan(ref)])
+    assert_close(got[fin], ref[fin], den[fin], FP64_TOL, "finite rows")
+
+
+def test_determinism():
+    A, x = mats()["irregular"]
+    a = gpu_spmv(A, x, runs=3)
+    b = gpu_spmv(A, x, runs=3)
+    assert np.array_equal(a, b)
+
+
+def test_accumulates_into_c():
+    A, x = mats()["27pt"]
+    xi = np.round(x * 8)
+    Ai = gen.stencil_27pt_3d(30)
+    got = gpu_spmv(Ai, xi, runs=3)
+    assert np.array_equal(got, 3 * oracle.spmv(Ai.row_ptr, Ai.col_idx, Ai.val, xi))
+
+
+# ---------------------------------------------------------------------------- a1
+
+SPECIAL = np.array([0.0, -0.0, 1.0, 1 + 2 ** -8, 1 + 3 * 2 ** -8, 1 + 2 ** -24, 1 + 2 ** -23 + 2 ** -24,
+                    3.0e38, 3.4e38, 3.5e38, 1e39, 1e-40, 9.1e-41, 5e-324, 1e-300, np.inf, -np.inf,
+                    np.nan, 1.00000001, -7.5, 2.0 ** -126, 2.0 ** -127, 2.0 ** -133, 2.0 ** -134,
+                    1.5 * 2.0 ** -134, 65504.0, 1 / 3])
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f32f64"])
+def test_ingest_export_matches_oracle_encoding(prec):
+    rng = gen.rng_for(13, 0)
+    A = gen.random_crs(4000, 500, rng, max_len=16)
+    A.val[: SPECIAL.size] = SPECIAL
+    A.val[SPECIAL.size:] *= 10.0 ** rng.integers(-40, 38, size=A.val.size - SPECIAL.size)
+    for base in (0, 1):
+        h = spmv.spmv_create_crs(A.row_ptr + base, A.col_idx + base, A.val, A.n_cols,
+                                 index_base=base, prec=prec, flags=NOTUNE)
+        try:
+            assert np.array_equal(spmv.spmv_export(h, spmv.SPMV_ARR_ROW_PTR), A.row_ptr)
+            assert np.array_equal(spmv.spmv_export(h, spmv.SPMV_ARR_COL), A.col_idx)
+            v = spmv.spmv_export(h, spmv.SPMV_ARR_VAL)
+            info = spmv.spmv_get_info(h)
+        finally:
+            spmv.spmv_destroy(h)
+        if prec == "f64":
+            assert np.array_equal(v.view(np.uint64), A.val.view(np.uint64))
+        elif prec == "bf16":
+            exp = oracle.round_bf16(A.val)
+            nan = np.isnan(A.val)
+            assert np.array_equal(v[~nan], exp[~nan])
+            assert np.all((v[nan] & 0x7FFF) == 0x7FC0)
+        else:
+            exp = oracle.round_f32(A.val)
+            nan = np.isnan(A.val)
+            assert np.array_equal(v[~nan].view(np.uint32), exp[~nan].view(np.uint32))
+            assert np.all(np.isnan(v[nan]))
+        rl = np.diff(A.row_ptr)
+        assert info["nnz"] == A.nnz and info["row_len_max"] == rl.max()
+        assert abs(info["row_len_mean"] - rl.mean()) < 1e-9
+
+
+# ---------------------------------------------------------------------------- a2, a4-a6
+
+def _split_handles(A, h_begin, prec="f64", flags=NOTUNE):
+    a = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, prec=prec, flags=flags)
+    s = spmv.spmv_split_local_nonlocal(a, h_begin)
+    return a, s
+
+
+@pytest.mark.parametrize("prec", ["f64", "bf16"])
+@pytest.mark.parametrize("where", ["band", "zero", "all", "mid"])
+def test_split_bookkeeping_bit_exact(prec, where):
+    A, x = mats()["irregular"]
+    h_begin = {"band": gen.halo_begin(A.n_cols), "zero": 0, "all": A.n_cols,
+               "mid": A.n_cols // 2 + 1}[where]
+    a, s = _split_handles(A, h_begin, prec)
+    try:
+        got = {k: spmv.spmv_export(s, w) for k, w in (
+            ("loc_row_ptr", spmv.SPMV_ARR_ROW_PTR), ("loc_col", spmv.SPMV_ARR_COL),
+            ("loc_val", spmv.SPMV_ARR_VAL), ("nl_rows", spmv.SPMV_ARR_NL_ROWS),
+            ("nl_ptr", spmv.SPMV_ARR_NL_PTR), ("nl_col", spmv.SPMV_ARR_NL_COL),
+            ("nl_val", spmv.SPMV_ARR_NL_VAL))}
+        info = spmv.spmv_get_info(s)
+    finally:
+        spmv.spmv_destroy(s)
+        spmv.spmv_destroy(a)
+    ref = oracle.split(A.row_ptr, A.col_idx, A.val, h_begin)
+    for k in ("loc_row_ptr", "loc_col", "nl_rows", "nl_ptr", "nl_col"):
+        assert np.array_equal(got[k], ref[k]), k
+    enc = (lambda v: v) if prec == "f64" else oracle.round_bf16
+    for k in ("loc_val", "nl_val"):
+        assert np.array_equal(got[k], enc(ref[k])), k
+    assert info["nnz_local"] == ref["loc_col"].size
+    assert info["n_nonlocal_rows"] == ref["nl_rows"].size
+    assert info["halo_begin"] == h_begin
+
+
+def _run_split(A, x, h_begin, schedule, prec="f64", halo="pinned", c0=None, flags=NOTUNE):
+    import torch
+
+    a, s = _split_handles(A, h_begin, prec, flags)
+    try:
+        spmv.spmv_set_schedule(s, schedule)
+        xd = np.asarray(x, dtype=np.float64)
+        B_host = xd.copy()
+        B_host[h_begin:] = np.nan  # receive area: must be overwritten by the halo copy
+        B = to_dev(B_host, prec)
+        C = to_dev(np.zeros(A.n_rows) if c0 is None else c0, prec)
+        halo_t = torch.from_numpy(np.ascontiguousarray(xd[h_begin:])).to(B.dtype)
+        if halo == "pinned":
+            halo_t = halo_t.pin_memory()
+        spmv.spmv_run(s, B, C, halo_t)
+        torch.cuda.synchronize()
+        recv = B[h_begin:].cpu().numpy()
+        return C.cpu().numpy().astype(np.float64), recv
+    finally:
+        spmv.spmv_destroy(s)
+        spmv.spmv_destroy(a)
+
+
+@pytest.mark.parametrize("schedule", [spmv.SPMV_SCHEDULE_OVERLAP, spmv.SPMV_SCHEDULE_SERIAL])
+def test_split_run_matches_oracle(schedule):
+    A, x = mats()["irregular"]
+    h_begin = gen.halo_begin(A.n_cols)
+    c0 = gen.uniform_vector(A.n_rows, gen.rng_for(14, 0))
+    got, recv = _run_split(A, x, h_begin, schedule, c0=c0)
+    assert np.array_equal(recv, x[h_begin:])
+    ref, den = oracle_ref(A, x, c0)
+    assert_close(got, ref, den, FP64_TOL, "split vs unsplit oracle")
+    parts = oracle.split(A.row_ptr, A.col_idx, A.val, h_begin)
+    assert_close(got, oracle.spmv_split(parts, x, c0), den, FP64_TOL, "split vs split oracle")
+
+
+def test_split_integer_bit_exact_and_edges():
+    rng = gen.rng_for(15, 0)
+    A = gen.random_crs(20000, 20000, rng, max_len=20, integer_values=True)
+    x = gen.integer_vector(A.n_cols, rng)
+    exact = oracle.spmv(A.row_ptr, A.col_idx, A.val, x)
+    for h_begin in (0, 1, 18800, 19999, 20000):
+        for sch in (spmv.SPMV_SCHEDULE_OVERLAP, spmv.SPMV_SCHEDULE_SERIAL):
+            got, _ = _run_split(A, x, h_begin, sch)
+            assert np.array_equal(got, exact), (h_begin, sch)
+
+
+def test_split_resident_halo_and_pageable_rejection():
+    import torch
+
+    A, x = mats()["irregular"]
+    h_begin = gen.halo_begin(A.n_cols)
+    a, s = _split_handles(A, h_begin)
+    try:
+        B = to_dev(x, "f64")
+        C = to_dev(np.zeros(A.n_rows), "f64")
+        spmv.spmv_run(s, B, C)  # halo already resident
+        torch.cuda.synchronize()
+        ref, den = oracle_ref(A, x)
+        assert_close(C.cpu().numpy(), ref, den, FP64_TOL, "resident halo")
+        pageable = torch.from_numpy(np.ascontiguousarray(x[h_begin:]))
+        with pytest.raises(spmv.SpmvError) as ei:
+            spmv.spmv_run(s, B, C, pageable)
+        assert ei.value.status == spmv.SPMV_ERR_INVALID_ARG and "pinned" in ei.value.message
+        with pytest.raises((ValueError, spmv.SpmvError)):
+            spmv.spmv_run(a, B, C, pageable.pin_memory())  # plain handle takes no halo
+        hp = pageable.pin_memory()
+        st = spmv.load().spmv_run(spmv.ctypes.c_void_p(a.ptr), spmv.ctypes.c_void_p(B.data_ptr()),
+                                  spmv.ctypes.c_void_p(C.data_ptr()),
+                                  spmv.ctypes.c_void_p(hp.data_ptr()), None)
+        assert st == spmv.SPMV_ERR_INVALID_ARG
+    finally:
+        spmv.spmv_destroy(s)
+        spmv.spmv_destroy(a)
+    got, _ = _run_split(A, x, h_begin, spmv.SPMV_SCHEDULE_OVERLAP, halo="pageable",
+                        flags=NOTUNE | spmv.SPMV_FLAG_ALLOW_PAGEABLE_HALO)
+    assert_close(got, ref, den, FP64_TOL, "pageable halo with flag")
+
+
+def test_split_of_split_unsupported():
+    A, _ = mats()["irregular"]
+    a, s = _split_handles(A, 10)
+    try:
+        with pytest.raises(spmv.SpmvError) as ei:
+            spmv.spmv_split_local_nonlocal(s, 5)
+        assert ei.value.status == spmv.SPMV_ERR_UNSUPPORTED
+        with pytest.raises(spmv.SpmvError) as ei:
+            spmv.spmv_split_local_nonlocal(a, A.n_cols + 1)
+        assert ei.value.status == spmv.SPMV_ERR_INVALID_ARG
+    finally:
+        spmv.spmv_destroy(s)
+        spmv.spmv_destroy(a)
+
+
+# ---------------------------------------------------------------------------- a7
+
+@pytest.mark.parametrize("prec", ["f32", "bf16", "f32f64"])
+@pytest.mark.parametrize("name", ["27pt", "irregular"])
+def test_precision_modes(prec, name):
+    A, x = mats()[name]
+    n = int(np.diff(A.row_ptr).max())
+    b_orig, b_same = prec_bounds(prec, n)
+    got = gpu_spmv(A, x, prec=prec)
+    ref, den = oracle_ref(A, x)
+    assert_close(got, ref, den, b_orig, f"{prec} vs FP64 oracle")
+    v, xr = rounded_inputs(A, x, prec)
+    ref2 = oracle.spmv(A.row_ptr, A.col_idx, v, xr)
+    den2 = oracle.abs_spmv(A.row_ptr, A.col_idx, v, xr)
+    assert_close(got, ref2, den2, b_same, f"{prec} vs oracle on rounded inputs")
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16", "f32f64"])
+def test_precision_modes_integer_exact(prec):
+    rng = gen.rng_for(16, 0)
+    A = gen.random_crs(6000, 6000, rng, max_len=30, integer_values=True, vmax=8)
+    x = gen.integer_vector(A.n_cols, rng, vmax=8)
+    assert np.array_equal(gpu_spmv(A, x, prec=prec), oracle.spmv(A.row_ptr, A.col_idx, A.val, x))
+
+
+# ---------------------------------------------------------------------------- a8
+
+def _gpu_block(A, X, prec="f64", kt=0, ldb_pad=0, ldc_pad=0, c0=None):
+    import torch
+
+    h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, prec=prec, flags=NOTUNE)
+    try:
+        if kt:
+            spmv.spmv_set_plan(h, block_kt=kt)
+        k = X.shape[1]
+        dt = torch.float64 if spmv.VEC_DTYPE[prec] == "float64" else torch.float32
+        Bw = torch.zeros((A.n_cols, k + ldb_pad), dtype=dt, device="cuda")
+        Bw[:, :k] = torch.from_numpy(X).to(dt)
+        Cw = torch.zeros((A.n_rows, k + ldc_pad), dtype=dt, device="cuda")
+        if c0 is not None:
+            Cw[:, :k] = torch.from_numpy(c0).to(dt)
+        spmv.spmv_run_block(h, Bw[:, :k], Cw[:, :k])
+        torch.cuda.synchronize()
+        return Cw[:, :k].cpu().numpy().astype(np.float64), Cw[:, k:].cpu().numpy()
+    finally:
+        spmv.spmv_destroy(h)
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 8, 16, 17, 33, 64])
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+def test_block(k, prec):
+    A, _ = mats()["irregular"]
+    X = gen.block_rhs(A.n_cols, k)
+    c0 = gen.block_rhs(A.n_rows, k, extra=1)
+    got, pad = _gpu_block(A, X, prec, c0=c0, ldb_pad=1 if k % 2 else 2, ldc_pad=3)
+    assert np.all(pad == 0)
+    n = int(np.diff(A.row_ptr).max())
+    b_orig, _ = prec_bounds(prec, n)
+    ref = oracle.spmv_block(A.row_ptr, A.col_idx, A.val, X, c0)
+    for t in range(k):
+        den = oracle.abs_spmv(A.row_ptr, A.col_idx, A.val, X[:, t], c0[:, t])
+        assert_close(got[:, t], ref[:, t], den, b_orig, f"block k={k} column {t}")
+
+
+@pytest.mark.parametrize("kt", [4, 8, 16])
+@pytest.mark.parametrize("k", [3, 8, 16])
+def test_block_tiles_integer_exact(kt, k):
+    rng = gen.rng_for(17, 0)
+    A = _long_row_matrix(3000, n_short=2000, n_cols=5000)
+    A.val = np.round(A.val * 4)
+    X = rng.integers(-5, 6, size=(A.n_cols, k)).astype(np.float64)
+    got, _ = _gpu_block(A, X, "f64", kt=kt)
+    assert np.array_equal(got, oracle.spmv_block(A.row_ptr, A.col_idx, A.val, X))
+
+
+def test_block_rejects_split_and_bad_k():
+    import torch
+
+    A, _ = mats()["irregular"]
+    a, s = _split_handles(A, 100)
+    try:
+        B = torch.zeros((A.n_cols, 4), dtype=torch.float64, device="cuda")
+        C = torch.zeros((A.n_rows, 4), dtype=torch.float64, device="cuda")
+        with pytest.raises(spmv.SpmvError) as ei:
+            spmv.spmv_run_block(s, B, C)
+        assert ei.value.status == spmv.SPMV_ERR_UNSUPPORTED
+        B = torch.zeros((A.n_cols, 65), dtype=torch.float64, device="cuda")
+        C = torch.zeros((A.n_rows, 65), dtype=torch.float64, device="cuda")
+        with pytest.raises(spmv.SpmvError) as ei:
+            spmv.spmv_run_block(a, B, C)
+        assert ei.value.status == spmv.SPMV_ERR_INVALID_ARG
+    finally:
+        spmv.spmv_destroy(s)
+        spmv.spmv_destroy(a)
+
+
+# ---------------------------------------------------------------------------- a9
+
+def _batch(count=40, nmax=30000, seed_extra=1):
+    return gen.workload_c5_batch(count=count, nmin=1000, nmax=nmax, seed_extra=seed_extra)
+
+
+@pytest.mark.parametrize("schedule", [spmv.SPMV_SCHEDULE_BATCH_GRAPH, spmv.SPMV_SCHEDULE_BATCH_DIRECT,
+                                      spmv.SPMV_SCHEDULE_BATCH_FLAT])
+@pytest.mark.parametrize("tile_items", [4, 8, 16])
+def test_batch_matches_members(schedule, tile_items):
+    import torch
+
+    mem = _batch()
+    h = spmv.spmv_create_batch([(A.row_ptr, A.col_idx, A.val, A.n_cols) for A, _ in mem], flags=NOTUNE)
+    try:
+        spmv.spmv_set_schedule(h, schedule)
+        spmv.spmv_set_plan(h, tile_items=tile_items)
+        xs = np.concatenate([x for _, x in mem])
+        c0 = gen.uniform_vector(sum(A.n_rows for A, _ in mem), gen.rng_for(18, 0))
+        B = to_dev(xs, "f64")
+        C = to_dev(c0, "f64")
+        spmv.spmv_run(h, B, C)
+        torch.cuda.synchronize()
+        got = C.cpu().numpy()
+    finally:
+        spmv.spmv_destroy(h)
+    off = 0
+    for A, x in mem:
+        sl = slice(off, off + A.n_rows)
+        ref, den = oracle_ref(A, x, c0[sl])
+        assert_close(got[sl], ref, den, FP64_TOL, f"member at {off}")
+        off += A.n_rows
+
+
+def test_batch_graph_replays_and_recapture():
+    import torch
+
+    mem = _batch(count=24, seed_extra=2)
+    xs = np.concatenate([np.round(8 * x) for _, x in mem])  # integer RHS: exact results
+    exact = []
+    off = 0
+    for A, _ in mem:
+        exact.append(oracle.spmv(A.row_ptr, A.col_idx, A.val, xs[off:off + A.n_cols]))
+        off += A.n_cols
+    exact = np.concatenate(exact)
+    h = spmv.spmv_create_batch([(A.row_ptr, A.col_idx, A.val, A.n_cols) for A, _ in mem], flags=NOTUNE)
+    try:
+        B = to_dev(xs, "f64")
+        C = torch.zeros(exact.size, dtype=torch.float64, device="cuda")
+        for r in range(1, 5):
+            spmv.spmv_run(h, B, C)  # graph replay (captured on the first call)
+            torch.cuda.synchronize()
+            junk = torch.randn(1 << 20, device="cuda").sum()  # eager work between replays
+            torch.cuda.synchronize()
+            assert np.array_equal(C.cpu().numpy(), r * exact), f"replay {r}"
+            del junk
+        # new buffers: the graph is captured again for them
+        B2 = B.clone()
+        C2 = torch.zeros_like(C)
+        spmv.spmv_run(h, B2, C2)
+        spmv.spmv_run(h, B2, C2)
+        torch.cuda.synchronize()
+        assert np.array_equal(C2.cpu().numpy(), 2 * exact)
+        assert np.array_equal(C.cpu().numpy(), 4 * exact)
+    finally:
+        spmv.spmv_destroy(h)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_batch_precision(prec):
+    import torch
+
+    mem = _batch(count=12, seed_extra=3)
+    h = spmv.spmv_create_batch([(A.row_ptr, A.col_idx, A.val, A.n_cols) for A, _ in mem], prec=prec,
+                               flags=NOTUNE)
+    try:
+        xs = np.concatenate([x for _, x in mem])
+        B = to_dev(xs, prec)
+        C = to_dev(np.zeros(sum(A.n_rows for A, _ in mem)), prec)
+        spmv.spmv_run(h, B, C)
+        torch.cuda.synchronize()
+        got = C.cpu().numpy().astype(np.float64)
+    finally:
+        spmv.spmv_destroy(h)
+    off = 0
+    for A, x in mem:
+        sl = slice(off, off + A.n_rows)
+        ref, den = oracle_ref(A, x)
+        assert_close(got[sl], ref, den, prec_bounds(prec, 7)[0], f"{prec} member at {off}")
+        off += A.n_rows
+
+
+# ---------------------------------------------------------------------------- a10
+
+def test_tuner_and_cache(tmp_path, monkeypatch):
+    monkeypatch.setenv("SPMV_TUNE_CACHE", str(tmp_path / "tune.json"))
+    A, x = mats()["irregular"]
+    h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols)
+    try:
+        spmv.spmv_tune(h, 1)
+        plan = spmv.spmv_get_plan(h)
+        spmv.spmv_tune(h, 8)
+    finally:
+        spmv.spmv_destroy(h)
+    text = (tmp_path / "tune.json").read_text()
+    assert "|k1|main|" in text and "|k8|block|" in text
+    # a new handle with the same statistics starts from the cached plan
+    h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols)
+    try:
+        assert spmv.spmv_get_plan(h) == plan
+    finally:
+        spmv.spmv_destroy(h)
+    ref, den = oracle_ref(A, x)
+    assert_close(gpu_spmv(A, x, flags=0), ref, den, FP64_TOL, "tuned plan")
+    # split and batch handles tune too
+    a, s = _split_handles(A, gen.halo_begin(A.n_cols), flags=0)
+    try:
+        spmv.spmv_tune(s, 1)
+        assert spmv.spmv_get_plan(s, spmv.SPMV_PART_NONLOCAL)["kernel"] in (1, 2)
+    finally:
+        spmv.spmv_destroy(s)
+        spmv.spmv_destroy(a)
+    mem = _batch(count=8, seed_extra=4)
+    hb = spmv.spmv_create_batch([(M.row_ptr, M.col_idx, M.val, M.n_cols) for M, _ in mem])
+    try:
+        spmv.spmv_tune(hb, 1)
+    finally:
+        spmv.spmv_destroy(hb)
+
+
+def test_set_plan_validation():
+    A, _ = mats()["irregular"]
+    h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, flags=NOTUNE)
+    try:
+        for bad in (dict(kernel=3), dict(tile_items=5), dict(lanes=3), dict(block_kt=2)):
+            with pytest.raises(spmv.SpmvError):
+                spmv.spmv_set_plan(h, **bad)
+        with pytest.raises(spmv.SpmvError):
+            spmv.spmv_get_plan(h, spmv.SPMV_PART_NONLOCAL)
+    finally:
+        spmv.spmv_destroy(h)
+    # a destroyed handle is refused without being dereferenced
+    assert spmv.load().spmv_run(spmv.ctypes.c_void_p(1), None, None, None, None) == spmv.SPMV_ERR_STATE
+
+
+# ---------------------------------------------------------------------------- probes
+
+def test_probes():
+    import time
+
+    import torch
+
+    n = (1 << 20) + 1
+    src = torch.randn(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    spmv.spmv_probe_copy(dst, src)
+    a = torch.empty_like(src)
+    c = torch.randn(n, dtype=torch.float64, device="cuda")
+    spmv.spmv_probe_triad(a, src, c, 3.0)
+    torch.cuda.synchronize()
+    assert torch.equal(dst, src)
+    assert torch.allclose(a, src + 3.0 * c, rtol=0, atol=1e-12)
+    t0 = time.perf_counter()
+    spmv.spmv_probe_spin(20_000_000)  # 20 ms
+    torch.cuda.synchronize()
+    assert time.perf_counter() - t0 >= 0.015
