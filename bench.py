@@ -1,0 +1,660 @@
+#!/usr/bin/env python3
+"""Benchmark of the CRS spMV path on one MI355X.
+
+Headline (the JSON line's `value`): C = C + A*B in FP64 on the 3D 27-point
+stencil on a 160^3 grid (N = 4,096,000 rows, 109,215,352 stored entries,
+entries 26 / -1 perturbed by U[-0.01, 0.01], B ~ U[-1, 1]), inputs resident
+in HBM.  One step is one spmv_run over the whole matrix.  The same run also
+measures the other paths of the library (reduced precision, the irregular
+matrix and its local / nonlocal split with the halo copy overlapped, block
+right-hand sides, the 512-matrix batch) and reports them under "paths".
+
+Performance model (Sect. 1.2 and Sect. 3.4 of Schubert, Fehske, Hager,
+Wellein 2011): code balance Eq. (1) B = 6 + 12/N_nzr + kappa/2 bytes/flop,
+split balance Eq. (2) 6 + 20/N_nzr + kappa/2; kappa from measured bandwidth
+and performance as in Sect. 2.  On the GPU the algorithmic byte count also
+includes row_ptr (4 bytes per row) and C is read and written once (no
+write-allocate): nnz*(s_val + 4) + 4*(N+1) + n_cols*k*s_x + 2*N*k*s_c.
+
+Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only headline]
+       python bench.py --pmc-pass        (headline kernel + copy calibration,
+                                          for rocprofv3 --pmc runs)
+       python bench.py --summarize-pmc FETCH_DIR WRITE_DIR OUT
+"""
+from __future__ import annotations
+
+import argparse
+import glob
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
+PROFILES = os.path.join(ROOT, "profiles")
+TRAFFIC_FILE = os.path.join(PROFILES, "traffic_csr_stream_27pt160_f64.json")
+KERNEL_SRC = os.path.join(ROOT, "paper_1106_5908_amd", "csrc", "kernels.hip")
+
+VAL_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f32f64": 4}
+VEC_BYTES = {"f64": 8, "f32": 4, "bf16": 4, "f32f64": 8}
+
+
+# ----------------------------------------------------------------------------
+# Performance model
+# ----------------------------------------------------------------------------
+
+def code_balance(nnzr: float, kappa: float = 0.0) -> float:
+    """Eq. (1): bytes per flop of the CRS kernel, FP64 val, 4-byte indices."""
+    return 6.0 + 12.0 / nnzr + kappa / 2.0
+
+
+def code_balance_split(nnzr: float, kappa: float = 0.0) -> float:
+    """Eq. (2): the split kernel writes the result vector twice."""
+    return 6.0 + 20.0 / nnzr + kappa / 2.0
+
+
+def perf_limit(bw_gbs: float, nnzr: float, kappa: float = 0.0) -> float:
+    """Upper performance limit in GFlop/s: bandwidth over code balance."""
+    return bw_gbs / code_balance(nnzr, kappa)
+
+
+def kappa_from(bw_gbs: float, perf_gflops: float, nnzr: float) -> float:
+    """kappa from the measured bandwidth and performance (Sect. 2)."""
+    return 2.0 * (bw_gbs / perf_gflops - 6.0 - 12.0 / nnzr)
+
+
+def rhs_loads(kappa: float, nnzr: float) -> float:
+    """How many times B is loaded: once plus kappa*N_nzr/8 extra loads."""
+    return 1.0 + kappa * nnzr / 8.0
+
+
+def algorithmic_bytes(n_rows: int, n_cols: int, nnz: int, prec: str = "f64", k: int = 1) -> int:
+    """Bytes one call must move at kappa = 0 (val, col_idx, row_ptr, B once,
+    C read and written once)."""
+    sv, sx = VAL_BYTES[prec], VEC_BYTES[prec]
+    return nnz * (sv + 4) + 4 * (n_rows + 1) + n_cols * k * sx + 2 * n_rows * k * sx
+
+
+def split_extra_bytes(n_nl_rows: int, prec: str = "f64") -> int:
+    """Extra bytes of the split: the nonlocal rows' C read and written again,
+    their row id and their row_ptr entry."""
+    sc = VEC_BYTES[prec]
+    return n_nl_rows * (2 * sc + 8) + 4
+
+
+def kappa_gpu(bytes_measured: float, flops: float, model_bytes: float) -> float:
+    """GPU analogue of kappa: twice the measured bytes per flop above the
+    kappa = 0 model."""
+    return 2.0 * (bytes_measured / flops - model_bytes / flops)
+
+
+# ----------------------------------------------------------------------------
+# Timing helpers
+# ----------------------------------------------------------------------------
+
+def time_launches(fn, steps: int, warmup: int):
+    """Run fn() warmup times, then `steps` times with an event pair around
+    each call and around the whole run (all on torch's current stream, the
+    stream the library launches on).  Returns dict of ms figures."""
+    import torch
+
+    s = torch.cuda.current_stream()
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    t0 = torch.cuda.Event(enable_timing=True)
+    t1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    t0.record(s)
+    ev[0].record(s)
+    for i in range(steps):
+        fn()
+        ev[i + 1].record(s)
+    t1.record(s)
+    torch.cuda.synchronize()
+    per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
+    total = t0.elapsed_time(t1)
+    return {
+        "ms_per_step": total / steps,
+        "mean_ms": float(per.mean()),
+        "p10_ms": float(np.percentile(per, 10)),
+        "p50_ms": float(np.percentile(per, 50)),
+        "p90_ms": float(np.percentile(per, 90)),
+    }
+
+
+def kernel_hash() -> str:
+    with open(KERNEL_SRC, "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def read_traffic(plan: dict):
+    """HBM bytes per launch from the committed counter summary, if it was
+    taken with the current kernel source and plan; else None."""
+    try:
+        with open(TRAFFIC_FILE) as f:
+            t = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if t.get("kernel_sha") != kernel_hash() or t.get("plan") != plan:
+        return None
+    return t.get("traffic_bytes")
+
+
+# ----------------------------------------------------------------------------
+# Workloads
+# ----------------------------------------------------------------------------
+
+def log(msg: str):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def make_handle(A, prec="f64", tune=True):
+    from paper_1106_5908_amd import spmv
+
+    h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, prec=prec,
+                             flags=spmv.SPMV_FLAG_NO_TUNE_CACHE)
+    if tune:
+        spmv.spmv_tune(h, 1)
+    return h
+
+
+def dev_vec(a, prec):
+    import torch
+
+    dt = torch.float64 if VEC_BYTES[prec] == 8 else torch.float32
+    return torch.from_numpy(np.ascontiguousarray(a)).to("cuda", dtype=dt)
+
+
+def normalized_err(A, x, got, ref=None, den=None):
+    import oracle
+
+    if ref is None:
+        ref = oracle.spmv(A.row_ptr, A.col_idx, A.val, x)
+        den = oracle.abs_spmv(A.row_ptr, A.col_idx, A.val, x)
+    e = oracle.normalized_error(got, ref, den)
+    with np.errstate(divide="ignore", invalid="ignore"):
+        rel = np.abs(got - ref) / np.abs(ref)
+    rel = rel[np.isfinite(rel)]
+    return {
+        "max_normalized_err": float(e.max()),
+        "max_rel_err": float(rel.max()) if rel.size else 0.0,
+        "n_rel_err_above_1e-12": int((rel > 1e-12).sum()),
+    }, ref, den
+
+
+def bound(prec: str, n: int) -> float:
+    u64, u32, u16 = 2.0 ** -53, 2.0 ** -24, 2.0 ** -8
+    return {"f64": 1e-12, "f32": (n + 3) * u32, "bf16": u16 + (n + 3) * u32,
+            "f32f64": u32 + (n + 2) * u64}[prec]
+
+
+def run_spmv_path(A, x, prec, steps, warmup, label, ref=None, den=None, tune=True):
+    """Time spmv_run on one matrix in one precision; check the first result."""
+    import torch
+
+    from paper_1106_5908_amd import spmv
+
+    h = make_handle(A, prec, tune)
+    B = dev_vec(x, prec)
+    C = torch.zeros(A.n_rows, dtype=B.dtype, device="cuda")
+    spmv.spmv_run(h, B, C)
+    torch.cuda.synchronize()
+    got = C.cpu().numpy().astype(np.float64)
+    err, ref, den = normalized_err(A, x, got, ref, den)
+    t = time_launches(lambda: spmv.spmv_run(h, B, C), steps, warmup)
+    plan = spmv.spmv_get_plan(h)
+    spmv.spmv_destroy(h)
+    del B, C
+    torch.cuda.empty_cache()
+    mb = algorithmic_bytes(A.n_rows, A.n_cols, A.nnz, prec)
+    flops = 2.0 * A.nnz
+    n = int(np.diff(A.row_ptr).max())
+    out = {
+        "path": label, "prec": prec, "gflops": flops / (t["ms_per_step"] * 1e6),
+        "model_GBs": mb / (t["ms_per_step"] * 1e6), "model_bytes": mb, **t, **err,
+        "err_bound": bound(prec, n), "within_bound": err["max_normalized_err"] <= bound(prec, n),
+        "plan": plan,
+    }
+    log(f"{label} {prec}: {out['gflops']:.0f} GFlop/s, {out['model_GBs']:.0f} GB/s model, "
+        f"err {err['max_normalized_err']:.2e}")
+    return out, ref, den
+
+
+def measure_bandwidth(steps=20):
+    """Copy and triad probes over 3 x 2^27 doubles (the STREAM role)."""
+    import torch
+
+    from paper_1106_5908_amd import spmv
+
+    n = 1 << 27
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.rand(n, dtype=torch.float64, device="cuda")
+    c = torch.rand(n, dtype=torch.float64, device="cuda")
+    tc = time_launches(lambda: spmv.spmv_probe_copy(a, b), steps, 3)
+    tt = time_launches(lambda: spmv.spmv_probe_triad(a, b, c, 3.0), steps, 3)
+    out = {"copy_GBs": 2 * 8 * n / (tc["p50_ms"] * 1e6), "triad_GBs": 3 * 8 * n / (tt["p50_ms"] * 1e6),
+           "copy_bytes": 2 * 8 * n, "copy_ms": tc["p50_ms"]}
+    del a, b, c
+    torch.cuda.empty_cache()
+    log(f"bandwidth probes: copy {out['copy_GBs']:.0f} GB/s, triad {out['triad_GBs']:.0f} GB/s")
+    return out
+
+
+def split_paths(A, x, steps, warmup):
+    """The three schedules of Fig. 5 on one GPU: (a) blocking halo copy then
+    the unsplit kernel, (b) split kernels with the copy serialised on the
+    compute stream, (c) split kernels with the copy overlapped."""
+    import torch
+
+    import oracle
+    from paper_1106_5908_amd import spmv
+    from workloads import gen
+
+    hb = gen.halo_begin(A.n_cols)
+    n_halo = A.n_cols - hb
+    halo = torch.from_numpy(np.ascontiguousarray(x[hb:])).pin_memory()
+    B = dev_vec(x, "f64")
+    C = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+    a = make_handle(A, "f64")
+    s = spmv.spmv_split_local_nonlocal(a, hb)
+    spmv.spmv_tune(s, 1)
+    info = spmv.spmv_get_info(s)
+    res = {"halo_begin": hb, "n_halo": n_halo, "halo_bytes": 8 * n_halo,
+           "nnz_local": info["nnz_local"], "nnz_nonlocal": info["nnz_nonlocal"],
+           "n_nonlocal_rows": info["n_nonlocal_rows"]}
+    # parity of the overlapped split (first call), against the unsplit oracle
+    Bc = B.clone()
+    Bc[hb:] = float("nan")
+    spmv.spmv_run(s, Bc, C, halo)
+    torch.cuda.synchronize()
+    ref = oracle.spmv(A.row_ptr, A.col_idx, A.val, x)
+    den = oracle.abs_spmv(A.row_ptr, A.col_idx, A.val, x)
+    res["split_max_normalized_err"] = float(oracle.normalized_error(C.cpu().numpy(), ref, den).max())
+
+    def mode_a():
+        B[hb:].copy_(halo, non_blocking=False)
+        spmv.spmv_run(a, B, C)
+
+    def mode_b():
+        spmv.spmv_run(s, B, C, halo)
+
+    spmv.spmv_set_schedule(s, spmv.SPMV_SCHEDULE_SERIAL)
+    tb = time_launches(mode_b, steps, warmup)
+    spmv.spmv_set_schedule(s, spmv.SPMV_SCHEDULE_OVERLAP)
+    tc = time_launches(mode_b, steps, warmup)
+    ta = time_launches(mode_a, steps, warmup)
+    tk = time_launches(lambda: spmv.spmv_run(s, B, C), steps, warmup)  # halo resident
+    tu = time_launches(lambda: spmv.spmv_run(a, B, C), steps, warmup)  # unsplit kernel only
+    flops = 2.0 * A.nnz
+    mb = algorithmic_bytes(A.n_rows, A.n_cols, A.nnz, "f64")
+    res.update({
+        "a_blocking_copy_then_unsplit_ms": ta["p50_ms"],
+        "b_split_serial_copy_ms": tb["p50_ms"],
+        "c_split_overlap_copy_ms": tc["p50_ms"],
+        "split_kernels_only_ms": tk["p50_ms"],
+        "unsplit_kernel_only_ms": tu["p50_ms"],
+        "c_gflops": flops / (tc["p50_ms"] * 1e6),
+        "split_model_bytes": mb + split_extra_bytes(info["n_nonlocal_rows"]),
+        "split_kernel_penalty": tk["p50_ms"] / tu["p50_ms"] - 1.0,
+        "overlap_speedup_vs_a": ta["p50_ms"] / tc["p50_ms"],
+        "overlap_speedup_vs_b": tb["p50_ms"] / tc["p50_ms"],
+        "plans": {"local": spmv.spmv_get_plan(s, spmv.SPMV_PART_MAIN),
+                  "nonlocal": spmv.spmv_get_plan(s, spmv.SPMV_PART_NONLOCAL)},
+    })
+    log(f"split: (a) {ta['p50_ms']*1e3:.0f} us, (b) {tb['p50_ms']*1e3:.0f} us, "
+        f"(c) {tc['p50_ms']*1e3:.0f} us, kernels only {tk['p50_ms']*1e3:.0f} us, "
+        f"unsplit {tu['p50_ms']*1e3:.0f} us")
+    spmv.spmv_destroy(s)
+    spmv.spmv_destroy(a)
+    del B, C, Bc
+    torch.cuda.empty_cache()
+    return res, ref, den
+
+
+def block_paths(A, steps, warmup, fp64_ms):
+    import torch
+
+    import oracle
+    from paper_1106_5908_amd import spmv
+    from workloads import gen
+
+    out = []
+    rows = np.random.default_rng(5).integers(0, A.n_rows, size=2000)
+    for prec in ("f64", "f32"):
+        h = make_handle(A, prec, tune=False)
+        for k in gen.BLOCK_KS:
+            spmv.spmv_tune(h, k)
+            X = gen.block_rhs(A.n_cols, k)
+            dt = torch.float64 if prec == "f64" else torch.float32
+            B = torch.from_numpy(X).to("cuda", dtype=dt)
+            C = torch.zeros((A.n_rows, k), dtype=dt, device="cuda")
+            spmv.spmv_run_block(h, B, C)
+            torch.cuda.synchronize()
+            got = C[torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.float64)
+            errs = []
+            Xr = X if prec == "f64" else oracle.round_f32(X).astype(np.float64)
+            for t in range(k):
+                xt = np.ascontiguousarray(X[:, t])
+                ref = oracle.spmv_rows(rows, A.row_ptr, A.col_idx, A.val, xt)
+                den = oracle.spmv_rows(rows, A.row_ptr, A.col_idx, np.abs(A.val), np.abs(xt))
+                errs.append(float(oracle.normalized_error(got[:, t], ref, den).max()))
+            del Xr
+            tm = time_launches(lambda: spmv.spmv_run_block(h, B, C), steps, warmup)
+            flops = 2.0 * A.nnz * k
+            mb = algorithmic_bytes(A.n_rows, A.n_cols, A.nnz, prec, k)
+            n = int(np.diff(A.row_ptr).max())
+            r = {"path": f"block k={k}", "prec": prec, "k": k,
+                 "gflops": flops / (tm["ms_per_step"] * 1e6),
+                 "model_GBs": mb / (tm["ms_per_step"] * 1e6), "model_bytes": mb, **tm,
+                 "max_normalized_err_sampled": max(errs), "err_bound": bound(prec, n),
+                 "speedup_vs_k_fp64_calls": k * fp64_ms / tm["ms_per_step"]}
+            log(f"block k={k} {prec}: {r['gflops']:.0f} GFlop/s, x{r['speedup_vs_k_fp64_calls']:.2f} "
+                f"vs k FP64 calls, err {max(errs):.1e}")
+            out.append(r)
+            del B, C
+            torch.cuda.empty_cache()
+        spmv.spmv_destroy(h)
+    return out
+
+
+def batch_paths(steps, warmup):
+    import torch
+
+    import oracle
+    from paper_1106_5908_amd import spmv
+    from workloads import gen
+
+    t0 = time.time()
+    mem = gen.workload_c5_batch()
+    log(f"batch generated in {time.time() - t0:.1f}s")
+    n_rows = sum(A.n_rows for A, _ in mem)
+    n_cols = sum(A.n_cols for A, _ in mem)
+    nnz = sum(A.nnz for A, _ in mem)
+    xs = np.concatenate([x for _, x in mem])
+    h = spmv.spmv_create_batch([(A.row_ptr, A.col_idx, A.val, A.n_cols) for A, _ in mem],
+                               flags=spmv.SPMV_FLAG_NO_TUNE_CACHE)
+    spmv.spmv_tune(h, 1)
+    B = dev_vec(xs, "f64")
+    C = torch.zeros(n_rows, dtype=torch.float64, device="cuda")
+    spmv.spmv_run(h, B, C)
+    torch.cuda.synchronize()
+    got = C.cpu().numpy()
+    worst = 0.0
+    off_r = off_c = 0
+    for A, x in mem[:64]:
+        ref = oracle.spmv(A.row_ptr, A.col_idx, A.val, x)
+        den = oracle.abs_spmv(A.row_ptr, A.col_idx, A.val, x)
+        worst = max(worst, float(oracle.normalized_error(got[off_r:off_r + A.n_rows], ref, den).max()))
+        off_r += A.n_rows
+        off_c += A.n_cols
+    res = {"members": len(mem), "n_rows": n_rows, "nnz": nnz,
+           "max_normalized_err_first64": worst, "plan": spmv.spmv_get_plan(h)}
+    flops = 2.0 * nnz
+    mb = algorithmic_bytes(n_rows, n_cols, nnz, "f64") + 4 * len(mem)
+    for name, sch in (("graph", spmv.SPMV_SCHEDULE_BATCH_GRAPH), ("direct", spmv.SPMV_SCHEDULE_BATCH_DIRECT),
+                      ("flat", spmv.SPMV_SCHEDULE_BATCH_FLAT)):
+        spmv.spmv_set_schedule(h, sch)
+        tm = time_launches(lambda: spmv.spmv_run(h, B, C), steps, warmup)
+        res[f"{name}_ms"] = tm["p50_ms"]
+        res[f"{name}_gflops"] = flops / (tm["ms_per_step"] * 1e6)
+        res[f"{name}_model_GBs"] = mb / (tm["ms_per_step"] * 1e6)
+    spmv.spmv_destroy(h)
+    # baseline: one plain launch per member
+    hs = [make_handle(A, "f64", tune=False) for A, _ in mem]
+    views = []
+    off_r = off_c = 0
+    for A, _ in mem:
+        views.append((B[off_c:off_c + A.n_cols], C[off_r:off_r + A.n_rows]))
+        off_r += A.n_rows
+        off_c += A.n_cols
+
+    def per_member():
+        for hh, (b, c) in zip(hs, views):
+            spmv.spmv_run(hh, b, c)
+
+    tm = time_launches(per_member, max(3, steps // 5), 2)
+    res["per_member_launches_ms"] = tm["p50_ms"]
+    res["per_member_gflops"] = flops / (tm["ms_per_step"] * 1e6)
+    res["graph_speedup_vs_per_member"] = tm["p50_ms"] / res["graph_ms"]
+    res["model_bytes"] = mb
+    for hh in hs:
+        spmv.spmv_destroy(hh)
+    log(f"batch: graph {res['graph_ms']*1e3:.0f} us ({res['graph_gflops']:.0f} GFlop/s), direct "
+        f"{res['direct_ms']*1e3:.0f} us, flat {res['flat_ms']*1e3:.0f} us, per-member launches "
+        f"{res['per_member_launches_ms']*1e3:.0f} us")
+    del B, C, views
+    torch.cuda.empty_cache()
+    return res
+
+
+def cpu_baseline(A, x, budget_s: float = 10.0):
+    """The oracle (sequential, one core) on repeated full passes of the
+    headline matrix until about budget_s seconds of CPU work."""
+    import oracle
+
+    oracle.spmv(A.row_ptr[:2], A.col_idx[:A.row_ptr[1]], A.val[:A.row_ptr[1]], x)  # load
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        oracle.spmv(A.row_ptr, A.col_idx, A.val, x)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= budget_s or reps >= 200:
+            break
+    gflops = 2.0 * A.nnz * reps / el / 1e9
+    log(f"cpu oracle: {reps} passes in {el:.1f}s -> {gflops:.3f} GFlop/s")
+    return {"value": gflops, "unit": "GFlop/s", "cores": 1, "kind": "oracle",
+            "sample": f"{reps} full sequential passes of the 27-point 160^3 FP64 product "
+                      f"({el:.1f} s, one thread)"}
+
+
+# ----------------------------------------------------------------------------
+# rocprofv3 counter passes
+# ----------------------------------------------------------------------------
+
+def pmc_pass(steps: int, plan_json: str | None):
+    """Headline kernel `steps` times with the given plan (no tuning, so the
+    profile holds only these dispatches), then a copy of 2^27 doubles (the
+    calibration kernel of known size), each bracketed by synchronisation."""
+    import torch
+
+    from paper_1106_5908_amd import spmv
+    from workloads import gen
+
+    A, x = gen.workload_c2()
+    h = make_handle(A, "f64", tune=False)
+    if plan_json:
+        spmv.spmv_set_plan(h, **json.loads(plan_json))
+    B = dev_vec(x, "f64")
+    C = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+    for _ in range(steps):
+        spmv.spmv_run(h, B, C)
+    torch.cuda.synchronize()
+    n = 1 << 27
+    a = torch.empty(n, dtype=torch.float64, device="cuda")
+    b = torch.rand(n, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        spmv.spmv_probe_copy(a, b)
+    torch.cuda.synchronize()
+    plan = spmv.spmv_get_plan(h)
+    print(json.dumps({"pmc_pass": "done", "plan": plan, "copy_bytes_read": 8 * n,
+                      "copy_bytes_written": 8 * n}), flush=True)
+
+
+def _counter_rows(d):
+    import csv
+
+    rows = []
+    for f in glob.glob(os.path.join(d, "**", "*counter_collection.csv"), recursive=True):
+        with open(f) as fh:
+            rows += list(csv.DictReader(fh))
+    return rows
+
+
+def summarize_pmc(fetch_dir, write_dir, out_path, plan_json):
+    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the spMV kernel, scaled
+    by the same counters' reading for the copy kernel of known size."""
+    def per_kernel(rows, counter):
+        acc = {}
+        for r in rows:
+            if r.get("Counter_Name") != counter:
+                continue
+            name = r["Kernel_Name"]
+            key = "spmv" if "k_stream" in name or "k_vector" in name else (
+                "copy" if "k_copy" in name else None)
+            if key is None:
+                continue
+            acc.setdefault((key, r["Dispatch_Id"]), 0.0)
+            acc[(key, r["Dispatch_Id"])] += float(r["Counter_Value"])
+        out = {}
+        for (key, _), v in acc.items():
+            out.setdefault(key, []).append(v)
+        return {k: float(np.median(v)) for k, v in out.items()}
+
+    fetch = per_kernel(_counter_rows(fetch_dir), "FETCH_SIZE")
+    write = per_kernel(_counter_rows(write_dir), "WRITE_SIZE")
+    copy_bytes = 8 * (1 << 27)
+    f_fac = copy_bytes / (fetch["copy"] * 1024.0)
+    w_fac = copy_bytes / (write["copy"] * 1024.0)
+    fetch_b = fetch["spmv"] * 1024.0 * f_fac
+    write_b = write["spmv"] * 1024.0 * w_fac
+    res = {
+        "kernel_sha": kernel_hash(), "plan": json.loads(plan_json),
+        "workload": "27-point 160^3 FP64",
+        "fetch_kib_per_dispatch": fetch["spmv"], "write_kib_per_dispatch": write["spmv"],
+        "copy_fetch_kib": fetch["copy"], "copy_write_kib": write["copy"],
+        "fetch_scale": f_fac, "write_scale": w_fac,
+        "traffic_bytes": fetch_b + write_b,
+        "algorithmic_bytes": algorithmic_bytes(4096000, 4096000, 109215352, "f64"),
+    }
+    with open(out_path, "w") as f:
+        json.dump(res, f, indent=1)
+    print(json.dumps(res))
+
+
+# ----------------------------------------------------------------------------
+# main
+# ----------------------------------------------------------------------------
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=100)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--only", choices=["all", "headline"], default="all")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--pmc-pass", action="store_true")
+    ap.add_argument("--plan", default=None, help="plan (JSON) for --pmc-pass")
+    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "OUT", "PLAN_JSON"))
+    args = ap.parse_args()
+
+    if args.summarize_pmc:
+        summarize_pmc(*args.summarize_pmc)
+        return 0
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
+        print("bench.py measures one GPU only: the path runs on a single MI355X and has no "
+              "multi-GPU mode (run with --gpus 1)", file=sys.stderr)
+        return 2
+
+    import torch
+
+    from paper_1106_5908_amd import spmv
+    from workloads import gen
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        return 2
+    spmv.load()
+    if args.pmc_pass:
+        pmc_pass(args.steps, args.plan)
+        return 0
+
+    t_start = time.time()
+    bw = measure_bandwidth()
+    t0 = time.time()
+    A2, x2 = gen.workload_c2()
+    log(f"27-point 160^3 generated in {time.time() - t0:.1f}s ({A2.nnz} entries)")
+    head, ref2, den2 = run_spmv_path(A2, x2, "f64", args.steps, args.warmup, "27pt160")
+    flops = 2.0 * A2.nnz
+    mb = head["model_bytes"]
+    traffic = read_traffic(head["plan"])
+    achieved = mb / (head["mean_ms"] * 1e6)
+    roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic}
+    paths = {"bandwidth_probes": bw,
+             "headline_detail": {**head, "frac_of_copy_bw": achieved / bw["copy_GBs"],
+                                 "frac_of_triad_bw": achieved / bw["triad_GBs"],
+                                 "model_balance_B_per_flop": mb / flops,
+                                 "paper_eq1_balance": code_balance(A2.nnz / A2.n_rows)}}
+    if traffic:
+        paths["headline_detail"]["kappa_gpu"] = kappa_gpu(traffic, flops, mb)
+
+    if args.only == "all":
+        prec_rows = []
+        for prec in ("f32", "bf16", "f32f64"):
+            r, _, _ = run_spmv_path(A2, x2, prec, args.steps, args.warmup, "27pt160", ref2, den2)
+            r["speedup_vs_f64"] = head["ms_per_step"] / r["ms_per_step"]
+            prec_rows.append(r)
+        paths["precision_27pt160"] = prec_rows
+    cpu = None
+    if not args.no_cpu:
+        cpu = cpu_baseline(A2, x2)
+    del A2, x2, ref2, den2
+
+    if args.only == "all":
+        t0 = time.time()
+        A3, x3 = gen.workload_c3()
+        log(f"irregular N=8e6 generated in {time.time() - t0:.1f}s ({A3.nnz} entries)")
+        r3, ref3, den3 = run_spmv_path(A3, x3, "f64", args.steps, args.warmup, "irregular8M")
+        paths["irregular8M_f64"] = r3
+        p3 = []
+        for prec in ("f32", "bf16", "f32f64"):
+            r, _, _ = run_spmv_path(A3, x3, prec, args.steps, args.warmup, "irregular8M", ref3, den3)
+            r["speedup_vs_f64"] = r3["ms_per_step"] / r["ms_per_step"]
+            p3.append(r)
+        paths["precision_irregular8M"] = p3
+        del ref3, den3
+        sp, _, _ = split_paths(A3, x3, max(20, args.steps // 2), args.warmup)
+        paths["split_irregular8M"] = sp
+        paths["block_irregular8M"] = block_paths(A3, max(10, args.steps // 4), 3, r3["ms_per_step"])
+        del A3, x3
+        paths["batch_512_stencils"] = batch_paths(max(10, args.steps // 4), 3)
+
+    line = {
+        "metric": "spMV GFlop/s + achieved HBM GB/s vs 8 TB/s peak; FP64 vs mixed-prec at stated error",
+        "value": flops / (head["ms_per_step"] * 1e6),
+        "unit": "GFlop/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": head["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "3D 27-point stencil 160^3, FP64 CRS, int32 indices, "
+                               "C = C + A*B, inputs resident in HBM",
+                   "n_rows": 4096000, "nnz": 109215352, "achieved_model_GBs": achieved,
+                   "max_normalized_err": head["max_normalized_err"], "parallelism": "single GPU"},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+        "paths": paths,
+        "wall_s": time.time() - t_start,
+    }
+    print(json.dumps(line), flush=True)
+    return 0
+
+
+if __name__ == "__main__":
+    sys.exit(main())

@@ -204,6 +204,15 @@ spmv_status_t spmv_create_batch(int32_t count, const int64_t *n_rows, const int6
  *                MI355X's eight XCDs has its own L2)
  *   block_kt     columns of B processed per pass by spmv_run_block (4, 8,
  *                16); 0 lets the library choose
+ *   tiles_per_group  stream kernel: consecutive tiles handled by one
+ *                workgroup (1..64); with more than one, the next tile's
+ *                val / col_idx loads are issued while the current tile is
+ *                reduced (software pipelining)
+ *   panels       1, 2, 4 or 8: the entries of a part that covers all rows are
+ *                grouped by their offset from the diagonal (col - row) into
+ *                this many equal slices, each a CRS applied in turn, so the
+ *                window of B one slice gathers from is that many times
+ *                narrower and can stay in the L2 cache
  * ------------------------------------------------------------------------- */
 #define SPMV_KERNEL_STREAM 1
 #define SPMV_KERNEL_VECTOR 2
@@ -217,6 +226,8 @@ typedef struct spmv_plan {
     int32_t nontemporal;
     int32_t xcd_remap;
     int32_t block_kt;
+    int32_t tiles_per_group;
+    int32_t panels;
 } spmv_plan_t;
 
 spmv_status_t spmv_get_plan(spmv_handle_t h, int32_t part, spmv_plan_t *plan);

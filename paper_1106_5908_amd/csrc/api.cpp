@@ -199,18 +199,20 @@ RowStats row_stats(const int32_t *rp, int64_t n) {
   return s;
 }
 
-// Greedy tiles of consecutive rows holding at most `tile` entries (and at
-// most `tile` rows); a row longer than `tile` gets a tile of its own.
+// Greedy tiles of consecutive rows holding at most `tile` entries and at
+// most `tile` rows; a row longer than `tile` gets a tile of its own.  (Tiles
+// of more than 256 rows are reduced one row per lane in a loop.)
 std::vector<int32_t> make_tiles(const int32_t *rp, int64_t n, int64_t tile) {
+  const int64_t kMaxRows = tile;
   std::vector<int32_t> t;
-  t.reserve(size_t(n / std::max<int64_t>(1, tile / 16) + 2));
+  t.reserve(size_t(n / std::max<int64_t>(1, std::min(tile / 16, kMaxRows)) + 2));
   t.push_back(0);
   int64_t r = 0;
   while (r < n) {
     const int64_t start = rp[r];
     int64_t e = r + 1;
     if (int64_t(rp[e]) - start <= tile)
-      while (e < n && int64_t(rp[e + 1]) - start <= tile && e - r < tile) ++e;
+      while (e < n && int64_t(rp[e + 1]) - start <= tile && e - r < kMaxRows) ++e;
     t.push_back(int32_t(e));
     r = e;
   }
@@ -227,6 +229,8 @@ spmv_plan_t default_plan() {
   p.nontemporal = 1;
   p.xcd_remap = 1;
   p.block_kt = 0;
+  p.tiles_per_group = 1;
+  p.panels = 1;
   return p;
 }
 
@@ -239,6 +243,10 @@ void check_plan(const spmv_plan_t &p) {
     fail(SPMV_ERR_INVALID_ARG, "plan.lanes must be a power of two in [2, 64]");
   if (p.block_kt != 0 && p.block_kt != 4 && p.block_kt != 8 && p.block_kt != 16)
     fail(SPMV_ERR_INVALID_ARG, "plan.block_kt must be 0, 4, 8 or 16");
+  if (p.tiles_per_group < 1 || p.tiles_per_group > 64)
+    fail(SPMV_ERR_INVALID_ARG, "plan.tiles_per_group must be in [1, 64]");
+  if (p.panels != 1 && p.panels != 2 && p.panels != 4 && p.panels != 8)
+    fail(SPMV_ERR_INVALID_ARG, "plan.panels must be 1, 2, 4 or 8");
 }
 
 PlanDev to_dev(const spmv_plan_t &p) {
@@ -248,6 +256,7 @@ PlanDev to_dev(const spmv_plan_t &p) {
   d.lanes = p.lanes;
   d.nontemporal = p.nontemporal ? 1 : 0;
   d.xcd_remap = p.xcd_remap ? 1 : 0;
+  d.tiles_per_group = p.tiles_per_group;
   return d;
 }
 
@@ -268,7 +277,11 @@ struct Part {
   std::vector<int32_t> h_row_ptr;  // host copy (0-based), for tiling
   RowStats stats;
   spmv_plan_t plan = default_plan();
-  std::map<int, std::pair<DevBuf, int64_t>> tiles;  // tile_items -> (row starts, count)
+  // diagonal panels of this part (built when plan.panels > 1)
+  std::vector<std::unique_ptr<Part>> panels;
+  int panels_built = 1;
+  int64_t d_min = 0, d_max = 0;
+  std::map<int, std::pair<DevBuf, int64_t>> tiles;  // tile_items -> (tile starts, count)
 
   CsrDev dev() const {
     CsrDev d;
@@ -279,15 +292,17 @@ struct Part {
     d.n_rows = n_rows;
     return d;
   }
-  std::pair<const int32_t *, int64_t> tiles_for(int items) {
+  std::pair<const TileRP *, int64_t> tiles_for(int items) {
     auto it = tiles.find(items);
     if (it == tiles.end()) {
-      std::vector<int32_t> t = make_tiles(h_row_ptr.data(), n_rows, int64_t(kWG) * items);
+      const std::vector<int32_t> t = make_tiles(h_row_ptr.data(), n_rows, int64_t(kWG) * items);
+      std::vector<TileRP> tr(t.size());
+      for (size_t i = 0; i < t.size(); ++i) tr[i] = TileRP{t[i], h_row_ptr[size_t(t[i])]};
       DevBuf d;
-      upload(d, t.data(), t.size() * sizeof(int32_t), "tiles");
+      upload(d, tr.data(), tr.size() * sizeof(TileRP), "tiles");
       it = tiles.emplace(items, std::make_pair(std::move(d), int64_t(t.size()) - 1)).first;
     }
-    return {it->second.first.as<const int32_t>(), it->second.second};
+    return {it->second.first.as<const TileRP>(), it->second.second};
   }
 };
 
@@ -443,6 +458,8 @@ std::map<std::string, spmv_plan_t> cache_read() {
     field("nontemporal", p.nontemporal);
     field("xcd_remap", p.xcd_remap);
     field("block_kt", p.block_kt);
+    field("tiles_per_group", p.tiles_per_group);
+    field("panels", p.panels);
     out[key] = p;
     pos = b1 + 1;
   }
@@ -484,7 +501,9 @@ void cache_store(const std::string &key, const spmv_plan_t &p) {
       const spmv_plan_t &q = kv.second;
       f << "  \"" << kv.first << "\": {\"kernel\": " << q.kernel << ", \"tile_items\": "
         << q.tile_items << ", \"lanes\": " << q.lanes << ", \"nontemporal\": " << q.nontemporal
-        << ", \"xcd_remap\": " << q.xcd_remap << ", \"block_kt\": " << q.block_kt << "}"
+        << ", \"xcd_remap\": " << q.xcd_remap << ", \"block_kt\": " << q.block_kt
+        << ", \"tiles_per_group\": " << q.tiles_per_group << ", \"panels\": " << q.panels
+        << "}"
         << (++i < m.size() ? ",\n" : "\n");
     }
     f << "}\n";
@@ -592,12 +611,16 @@ void encode(int64_t n_rows, int64_t nnz, const int32_t *rp, const int32_t *col, 
   }
 }
 
+void build_panels(spmv_handle_s *h, Part &p, int K);
+
 void choose_plan(spmv_handle_s *h, Part &p, const char *part_name) {
   p.plan = default_plan();
   if (!(h->flags & SPMV_FLAG_NO_TUNE_CACHE)) {
     spmv_plan_t c;
     if (cache_lookup(tune_key(h->device, h->prec, 1, part_name, p.n_rows, p.stats), &c)) p.plan = c;
   }
+  if (p.plan.panels > 1 && (p.row_ids.p || h->kind == SPMV_KIND_BATCH)) p.plan.panels = 1;
+  if (p.plan.panels > 1) build_panels(h, p, p.plan.panels);
   if (std::getenv("SPMV_LOG"))
     std::fprintf(stderr, "libspmv: %s part n=%lld nnz=%lld mean=%.2f max=%lld cv=%.2f -> kernel=%d "
                          "tile_items=%d lanes=%d nt=%d remap=%d\n",
@@ -907,8 +930,78 @@ bool is_pinned_host(const void *p) {
   return attr.type == hipMemoryTypeHost;
 }
 
+// Diagonal panels of a part without a row list: entries grouped by their
+// offset d = col - row into K equal slices of the part's offset range, each
+// slice a CRS over all rows (built on the device; synchronous).
+void build_panels(spmv_handle_s *h, Part &p, int K) {
+  if (p.panels_built == K) return;
+  p.panels.clear();
+  p.panels_built = 1;
+  if (K <= 1) return;
+  if (p.row_ids.p) fail(SPMV_ERR_UNSUPPORTED, "diagonal panels need a part that covers all rows");
+  hipStream_t s = nullptr;
+  hip_ok(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
+  struct StreamCloser {
+    hipStream_t s;
+    ~StreamCloser() { (void)hipStreamDestroy(s); }
+  } closer{s};
+  const int64_t n = p.n_rows, m = n + 1;
+  DevBuf d2, counts, tmp;
+  d2.alloc(16, "panel range");
+  hip_ok(panel_d_range(p.row_ptr.as<int32_t>(), p.col.as<int32_t>(), n, d2.as<int64_t>(), &p.d_min,
+                       &p.d_max, s),
+         "panel range");
+  const int64_t span = p.d_max - p.d_min + 1;
+  counts.alloc(size_t(K) * size_t(m) * 4, "panel counts");
+  tmp.alloc(size_t(scan_tmp_elems(m)) * 4, "scan scratch");
+  hip_ok(panel_count(p.row_ptr.as<int32_t>(), p.col.as<int32_t>(), n, p.d_min, span, K,
+                     counts.as<int32_t>(), tmp.as<int32_t>(), s),
+         "panel count");
+  const int vb = val_bytes(h->prec);
+  PanelOut out{};
+  std::vector<std::unique_ptr<Part>> ps;
+  for (int k = 0; k < K; ++k) {
+    std::unique_ptr<Part> q(new Part());
+    q->n_rows = n;
+    q->h_row_ptr.resize(size_t(m));
+    hip_ok(hipMemcpyAsync(q->h_row_ptr.data(), counts.as<int32_t>() + int64_t(k) * m, size_t(m) * 4,
+                          hipMemcpyDeviceToHost, s),
+           "panel row_ptr readback");
+    ps.push_back(std::move(q));
+  }
+  hip_ok(hipStreamSynchronize(s), "panels");
+  for (int k = 0; k < K; ++k) {
+    Part &q = *ps[size_t(k)];
+    q.nnz = q.h_row_ptr[size_t(n)];
+    upload(q.row_ptr, q.h_row_ptr.data(), size_t(m) * 4, "panel row_ptr");
+    q.col.alloc(size_t(q.nnz) * 4, "panel col_idx");
+    q.val.alloc(size_t(q.nnz) * vb, "panel val");
+    q.stats = row_stats(q.h_row_ptr.data(), n);
+    out.col[k] = q.col.as<int32_t>();
+    out.val[k] = q.val.p;
+  }
+  hip_ok(panel_fill(h->prec, p.row_ptr.as<int32_t>(), p.col.as<int32_t>(), p.val.p, n, p.d_min,
+                    span, K, counts.as<int32_t>(), out, s),
+         "panel fill");
+  hip_ok(hipStreamSynchronize(s), "panels");
+  p.panels = std::move(ps);
+  p.panels_built = K;
+}
+
 void run_part(spmv_handle_s *h, Part &p, const void *B, void *C, hipStream_t s) {
   if (p.n_rows == 0 || p.nnz == 0) return;
+  if (p.plan.panels > 1) {
+    build_panels(h, p, p.plan.panels);
+    spmv_plan_t sub = p.plan;
+    sub.panels = 1;
+    const PlanDev pl = to_dev(sub);
+    for (auto &q : p.panels) {
+      if (q->nnz == 0) continue;
+      auto t = q->tiles_for(sub.tile_items);
+      hip_ok(launch_spmv(h->prec, q->dev(), pl, t.first, t.second, B, C, s), "kernel launch");
+    }
+    return;
+  }
   const PlanDev pl = to_dev(p.plan);
   auto t = p.tiles_for(p.plan.tile_items);
   hip_ok(launch_spmv(h->prec, p.dev(), pl, t.first, t.second, B, C, s), "kernel launch");
@@ -1067,16 +1160,20 @@ struct Timer {
 
 std::vector<spmv_plan_t> candidates() {
   std::vector<spmv_plan_t> c;
-  for (int e : {4, 8, 16}) {
+  for (int e : {4, 8, 16})
+    for (int tpw : {1, 2, 4, 8, 16, 32}) {
+      spmv_plan_t p = default_plan();
+      p.tile_items = e;
+      p.tiles_per_group = tpw;
+      c.push_back(p);
+    }
+  for (int e : {4, 8}) {
     spmv_plan_t p = default_plan();
     p.tile_items = e;
-    c.push_back(p);
-  }
-  {
-    spmv_plan_t p = default_plan();
+    p.tiles_per_group = 8;
     p.nontemporal = 0;
     c.push_back(p);
-    p = default_plan();
+    p.nontemporal = 1;
     p.xcd_remap = 0;
     c.push_back(p);
   }
@@ -1089,12 +1186,32 @@ std::vector<spmv_plan_t> candidates() {
   return c;
 }
 
+// Diagonal-panel candidates (parts that cover all rows only).
+std::vector<spmv_plan_t> panel_candidates() {
+  std::vector<spmv_plan_t> c;
+  for (int k : {2, 4, 8})
+    for (int e : {4, 8})
+      for (int rm : {0, 1}) {
+        spmv_plan_t p = default_plan();
+        p.panels = k;
+        p.tile_items = e;
+        p.xcd_remap = rm;
+        c.push_back(p);
+      }
+  return c;
+}
+
 void tune_part(spmv_handle_s *h, Part &p, const char *name, void *x, void *y, hipStream_t s,
                Timer &tm) {
   if (p.n_rows == 0 || p.nnz == 0) return;
   float best = 1e30f;
   spmv_plan_t best_p = p.plan;
-  for (const spmv_plan_t &c : candidates()) {
+  std::vector<spmv_plan_t> cands = candidates();
+  if (!p.row_ids.p) {
+    const std::vector<spmv_plan_t> pc = panel_candidates();
+    cands.insert(cands.end(), pc.begin(), pc.end());
+  }
+  for (const spmv_plan_t &c : cands) {
     p.plan = c;
     const float ms = tm.median_ms([&] { run_part(h, p, x, y, s); }, s);
     if (ms < best) {
@@ -1105,6 +1222,11 @@ void tune_part(spmv_handle_s *h, Part &p, const char *name, void *x, void *y, hi
   best_p.block_kt = 0;
   p.plan = best_p;
   (void)p.tiles_for(p.plan.tile_items);
+  if (p.plan.panels > 1) build_panels(h, p, p.plan.panels);
+  else {
+    p.panels.clear();  // free the device copies of panels that lost
+    p.panels_built = 1;
+  }
   if (std::getenv("SPMV_LOG"))
     std::fprintf(stderr, "libspmv: tuned %s part: kernel=%d tile_items=%d lanes=%d nt=%d remap=%d "
                          "(%.1f us)\n",
@@ -1131,10 +1253,20 @@ extern "C" spmv_status_t spmv_set_plan(spmv_handle_t h_, int32_t part, const spm
     check_plan(*plan);
     if (h->kind == SPMV_KIND_BATCH && plan->kernel != SPMV_KERNEL_STREAM)
       fail(SPMV_ERR_UNSUPPORTED, "batch handles run the stream kernel only");
+    if (h->kind == SPMV_KIND_BATCH && plan->panels != 1)
+      fail(SPMV_ERR_UNSUPPORTED, "batch handles do not use diagonal panels");
     Part &p = part_of(h, part);
+    if (plan->panels > 1 && p.row_ids.p)
+      fail(SPMV_ERR_UNSUPPORTED, "diagonal panels need a part that covers all rows");
     DeviceGuard dg(h->device);
     p.plan = *plan;
-    if (h->kind != SPMV_KIND_BATCH) (void)p.tiles_for(p.plan.tile_items);
+    if (h->kind != SPMV_KIND_BATCH) {
+      (void)p.tiles_for(p.plan.tile_items);
+      if (p.plan.panels > 1) {
+        build_panels(h, p, p.plan.panels);
+        for (auto &q : p.panels) (void)q->tiles_for(p.plan.tile_items);
+      }
+    }
   });
 }
 

@@ -67,9 +67,117 @@ __device__ __forceinline__ int64_t xcd_tile(int64_t bid, int64_t n, int remap) {
 
 __device__ __forceinline__ int floor_pow2(int v) { return 1 << (31 - __builtin_clz(v)); }
 
+// Barrier for LDS hand-over only.  The fence is restricted to the local
+// address space, so loads of global memory still in flight (the next tile's
+// prefetch) are not drained at the barrier.
+__device__ __forceinline__ void lds_barrier() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup", "local");
+  __builtin_amdgcn_s_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
+}
+
 // ---------------------------------------------------------------------------
-// One tile of the stream kernel: rows [r0, r1) of a CRS part.
+// Stream kernel building blocks.  A tile is rows [r0, r1) holding entries
+// [p0, p1); p1 - p0 <= 256 * E unless the tile is a single long row.
 // ---------------------------------------------------------------------------
+
+// Coalesced loads of a tile's col_idx and val: lane tid takes entries
+// tid, tid + 256, ...; indices past the tile are clamped to its last entry
+// (nnz >= 1), so every lane issues all E loads with no branch.
+template <int E, bool NT, class V>
+__device__ __forceinline__ void load_cv(const int32_t *__restrict__ col,
+                                        const V *__restrict__ val, int p0, int nnz, int (&c)[E],
+                                        V (&v)[E]) {
+  const int last = nnz - 1;
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int k = min(e * WG + (int)threadIdx.x, last);
+    c[e] = ld<int32_t, NT>(col + p0 + k);
+    v[e] = ld<V, NT>(val + p0 + k);
+  }
+}
+
+// A row longer than a tile (the planner gives it a tile of its own): the
+// workgroup strides through it and reduces in LDS.  Ends with a barrier.
+template <int P, bool NT>
+__device__ void long_row(const int32_t *__restrict__ col, const typename Ty<P>::V *__restrict__ val,
+                         int p0, int p1, int64_t out, const typename Ty<P>::X *__restrict__ x,
+                         typename Ty<P>::X *__restrict__ y, typename Ty<P>::X *s_red) {
+  using V = typename Ty<P>::V;
+  using X = typename Ty<P>::X;
+  const int tid = threadIdx.x;
+  X acc = neg_zero<X>();
+  for (int j = p0 + tid; j < p1; j += WG)
+    acc += widen<X>(ld<V, NT>(val + j)) * x[ld<int32_t, NT>(col + j)];
+  s_red[tid] = acc;
+  lds_barrier();
+  for (int off = WG / 2; off > 0; off >>= 1) {
+    if (tid < off) s_red[tid] += s_red[tid + off];
+    lds_barrier();
+  }
+  if (tid == 0) y[out] = y[out] + s_red[0];
+  lds_barrier();
+}
+
+// Where a lane's row sum goes in phase 2 (see tile_reduce).
+template <class X>
+struct RowSlot {
+  int L, lane, a, b;
+  int64_t o;
+  X c_old;
+};
+
+// Phase-2 assignment of a tile with at most 256 rows: L lanes per row (a
+// power of two, at most 64).  Row bounds and the old C value are loaded here,
+// early and without branches (lanes past the last row take the last row and
+// are masked at the write), so their latency hides under phase 1.  C rows of
+// a tile are written by this workgroup only.  Lanes with b <= a write nothing.
+template <class X, bool IND>
+__device__ __forceinline__ RowSlot<X> row_slot(const int32_t *__restrict__ rp,
+                                               const int32_t *__restrict__ row_ids, int r0,
+                                               int nrows, int p0, const X *__restrict__ y) {
+  RowSlot<X> s;
+  s.L = min(floor_pow2(max(WG / max(nrows, 1), 1)), 64);
+  const int lg = __builtin_ctz(s.L);
+  const int row = (int)threadIdx.x >> lg;
+  const int rc = min(row, max(nrows, 1) - 1);
+  s.lane = (int)threadIdx.x & (s.L - 1);
+  s.a = rp[r0 + rc] - p0;
+  s.b = rp[r0 + rc + (row < nrows ? 1 : 0)] - p0;  // a lane past the last row gets b == a
+  if constexpr (IND) s.o = row_ids[r0 + rc];
+  else s.o = (int64_t)(r0 + rc);
+  s.c_old = y[s.o];
+  return s;
+}
+
+// Phase 2: every row of the tile summed out of LDS and added to C.
+template <class X, bool IND>
+__device__ __forceinline__ void tile_reduce(const int32_t *__restrict__ rp,
+                                            const int32_t *__restrict__ row_ids, int r0, int nrows,
+                                            int p0, const RowSlot<X> &s, X *__restrict__ y,
+                                            const X *s_prod) {
+  if (nrows <= WG) {
+    X acc = neg_zero<X>();
+    for (int j = s.a + s.lane; j < s.b; j += s.L) acc += s_prod[j];
+    for (int off = s.L >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (s.lane == 0 && s.b > s.a) y[s.o] = s.c_old + acc;
+  } else {
+    for (int rr = (int)threadIdx.x; rr < nrows; rr += WG) {
+      const int ra = rp[r0 + rr] - p0;
+      const int rb = rp[r0 + rr + 1] - p0;
+      if (rb > ra) {
+        X acc = neg_zero<X>();
+        for (int j = ra; j < rb; ++j) acc += s_prod[j];
+        int64_t oo;
+        if constexpr (IND) oo = row_ids[r0 + rr];
+        else oo = (int64_t)(r0 + rr);
+        y[oo] = y[oo] + acc;
+      }
+    }
+  }
+}
+
+// One tile, not pipelined (used by the batch kernels).  Ends with a barrier.
 template <int P, int E, bool NT>
 __device__ __forceinline__ void stream_tile(const int32_t *__restrict__ rp,
                                             const int32_t *__restrict__ col,
@@ -80,92 +188,150 @@ __device__ __forceinline__ void stream_tile(const int32_t *__restrict__ rp,
                                             typename Ty<P>::X *s_prod) {
   using V = typename Ty<P>::V;
   using X = typename Ty<P>::X;
-  constexpr int TILE = WG * E;
-  const int tid = threadIdx.x;
   const int p0 = rp[r0];
-  const int p1 = rp[r1];
-  const int nnz = p1 - p0;
-
-  if (nnz > TILE) {
-    // A row longer than a tile; the planner gives such a row a tile of its own.
-    X acc = neg_zero<X>();
-    for (int j = p0 + tid; j < p1; j += WG)
-      acc += widen<X>(ld<V, NT>(val + j)) * x[ld<int32_t, NT>(col + j)];
-    s_prod[tid] = acc;
-    __syncthreads();
-    for (int off = WG / 2; off > 0; off >>= 1) {
-      if (tid < off) s_prod[tid] += s_prod[tid + off];
-      __syncthreads();
-    }
-    if (tid == 0) {
-      const int64_t o = row_ids ? row_ids[r0] : r0;
-      y[o] = y[o] + s_prod[0];
-    }
+  const int nnz = rp[r1] - p0;
+  const int nrows = r1 - r0;
+  if (nnz > WG * E) {
+    long_row<P, NT>(col, val, p0, p0 + nnz, row_ids ? row_ids[r0] : r0, x, y, s_prod);
     return;
   }
-
-  // Phase 1: coalesced loads of the tile's col_idx and val, all in flight
-  // before the gathers of B, products into LDS.
-  int c[E];
-  V v[E];
+  RowSlot<X> slot{};
+  if (nrows <= WG) slot = row_slot<X, false>(rp, row_ids, r0, nrows, p0, y);
+  if (nnz > 0) {
+    int c[E];
+    V v[E];
+    load_cv<E, NT>(col, val, p0, nnz, c, v);
+    X xv[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int k = e * WG + tid;
-    if (k < nnz) {
-      c[e] = ld<int32_t, NT>(col + p0 + k);
-      v[e] = ld<V, NT>(val + p0 + k);
-    }
-  }
+    for (int e = 0; e < E; ++e) xv[e] = x[c[e]];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int k = e * WG + tid;
-    if (k < nnz) s_prod[k] = widen<X>(v[e]) * x[c[e]];
+    for (int e = 0; e < E; ++e) s_prod[e * WG + threadIdx.x] = widen<X>(v[e]) * xv[e];
   }
-  __syncthreads();
-
-  // Phase 2: per-row sums out of LDS.
-  const int nrows = r1 - r0;
-  if (nrows <= WG) {
-    const int L = min(floor_pow2(WG / nrows), 64);
-    const int lg = __builtin_ctz(L);
-    const int row = tid >> lg;
-    const int lane = tid & (L - 1);
-    int a = 0, b = 0;
-    if (row < nrows) {
-      a = rp[r0 + row] - p0;
-      b = rp[r0 + row + 1] - p0;
-    }
-    X acc = neg_zero<X>();
-    for (int j = a + lane; j < b; j += L) acc += s_prod[j];
-    for (int off = L >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (lane == 0 && b > a) {
-      const int64_t o = row_ids ? row_ids[r0 + row] : (int64_t)(r0 + row);
-      y[o] = y[o] + acc;
-    }
-  } else {
-    for (int row = tid; row < nrows; row += WG) {
-      const int a = rp[r0 + row] - p0;
-      const int b = rp[r0 + row + 1] - p0;
-      if (b > a) {
-        X acc = neg_zero<X>();
-        for (int j = a; j < b; ++j) acc += s_prod[j];
-        const int64_t o = row_ids ? row_ids[r0 + row] : (int64_t)(r0 + row);
-        y[o] = y[o] + acc;
-      }
-    }
-  }
+  lds_barrier();
+  tile_reduce<X, false>(rp, row_ids, r0, nrows, p0, slot, y, s_prod);
+  lds_barrier();
 }
 
-template <int P, int E, bool NT>
-__global__ __launch_bounds__(WG) void k_stream(CsrDev A, const int32_t *__restrict__ tiles,
-                                               int64_t n_tiles, int remap, const void *xv,
-                                               void *yv) {
+// Stream kernel: workgroup g takes tiles [g*tpw, min((g+1)*tpw, n_tiles)) in
+// order.  While a tile's products are reduced, the next tile's col_idx and
+// val are already in flight (issued before the current tile's barrier).
+// Phase 1 per tile: E coalesced col_idx / val loads per lane, then E gathers
+// of B, then products into LDS; indices past the tile are clamped to its
+// last entry and their products land in LDS slots phase 2 never reads.
+// Every load of the loop is issued unconditionally (a tile without entries,
+// or a missing next tile, reads entry 0 of the part instead), so the
+// compiler's wait counts never have to drain the prefetch early.  The kernel
+// is only launched for parts with at least one entry.
+// One tile per workgroup (tiles_per_group == 1): the plain form of the
+// stream kernel, with no prefetch state.
+template <int P, int E, bool NT, bool IND>
+__global__ __launch_bounds__(WG) void k_stream1(CsrDev A, const TileRP *__restrict__ tiles,
+                                                int64_t n_tiles, int remap, const void *xv,
+                                                void *yv) {
   using V = typename Ty<P>::V;
   using X = typename Ty<P>::X;
-  __shared__ X s_prod[WG * E];
+  constexpr int TILE = WG * E;
+  __shared__ X s_prod[TILE];
+  const V *__restrict__ val = static_cast<const V *>(A.val);
+  const X *__restrict__ x = static_cast<const X *>(xv);
+  X *__restrict__ y = static_cast<X *>(yv);
   const int64_t t = xcd_tile(blockIdx.x, n_tiles, remap);
-  stream_tile<P, E, NT>(A.row_ptr, A.col, static_cast<const V *>(A.val), A.row_ids, tiles[t],
-                        tiles[t + 1], static_cast<const X *>(xv), static_cast<X *>(yv), s_prod);
+  const TileRP m0 = tiles[t], m1 = tiles[t + 1];
+  const int nnz = m1.p - m0.p;
+  const int nrows = m1.r - m0.r;
+  if (nnz > TILE) {
+    long_row<P, NT>(A.col, val, m0.p, m1.p, IND ? (int64_t)A.row_ids[m0.r] : (int64_t)m0.r, x, y,
+                    s_prod);
+    return;
+  }
+  if (nnz == 0) return;  // only empty rows: C stays as it is
+  int c[E];
+  V v[E];
+  load_cv<E, NT>(A.col, val, m0.p, nnz, c, v);
+  const RowSlot<X> slot = row_slot<X, IND>(A.row_ptr, A.row_ids, m0.r, nrows, m0.p, y);
+  X xg[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) xg[e] = x[c[e]];
+#pragma unroll
+  for (int e = 0; e < E; ++e) s_prod[e * WG + threadIdx.x] = widen<X>(v[e]) * xg[e];
+  __syncthreads();
+  tile_reduce<X, IND>(A.row_ptr, A.row_ids, m0.r, nrows, m0.p, slot, y, s_prod);
+}
+
+template <int P, int E, bool NT, bool IND>
+__global__ __launch_bounds__(WG) void k_stream(CsrDev A, const TileRP *__restrict__ tiles,
+                                               int64_t n_tiles, int tpw, int64_t n_groups,
+                                               int remap, const void *xv, void *yv) {
+  using V = typename Ty<P>::V;
+  using X = typename Ty<P>::X;
+  constexpr int TILE = WG * E;
+  __shared__ X s_prod[TILE];
+  const V *__restrict__ val = static_cast<const V *>(A.val);
+  const X *__restrict__ x = static_cast<const X *>(xv);
+  X *__restrict__ y = static_cast<X *>(yv);
+  const int64_t g = xcd_tile(blockIdx.x, n_groups, remap);
+  int64_t t = g * tpw;
+  const int64_t t_end = min(t + (int64_t)tpw, n_tiles);
+  if (t >= t_end) return;
+  TileRP m0 = tiles[t], m1 = tiles[t + 1];
+  int c[E];
+  V v[E];
+  RowSlot<X> slot;
+  {
+    const int nnz = m1.p - m0.p;
+    const bool ok = nnz > 0 && nnz <= TILE;
+    load_cv<E, NT>(A.col, val, ok ? m0.p : 0, ok ? nnz : 1, c, v);
+    slot = row_slot<X, IND>(A.row_ptr, A.row_ids, m0.r, m1.r - m0.r, m0.p, y);
+  }
+  for (;;) {
+    const int nnz = m1.p - m0.p;
+    const int nrows = m1.r - m0.r;
+    const bool more = t + 1 < t_end;
+    const TileRP m2 = tiles[min(t + 2, n_tiles)];
+    if (nnz > TILE) {
+      long_row<P, NT>(A.col, val, m0.p, m1.p, IND ? (int64_t)A.row_ids[m0.r] : (int64_t)m0.r, x, y,
+                      s_prod);
+      if (!more) break;
+      ++t;
+      m0 = m1;
+      m1 = m2;
+      const int nn = m1.p - m0.p;
+      const bool ok = nn > 0 && nn <= TILE;
+      load_cv<E, NT>(A.col, val, ok ? m0.p : 0, ok ? nn : 1, c, v);
+      slot = row_slot<X, IND>(A.row_ptr, A.row_ids, m0.r, m1.r - m0.r, m0.p, y);
+      continue;
+    }
+    X xg[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) xg[e] = x[c[e]];
+    // prefetch the next tile: its entries and its row assignment (the
+    // current tile's again when there is no next tile)
+    int cn[E];
+    V vn[E];
+    RowSlot<X> slot_n;
+    {
+      const int nn = m2.p - m1.p;
+      const bool ok = more && nn > 0 && nn <= TILE;
+      load_cv<E, NT>(A.col, val, ok ? m1.p : 0, ok ? nn : 1, cn, vn);
+      const TileRP q0 = more ? m1 : m0, q1 = more ? m2 : m1;
+      slot_n = row_slot<X, IND>(A.row_ptr, A.row_ids, q0.r, q1.r - q0.r, q0.p, y);
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) s_prod[e * WG + threadIdx.x] = widen<X>(v[e]) * xg[e];
+    lds_barrier();
+    tile_reduce<X, IND>(A.row_ptr, A.row_ids, m0.r, nrows, m0.p, slot, y, s_prod);
+    lds_barrier();
+    if (!more) break;
+    ++t;
+    m0 = m1;
+    m1 = m2;
+    slot = slot_n;
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      c[e] = cn[e];
+      v[e] = vn[e];
+    }
+  }
 }
 
 // ---------------------------------------------------------------------------
@@ -228,7 +394,7 @@ __device__ __forceinline__ void load_vec(const X *p, X (&out)[VW]) {
 }
 
 template <int P, int E, int KT, int VW, bool NT>
-__global__ __launch_bounds__(WG) void k_block(CsrDev A, const int32_t *__restrict__ tiles,
+__global__ __launch_bounds__(WG) void k_block(CsrDev A, const TileRP *__restrict__ tiles,
                                               int64_t n_tiles, int remap, int k, int t0,
                                               const void *Bv, int64_t ldb, void *Cv, int64_t ldc) {
   using V = typename Ty<P>::V;
@@ -244,8 +410,8 @@ __global__ __launch_bounds__(WG) void k_block(CsrDev A, const int32_t *__restric
   X *__restrict__ C = static_cast<X *>(Cv);
   const int tid = threadIdx.x;
   const int64_t t = xcd_tile(blockIdx.x, n_tiles, remap);
-  const int r0 = tiles[t], r1 = tiles[t + 1];
-  const int p0 = A.row_ptr[r0], p1 = A.row_ptr[r1];
+  const int r0 = tiles[t].r, r1 = tiles[t + 1].r;
+  const int p0 = tiles[t].p, p1 = tiles[t + 1].p;
   const int nnz = p1 - p0;
   const int g = tid / G;
   const int lane = tid % G;
@@ -283,12 +449,21 @@ __global__ __launch_bounds__(WG) void k_block(CsrDev A, const int32_t *__restric
     return;
   }
 
+  if (nnz > 0) {
+    // clamped, unconditional staging (slots past the tile are never read)
+    const int last = nnz - 1;
+    int cc[E];
+    V vv[E];
 #pragma unroll
-  for (int e = 0; e < E; ++e) {
-    const int kk = e * WG + tid;
-    if (kk < nnz) {
-      s_col[kk] = ld<int32_t, NT>(A.col + p0 + kk);
-      s_val[kk] = widen<X>(ld<V, NT>(val + p0 + kk));
+    for (int e = 0; e < E; ++e) {
+      const int kk = min(e * WG + tid, last);
+      cc[e] = ld<int32_t, NT>(A.col + p0 + kk);
+      vv[e] = ld<V, NT>(val + p0 + kk);
+    }
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      s_col[e * WG + tid] = cc[e];
+      s_val[e * WG + tid] = widen<X>(vv[e]);
     }
   }
   __syncthreads();
@@ -389,16 +564,31 @@ __global__ __launch_bounds__(WG) void k_batch_flat(const int32_t *__restrict__ r
 // ---------------------------------------------------------------------------
 // Dispatch helpers
 // ---------------------------------------------------------------------------
+template <int P, int E, bool NT, bool IND>
+void launch_stream(const CsrDev &A, const PlanDev &pl, const TileRP *tiles, int64_t n_tiles, int tpw,
+                   int64_t n_groups, const void *x, void *y, hipStream_t s) {
+  if (tpw == 1)
+    hipLaunchKernelGGL((k_stream1<P, E, NT, IND>), dim3((unsigned)n_tiles), dim3(WG), 0, s, A,
+                       tiles, n_tiles, pl.xcd_remap, x, y);
+  else
+    hipLaunchKernelGGL((k_stream<P, E, NT, IND>), dim3((unsigned)n_groups), dim3(WG), 0, s, A,
+                       tiles, n_tiles, tpw, n_groups, pl.xcd_remap, x, y);
+}
+
 template <int P, int E>
-hipError_t run_stream(const CsrDev &A, const PlanDev &pl, const int32_t *tiles, int64_t n_tiles,
+hipError_t run_stream(const CsrDev &A, const PlanDev &pl, const TileRP *tiles, int64_t n_tiles,
                       const void *x, void *y, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
-  if (pl.nontemporal)
-    hipLaunchKernelGGL((k_stream<P, E, true>), dim3((unsigned)n_tiles), dim3(WG), 0, s, A, tiles,
-                       n_tiles, pl.xcd_remap, x, y);
-  else
-    hipLaunchKernelGGL((k_stream<P, E, false>), dim3((unsigned)n_tiles), dim3(WG), 0, s, A, tiles,
-                       n_tiles, pl.xcd_remap, x, y);
+  const int tpw = pl.tiles_per_group < 1 ? 1 : pl.tiles_per_group;
+  const int64_t n_groups = (n_tiles + tpw - 1) / tpw;
+  const bool ind = A.row_ids != nullptr;
+  if (pl.nontemporal) {
+    if (ind) launch_stream<P, E, true, true>(A, pl, tiles, n_tiles, tpw, n_groups, x, y, s);
+    else launch_stream<P, E, true, false>(A, pl, tiles, n_tiles, tpw, n_groups, x, y, s);
+  } else {
+    if (ind) launch_stream<P, E, false, true>(A, pl, tiles, n_tiles, tpw, n_groups, x, y, s);
+    else launch_stream<P, E, false, false>(A, pl, tiles, n_tiles, tpw, n_groups, x, y, s);
+  }
   return hipGetLastError();
 }
 
@@ -417,7 +607,7 @@ hipError_t run_vector(const CsrDev &A, const PlanDev &pl, const void *x, void *y
 }
 
 template <int P>
-hipError_t dispatch_spmv(const CsrDev &A, const PlanDev &pl, const int32_t *tiles, int64_t n_tiles,
+hipError_t dispatch_spmv(const CsrDev &A, const PlanDev &pl, const TileRP *tiles, int64_t n_tiles,
                          const void *x, void *y, hipStream_t s) {
   if (pl.kernel == 2) {
     switch (pl.lanes) {
@@ -439,7 +629,7 @@ hipError_t dispatch_spmv(const CsrDev &A, const PlanDev &pl, const int32_t *tile
 }
 
 template <int P, int KT, int VW>
-hipError_t run_block_kt(const CsrDev &A, const int32_t *tiles, int64_t n_tiles, int nt, int remap,
+hipError_t run_block_kt(const CsrDev &A, const TileRP *tiles, int64_t n_tiles, int nt, int remap,
                         int k, int t0, const void *B, int64_t ldb, void *C, int64_t ldc,
                         hipStream_t s) {
   if (nt)
@@ -452,7 +642,7 @@ hipError_t run_block_kt(const CsrDev &A, const int32_t *tiles, int64_t n_tiles, 
 }
 
 template <int P, int VW>
-hipError_t run_block_vw(const CsrDev &A, const int32_t *tiles, int64_t n_tiles, int nt, int remap,
+hipError_t run_block_vw(const CsrDev &A, const TileRP *tiles, int64_t n_tiles, int nt, int remap,
                         int kt, int k, int t0, const void *B, int64_t ldb, void *C, int64_t ldc,
                         hipStream_t s) {
   switch (kt) {
@@ -464,7 +654,7 @@ hipError_t run_block_vw(const CsrDev &A, const int32_t *tiles, int64_t n_tiles, 
 }
 
 template <int P>
-hipError_t dispatch_block(const CsrDev &A, const int32_t *tiles, int64_t n_tiles, int nt, int remap,
+hipError_t dispatch_block(const CsrDev &A, const TileRP *tiles, int64_t n_tiles, int nt, int remap,
                           int kt, int k, const void *B, int64_t ldb, void *C, int64_t ldc,
                           hipStream_t s) {
   using X = typename Ty<P>::X;
@@ -533,12 +723,12 @@ int persistent_grid_for(int device) {
     default: return hipErrorInvalidValue; \
   }
 
-hipError_t launch_spmv(int prec, const CsrDev &A, const PlanDev &plan, const int32_t *tiles,
+hipError_t launch_spmv(int prec, const CsrDev &A, const PlanDev &plan, const TileRP *tiles,
                        int64_t n_tiles, const void *x, void *y, hipStream_t s) {
   SPMV_PREC_SWITCH(prec, (dispatch_spmv<PP>(A, plan, tiles, n_tiles, x, y, s)))
 }
 
-hipError_t launch_spmv_block(int prec, const CsrDev &A, const int32_t *tiles, int64_t n_tiles,
+hipError_t launch_spmv_block(int prec, const CsrDev &A, const TileRP *tiles, int64_t n_tiles,
                              int tile_items, int nontemporal, int xcd_remap, int kt, int k,
                              const void *B, int64_t ldb, void *C, int64_t ldc, hipStream_t s) {
   if (tile_items != 4) return hipErrorInvalidValue;

@@ -156,7 +156,121 @@ __global__ void k_split_fill(const int32_t *__restrict__ rp, const int32_t *__re
   }
 }
 
+// ---- diagonal panels --------------------------------------------------------
+// Panel of an entry: its offset d = col - row placed in one of K equal
+// slices of [dmin, dmin + span).
+__device__ __forceinline__ int panel_of(int64_t d, int64_t dmin, int64_t span, int K) {
+  const int64_t q = ((d - dmin) * K) / span;
+  return (int)(q < 0 ? 0 : (q >= K ? K - 1 : q));
+}
+
+__global__ void k_d_range(const int32_t *__restrict__ rp, const int32_t *__restrict__ col, int64_t n,
+                          int64_t *out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t lo = INT64_MAX, hi = INT64_MIN;
+  if (i < n)
+    for (int j = rp[i]; j < rp[i + 1]; ++j) {
+      const int64_t d = (int64_t)col[j] - i;
+      lo = d < lo ? d : lo;
+      hi = d > hi ? d : hi;
+    }
+  for (int off = 32; off > 0; off >>= 1) {
+    const int64_t a = __shfl_xor(lo, off), b = __shfl_xor(hi, off);
+    lo = a < lo ? a : lo;
+    hi = b > hi ? b : hi;
+  }
+  if ((threadIdx.x & 63) == 0 && lo <= hi) {
+    atomicMin((unsigned long long *)&out[0], (unsigned long long)(lo + ((int64_t)1 << 40)));
+    atomicMax((unsigned long long *)&out[1], (unsigned long long)(hi + ((int64_t)1 << 40)));
+  }
+}
+
+// counts: K arrays of n + 1 entries (entry n is a zero pad for the scan)
+__global__ void k_panel_count(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                              int64_t n, int64_t dmin, int64_t span, int K,
+                              int32_t *__restrict__ counts) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i > n) return;
+  int c[PANEL_MAX] = {0};
+  if (i < n)
+    for (int j = rp[i]; j < rp[i + 1]; ++j) ++c[panel_of((int64_t)col[j] - i, dmin, span, K)];
+  for (int k = 0; k < K; ++k) counts[(int64_t)k * (n + 1) + i] = c[k];
+}
+
+template <class T>
+__global__ void k_panel_fill(const int32_t *__restrict__ rp, const int32_t *__restrict__ col,
+                             const T *__restrict__ val, int64_t n, int64_t dmin, int64_t span, int K,
+                             const int32_t *__restrict__ starts, PanelOut out) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int pos[PANEL_MAX];
+  for (int k = 0; k < K; ++k) pos[k] = starts[(int64_t)k * (n + 1) + i];
+  for (int j = rp[i]; j < rp[i + 1]; ++j) {
+    const int k = panel_of((int64_t)col[j] - i, dmin, span, K);
+    out.col[k][pos[k]] = col[j];
+    static_cast<T *>(out.val[k])[pos[k]] = val[j];
+    ++pos[k];
+  }
+}
+
 }  // namespace
+
+hipError_t panel_d_range(const int32_t *row_ptr, const int32_t *col, int64_t n_rows, int64_t *dev2,
+                         int64_t *dmin, int64_t *dmax, hipStream_t s) {
+  const int64_t init[2] = {INT64_MAX, 0};
+  hipError_t e = hipMemcpyAsync(dev2, init, sizeof(init), hipMemcpyHostToDevice, s);
+  if (e != hipSuccess) return e;
+  if (n_rows > 0)
+    hipLaunchKernelGGL(k_d_range, dim3((unsigned)((n_rows + 255) / 256)), dim3(256), 0, s, row_ptr,
+                       col, n_rows, dev2);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  int64_t r[2];
+  e = hipMemcpyAsync(r, dev2, sizeof(r), hipMemcpyDeviceToHost, s);
+  if (e != hipSuccess) return e;
+  e = hipStreamSynchronize(s);
+  if (e != hipSuccess) return e;
+  if (r[0] == INT64_MAX) {  // no entries
+    *dmin = 0;
+    *dmax = 0;
+  } else {
+    *dmin = r[0] - ((int64_t)1 << 40);
+    *dmax = r[1] - ((int64_t)1 << 40);
+  }
+  return hipSuccess;
+}
+
+hipError_t panel_count(const int32_t *row_ptr, const int32_t *col, int64_t n_rows, int64_t dmin,
+                       int64_t span, int K, int32_t *counts, int32_t *scan_tmp, hipStream_t s) {
+  const int64_t m = n_rows + 1;
+  hipLaunchKernelGGL(k_panel_count, dim3((unsigned)((m + 255) / 256)), dim3(256), 0, s, row_ptr, col,
+                     n_rows, dmin, span, K, counts);
+  hipError_t e = hipGetLastError();
+  for (int k = 0; k < K && e == hipSuccess; ++k) e = scan_exclusive(counts + (int64_t)k * m, m, scan_tmp, s);
+  return e;
+}
+
+hipError_t panel_fill(int prec, const int32_t *row_ptr, const int32_t *col, const void *val,
+                      int64_t n_rows, int64_t dmin, int64_t span, int K, const int32_t *starts,
+                      const PanelOut &out, hipStream_t s) {
+  if (n_rows <= 0) return hipSuccess;
+  const unsigned nb = (unsigned)((n_rows + 255) / 256);
+  switch (val_bytes(prec)) {
+    case 8:
+      hipLaunchKernelGGL(k_panel_fill<uint64_t>, dim3(nb), dim3(256), 0, s, row_ptr, col,
+                         static_cast<const uint64_t *>(val), n_rows, dmin, span, K, starts, out);
+      break;
+    case 4:
+      hipLaunchKernelGGL(k_panel_fill<uint32_t>, dim3(nb), dim3(256), 0, s, row_ptr, col,
+                         static_cast<const uint32_t *>(val), n_rows, dmin, span, K, starts, out);
+      break;
+    default:
+      hipLaunchKernelGGL(k_panel_fill<uint16_t>, dim3(nb), dim3(256), 0, s, row_ptr, col,
+                         static_cast<const uint16_t *>(val), n_rows, dmin, span, K, starts, out);
+      break;
+  }
+  return hipGetLastError();
+}
 
 int64_t split_work_elems(int64_t n_rows) { return 3 * (n_rows + 1); }
 int64_t scan_tmp_elems(int64_t n) { return (n + SCAN_CHUNK - 1) / SCAN_CHUNK + 1; }

@@ -30,6 +30,14 @@ struct PlanDev {
   int lanes;        // vector: lanes per row
   int nontemporal;  // streaming hint on val / col
   int xcd_remap;    // place consecutive tiles on one XCD
+  int tiles_per_group;  // stream: consecutive tiles per workgroup (software pipelined)
+};
+
+// Start of a tile: first row and first stored entry (row_ptr[r]).  A part
+// with T tiles has T + 1 of these; the last one is (n_rows, nnz).
+struct TileRP {
+  int32_t r;
+  int32_t p;
 };
 
 // Per-member descriptor of a batch: offsets into the pooled arrays.
@@ -49,12 +57,12 @@ struct BatchTile {
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------------
-// All return hipSuccess or the launch error.  `tiles` (stream kernel) holds
-// n_tiles + 1 row starts of the tiles of `A`.
-hipError_t launch_spmv(int prec, const CsrDev &A, const PlanDev &plan, const int32_t *tiles,
+// All return hipSuccess or the launch error.  `tiles` (stream and block
+// kernels) holds the n_tiles + 1 tile starts of `A`.
+hipError_t launch_spmv(int prec, const CsrDev &A, const PlanDev &plan, const TileRP *tiles,
                        int64_t n_tiles, const void *x, void *y, hipStream_t s);
 
-hipError_t launch_spmv_block(int prec, const CsrDev &A, const int32_t *tiles, int64_t n_tiles,
+hipError_t launch_spmv_block(int prec, const CsrDev &A, const TileRP *tiles, int64_t n_tiles,
                              int tile_items, int nontemporal, int xcd_remap, int kt, int k,
                              const void *B, int64_t ldb, void *C, int64_t ldc, hipStream_t s);
 
@@ -93,6 +101,25 @@ int64_t scan_tmp_elems(int64_t n);
 hipError_t split_fill(int prec, const int32_t *row_ptr, const int32_t *col, const void *val,
                       int64_t n_rows, int32_t h, const int32_t *work, int64_t nnz_nl, int64_t R,
                       const SplitOut &out, hipStream_t s);
+
+// ---- diagonal panels (split.hip) ------------------------------------------------
+// Entries are grouped by their offset d = col - row into K <= PANEL_MAX equal
+// slices of [dmin, dmin + span); each panel is a CRS over all rows.
+constexpr int PANEL_MAX = 8;
+struct PanelOut {
+  int32_t *col[PANEL_MAX];
+  void *val[PANEL_MAX];
+};
+// dev2: two int64 of device scratch.  Sets dmin / dmax of the part's offsets.
+hipError_t panel_d_range(const int32_t *row_ptr, const int32_t *col, int64_t n_rows, int64_t *dev2,
+                         int64_t *dmin, int64_t *dmax, hipStream_t s);
+// counts: K * (n_rows + 1) int32; on return panel k's row_ptr is
+// counts + k * (n_rows + 1).
+hipError_t panel_count(const int32_t *row_ptr, const int32_t *col, int64_t n_rows, int64_t dmin,
+                       int64_t span, int K, int32_t *counts, int32_t *scan_tmp, hipStream_t s);
+hipError_t panel_fill(int prec, const int32_t *row_ptr, const int32_t *col, const void *val,
+                      int64_t n_rows, int64_t dmin, int64_t span, int K, const int32_t *starts,
+                      const PanelOut &out, hipStream_t s);
 
 // ---- probes (probes.hip) -------------------------------------------------------
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t s);

@@ -81,7 +81,8 @@ class SpmvError(RuntimeError):
 
 class spmv_plan_t(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int32) for n in
-                ("kernel", "tile_items", "lanes", "nontemporal", "xcd_remap", "block_kt")]
+                ("kernel", "tile_items", "lanes", "nontemporal", "xcd_remap", "block_kt",
+                 "tiles_per_group", "panels")]
 
 
 class spmv_info_t(ctypes.Structure):

@@ -36,6 +36,11 @@ def mats():
 
 PLANS = ([dict(kernel=1, tile_items=e, nontemporal=nt, xcd_remap=rm)
           for e in (4, 8, 16) for nt in (0, 1) for rm in (0, 1)] +
+         [dict(kernel=1, tile_items=e, tiles_per_group=tpw)
+          for e in (4, 8, 16) for tpw in (2, 7, 32)] +
+         [dict(kernel=1, tile_items=e, panels=k, xcd_remap=rm)
+          for e in (4, 8) for k in (2, 4, 8) for rm in (0, 1)] +
+         [dict(kernel=1, tile_items=8, panels=4, tiles_per_group=4)] +
          [dict(kernel=2, lanes=l) for l in (2, 4, 8, 16, 32, 64)])
 
 
@@ -85,6 +90,9 @@ def _long_row_matrix(long_len, n_short=300, n_cols=20000, seed=3):
 
 @pytest.mark.parametrize("long_len", [1023, 1024, 1025, 2048, 2049, 4096, 4097, 50_000])
 @pytest.mark.parametrize("plan", [dict(kernel=1, tile_items=e) for e in (4, 8, 16)] +
+                         [dict(kernel=1, tile_items=e, tiles_per_group=t) for e in (4, 8)
+                          for t in (3, 16)] +
+                         [dict(kernel=1, tile_items=8, panels=k) for k in (2, 8)] +
                          [dict(kernel=2, lanes=64)], ids=_pid)
 def test_long_rows(long_len, plan):
     A = _long_row_matrix(long_len)
@@ -111,6 +119,14 @@ def test_edge_shapes():
         c0 = gen.uniform_vector(m, rng)
         ref, den = oracle_ref(A, x, c0)
         assert_close(gpu_spmv(A, x, c0), ref, den, FP64_TOL, f"{m}x{n}")
+    # diagonal panels on rectangular shapes and an empty matrix
+    for (m, n) in ((1000, 3000), (3000, 10), (0, 5)):
+        A = gen.random_crs(m, n, rng, max_len=12)
+        x = gen.uniform_vector(n, rng)
+        c0 = gen.uniform_vector(m, rng)
+        ref, den = oracle_ref(A, x, c0)
+        for k in (2, 8):
+            assert_close(gpu_spmv(A, x, c0, plan=dict(panels=k)), ref, den, FP64_TOL, f"{m}x{n} panels")
     # 1-based input gives the same product
     A = gen.random_crs(2000, 2000, rng, max_len=20)
     x = gen.uniform_vector(2000, rng)
@@ -268,6 +284,49 @@ def test_split_run_matches_oracle(schedule):
     assert_close(got, ref, den, FP64_TOL, "split vs unsplit oracle")
     parts = oracle.split(A.row_ptr, A.col_idx, A.val, h_begin)
     assert_close(got, oracle.spmv_split(parts, x, c0), den, FP64_TOL, "split vs split oracle")
+
+
+def test_split_local_part_panels():
+    import torch
+
+    A, x = mats()["irregular"]
+    h_begin = gen.halo_begin(A.n_cols)
+    a, s = _split_handles(A, h_begin)
+    try:
+        spmv.spmv_set_plan(s, spmv.SPMV_PART_MAIN, panels=4)
+        with pytest.raises(spmv.SpmvError) as ei:
+            spmv.spmv_set_plan(s, spmv.SPMV_PART_NONLOCAL, panels=2)
+        assert ei.value.status == spmv.SPMV_ERR_UNSUPPORTED
+        B = to_dev(x, "f64")
+        C = to_dev(np.zeros(A.n_rows), "f64")
+        spmv.spmv_run(s, B, C)
+        torch.cuda.synchronize()
+        ref, den = oracle_ref(A, x)
+        assert_close(C.cpu().numpy(), ref, den, FP64_TOL, "split with local panels")
+    finally:
+        spmv.spmv_destroy(s)
+        spmv.spmv_destroy(a)
+
+
+@pytest.mark.parametrize("tpw", [1, 4, 32])
+def test_split_pipelined_plans(tpw):
+    import torch
+
+    A, x = mats()["irregular"]
+    h_begin = gen.halo_begin(A.n_cols)
+    a, s = _split_handles(A, h_begin)
+    try:
+        spmv.spmv_set_plan(s, spmv.SPMV_PART_MAIN, tiles_per_group=tpw, tile_items=8)
+        spmv.spmv_set_plan(s, spmv.SPMV_PART_NONLOCAL, tiles_per_group=tpw, tile_items=4)
+        B = to_dev(x, "f64")
+        C = to_dev(np.zeros(A.n_rows), "f64")
+        spmv.spmv_run(s, B, C)
+        torch.cuda.synchronize()
+        ref, den = oracle_ref(A, x)
+        assert_close(C.cpu().numpy(), ref, den, FP64_TOL, f"split tpw={tpw}")
+    finally:
+        spmv.spmv_destroy(s)
+        spmv.spmv_destroy(a)
 
 
 def test_split_integer_bit_exact_and_edges():
@@ -558,7 +617,8 @@ def test_set_plan_validation():
     A, _ = mats()["irregular"]
     h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, flags=NOTUNE)
     try:
-        for bad in (dict(kernel=3), dict(tile_items=5), dict(lanes=3), dict(block_kt=2)):
+        for bad in (dict(kernel=3), dict(tile_items=5), dict(lanes=3), dict(block_kt=2),
+                    dict(tiles_per_group=0), dict(tiles_per_group=65), dict(panels=3)):
             with pytest.raises(spmv.SpmvError):
                 spmv.spmv_set_plan(h, **bad)
         with pytest.raises(spmv.SpmvError):
