@@ -40,7 +40,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 PROFILES = os.path.join(ROOT, "profiles")
-TRAFFIC_FILE = os.path.join(PROFILES, "traffic_csr_stream_27pt160_f64.json")
+TRAFFIC_FILE = os.path.join(PROFILES, "traffic_csr_stream_27pt160_f64.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1106_5908_amd", "csrc", "kernels.hip")
 
 VAL_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f32f64": 4}
@@ -240,13 +240,17 @@ def measure_bandwidth(steps=20):
     a = torch.empty(n, dtype=torch.float64, device="cuda")
     b = torch.rand(n, dtype=torch.float64, device="cuda")
     c = torch.rand(n, dtype=torch.float64, device="cuda")
+    sums = torch.empty(spmv.read_sums_needed(n), dtype=torch.float64, device="cuda")
     tc = time_launches(lambda: spmv.spmv_probe_copy(a, b), steps, 3)
     tt = time_launches(lambda: spmv.spmv_probe_triad(a, b, c, 3.0), steps, 3)
+    tr = time_launches(lambda: spmv.spmv_probe_read(b, sums), steps, 3)
     out = {"copy_GBs": 2 * 8 * n / (tc["p50_ms"] * 1e6), "triad_GBs": 3 * 8 * n / (tt["p50_ms"] * 1e6),
-           "copy_bytes": 2 * 8 * n, "copy_ms": tc["p50_ms"]}
-    del a, b, c
+           "read_GBs": 8 * n / (tr["p50_ms"] * 1e6), "copy_bytes": 2 * 8 * n, "copy_ms": tc["p50_ms"],
+           "array_doubles": n}
+    del a, b, c, sums
     torch.cuda.empty_cache()
-    log(f"bandwidth probes: copy {out['copy_GBs']:.0f} GB/s, triad {out['triad_GBs']:.0f} GB/s")
+    log(f"bandwidth probes: copy {out['copy_GBs']:.0f} GB/s, triad {out['triad_GBs']:.0f} GB/s, "
+        f"read {out['read_GBs']:.0f} GB/s")
     return out
 
 
@@ -510,7 +514,7 @@ def summarize_pmc(fetch_dir, write_dir, out_path, plan_json):
             if r.get("Counter_Name") != counter:
                 continue
             name = r["Kernel_Name"]
-            key = "spmv" if "k_stream" in name or "k_vector" in name else (
+            key = "spmv" if "spmv::" in name and ("k_stream" in name or "k_vector" in name) else (
                 "copy" if "k_copy" in name else None)
             if key is None:
                 continue
@@ -536,10 +540,40 @@ def summarize_pmc(fetch_dir, write_dir, out_path, plan_json):
         "fetch_scale": f_fac, "write_scale": w_fac,
         "traffic_bytes": fetch_b + write_b,
         "algorithmic_bytes": algorithmic_bytes(4096000, 4096000, 109215352, "f64"),
+        "commands": [
+            "rocprofv3 --pmc FETCH_SIZE -d <fetch_dir> -o p --output-format csv -- "
+            "python3 bench.py --pmc-pass --steps 10 --plan '<plan>'",
+            "rocprofv3 --pmc WRITE_SIZE -d <write_dir> -o p --output-format csv -- "
+            "python3 bench.py --pmc-pass --steps 10 --plan '<plan>'",
+            "python3 bench.py --summarize-pmc <fetch_dir> <write_dir> <this file> '<plan>'",
+        ],
+        "scale_note": "counter KiB per dispatch x 1024 x (known bytes of the 2^27-double copy "
+                      "/ the same counter's reading for that copy)",
     }
     with open(out_path, "w") as f:
         json.dump(res, f, indent=1)
     print(json.dumps(res))
+
+
+def summarize_stats(stats_csv, out_path, command, kernel_filter=""):
+    """Short text summary of a rocprofv3 --stats kernel table."""
+    import csv
+
+    rows = list(csv.DictReader(open(stats_csv)))
+    rows.sort(key=lambda r: -float(r["TotalDurationNs"]))
+    lines = [f"# rocprofv3 kernel statistics", f"# command: {command}",
+             f"# {'calls':>6} {'avg_us':>10} {'min_us':>10} {'max_us':>10} {'total_%':>8}  kernel"]
+    for r in rows:
+        name = r["Name"]
+        if kernel_filter and kernel_filter not in name and "spmv" not in name:
+            continue
+        if len(name) > 110:
+            name = name[:107] + "..."
+        lines.append(f"  {int(r['Calls']):6d} {float(r['AverageNs'])/1e3:10.1f} {float(r['MinNs'])/1e3:10.1f} "
+                     f"{float(r['MaxNs'])/1e3:10.1f} {float(r['Percentage']):8.2f}  {name}")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
 
 
 # ----------------------------------------------------------------------------
@@ -556,10 +590,14 @@ def main():
     ap.add_argument("--pmc-pass", action="store_true")
     ap.add_argument("--plan", default=None, help="plan (JSON) for --pmc-pass")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "OUT", "PLAN_JSON"))
+    ap.add_argument("--summarize-stats", nargs=3, metavar=("STATS_CSV", "OUT", "COMMAND"))
     args = ap.parse_args()
 
     if args.summarize_pmc:
         summarize_pmc(*args.summarize_pmc)
+        return 0
+    if args.summarize_stats:
+        summarize_stats(*args.summarize_stats)
         return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X and has no "
@@ -594,6 +632,7 @@ def main():
     paths = {"bandwidth_probes": bw,
              "headline_detail": {**head, "frac_of_copy_bw": achieved / bw["copy_GBs"],
                                  "frac_of_triad_bw": achieved / bw["triad_GBs"],
+                                 "frac_of_read_bw": achieved / bw["read_GBs"],
                                  "model_balance_B_per_flop": mb / flops,
                                  "paper_eq1_balance": code_balance(A2.nnz / A2.n_rows)}}
     if traffic:

@@ -277,16 +277,23 @@ spmv_status_t spmv_export(spmv_handle_t h, int32_t which, void *dst, int64_t byt
                           int64_t *size_bytes);
 
 /* ---------------------------------------------------------------------------
- * Measurement probes (the GPU stand-ins for the STREAM benchmark of Sect. 2
+ * Measurement probes (the GPU stand-ins for the STREAM benchmark of Sect. 2;
+ * buffers must be 16-byte aligned
  * and the asynchrony test of Listing 2 / Sect. 3.1).
  *   spmv_probe_copy   dst[i] = src[i] for n doubles
  *   spmv_probe_triad  a[i] = b[i] + s * c[i] for n doubles
+ *   spmv_probe_read   reads n doubles (n even contributes all of them; an odd
+ *                     last one is skipped) and writes one partial sum per
+ *                     workgroup to sums[0 .. (n/2 + 1023)/1024]; sums_len is
+ *                     the capacity of sums in doubles
  *   spmv_probe_spin   one wavefront waits `nanoseconds` on the GPU's constant-rate
  *                     clock without touching memory (at most 10 s)
  * ------------------------------------------------------------------------- */
 spmv_status_t spmv_probe_copy(double *dst, const double *src, int64_t n, void *stream);
 spmv_status_t spmv_probe_triad(double *a, const double *b, const double *c, double s,
                                int64_t n, void *stream);
+spmv_status_t spmv_probe_read(const double *src, int64_t n, double *sums, int64_t sums_len,
+                              void *stream);
 spmv_status_t spmv_probe_spin(int64_t nanoseconds, void *stream);
 
 /* Schedule used by spmv_run (for measurement and for callers that need it).

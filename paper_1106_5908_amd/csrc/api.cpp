@@ -200,10 +200,10 @@ RowStats row_stats(const int32_t *rp, int64_t n) {
 }
 
 // Greedy tiles of consecutive rows holding at most `tile` entries and at
-// most `tile` rows; a row longer than `tile` gets a tile of its own.  (Tiles
-// of more than 256 rows are reduced one row per lane in a loop.)
+// most 512 rows (two per lane of the workgroup, whose bounds the kernel
+// prefetches); a row longer than `tile` gets a tile of its own.
 std::vector<int32_t> make_tiles(const int32_t *rp, int64_t n, int64_t tile) {
-  const int64_t kMaxRows = tile;
+  constexpr int64_t kMaxRows = 2 * kWG;
   std::vector<int32_t> t;
   t.reserve(size_t(n / std::max<int64_t>(1, std::min(tile / 16, kMaxRows)) + 2));
   t.push_back(0);
@@ -1211,14 +1211,20 @@ void tune_part(spmv_handle_s *h, Part &p, const char *name, void *x, void *y, hi
     const std::vector<spmv_plan_t> pc = panel_candidates();
     cands.insert(cands.end(), pc.begin(), pc.end());
   }
+  std::vector<float> times;
   for (const spmv_plan_t &c : cands) {
     p.plan = c;
-    const float ms = tm.median_ms([&] { run_part(h, p, x, y, s); }, s);
-    if (ms < best) {
-      best = ms;
-      best_p = c;
-    }
+    times.push_back(tm.median_ms([&] { run_part(h, p, x, y, s); }, s));
+    best = std::min(best, times.back());
   }
+  // the earliest candidate within 1% of the fastest: near-ties resolve the
+  // same way from run to run
+  for (size_t i = 0; i < cands.size(); ++i)
+    if (times[i] <= best * 1.01f) {
+      best_p = cands[i];
+      best = times[i];
+      break;
+    }
   best_p.block_kt = 0;
   p.plan = best_p;
   (void)p.tiles_for(p.plan.tile_items);
@@ -1432,6 +1438,18 @@ extern "C" spmv_status_t spmv_probe_triad(double *a, const double *b, const doub
          reinterpret_cast<uintptr_t>(c)) % 16)
       fail(SPMV_ERR_INVALID_ARG, "triad buffers must be 16-byte aligned");
     hip_ok(launch_triad(a, b, c, s, n, static_cast<hipStream_t>(stream)), "triad launch");
+  });
+}
+
+extern "C" spmv_status_t spmv_probe_read(const double *src, int64_t n, double *sums,
+                                         int64_t sums_len, void *stream) {
+  return guarded([&] {
+    if (n < 0 || ((!src || !sums) && n > 1)) fail(SPMV_ERR_INVALID_ARG, "bad read arguments");
+    if (sums_len < read_sums_needed(n))
+      fail(SPMV_ERR_INVALID_ARG, "sums must hold " + std::to_string(read_sums_needed(n)) + " values");
+    if (reinterpret_cast<uintptr_t>(src) % 16)
+      fail(SPMV_ERR_INVALID_ARG, "read buffer must be 16-byte aligned");
+    hip_ok(launch_read(src, n, sums, static_cast<hipStream_t>(stream)), "read launch");
   });
 }
 

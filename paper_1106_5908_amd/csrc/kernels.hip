@@ -119,34 +119,56 @@ __device__ void long_row(const int32_t *__restrict__ col, const typename Ty<P>::
   lds_barrier();
 }
 
-// Where a lane's row sum goes in phase 2 (see tile_reduce).
+// Where a lane's row sums go in phase 2 (see tile_reduce).  A tile of at
+// most 256 rows gives each row L lanes (a power of two, at most 64); a tile
+// of 257..512 rows gives each lane the rows tid and tid + 256 (L = 1).  More
+// rows per tile are handled by a loop (the planner does not produce them).
 template <class X>
 struct RowSlot {
-  int L, lane, a, b;
-  int64_t o;
-  X c_old;
+  int L, lane;
+  int a0, b0, a1, b1;
+  int64_t o0, o1;
+  X c0, c1;
 };
 
-// Phase-2 assignment of a tile with at most 256 rows: L lanes per row (a
-// power of two, at most 64).  Row bounds and the old C value are loaded here,
-// early and without branches (lanes past the last row take the last row and
-// are masked at the write), so their latency hides under phase 1.  C rows of
-// a tile are written by this workgroup only.  Lanes with b <= a write nothing.
+// Row bounds and old C values are loaded here, early and without branches
+// (lanes past the last row take the last row with an empty range), so their
+// latency hides under phase 1.  C rows of a tile are written by this
+// workgroup only.
 template <class X, bool IND>
 __device__ __forceinline__ RowSlot<X> row_slot(const int32_t *__restrict__ rp,
                                                const int32_t *__restrict__ row_ids, int r0,
                                                int nrows, int p0, const X *__restrict__ y) {
   RowSlot<X> s;
-  s.L = min(floor_pow2(max(WG / max(nrows, 1), 1)), 64);
-  const int lg = __builtin_ctz(s.L);
-  const int row = (int)threadIdx.x >> lg;
-  const int rc = min(row, max(nrows, 1) - 1);
-  s.lane = (int)threadIdx.x & (s.L - 1);
-  s.a = rp[r0 + rc] - p0;
-  s.b = rp[r0 + rc + (row < nrows ? 1 : 0)] - p0;  // a lane past the last row gets b == a
-  if constexpr (IND) s.o = row_ids[r0 + rc];
-  else s.o = (int64_t)(r0 + rc);
-  s.c_old = y[s.o];
+  const int nr = max(nrows, 1);
+  const int tid = (int)threadIdx.x;
+  int row0, row1;
+  if (nr <= WG) {
+    s.L = min(floor_pow2(WG / nr), 64);
+    const int lg = __builtin_ctz(s.L);
+    row0 = tid >> lg;
+    s.lane = tid & (s.L - 1);
+    row1 = nr;  // none
+  } else {
+    s.L = 1;
+    s.lane = 0;
+    row0 = tid;
+    row1 = tid + WG;
+  }
+  const int rc0 = min(row0, nr - 1), rc1 = min(row1, nr - 1);
+  s.a0 = rp[r0 + rc0] - p0;
+  s.b0 = rp[r0 + rc0 + (row0 < nrows ? 1 : 0)] - p0;
+  s.a1 = rp[r0 + rc1] - p0;
+  s.b1 = rp[r0 + rc1 + (row1 < nrows ? 1 : 0)] - p0;
+  if constexpr (IND) {
+    s.o0 = row_ids[r0 + rc0];
+    s.o1 = row_ids[r0 + rc1];
+  } else {
+    s.o0 = (int64_t)(r0 + rc0);
+    s.o1 = (int64_t)(r0 + rc1);
+  }
+  s.c0 = y[s.o0];
+  s.c1 = y[s.o1];
   return s;
 }
 
@@ -156,11 +178,16 @@ __device__ __forceinline__ void tile_reduce(const int32_t *__restrict__ rp,
                                             const int32_t *__restrict__ row_ids, int r0, int nrows,
                                             int p0, const RowSlot<X> &s, X *__restrict__ y,
                                             const X *s_prod) {
-  if (nrows <= WG) {
+  if (nrows <= 2 * WG) {
     X acc = neg_zero<X>();
-    for (int j = s.a + s.lane; j < s.b; j += s.L) acc += s_prod[j];
+    for (int j = s.a0 + s.lane; j < s.b0; j += s.L) acc += s_prod[j];
     for (int off = s.L >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
-    if (s.lane == 0 && s.b > s.a) y[s.o] = s.c_old + acc;
+    if (s.lane == 0 && s.b0 > s.a0) y[s.o0] = s.c0 + acc;
+    if (nrows > WG) {
+      X acc1 = neg_zero<X>();
+      for (int j = s.a1; j < s.b1; ++j) acc1 += s_prod[j];
+      if (s.b1 > s.a1) y[s.o1] = s.c1 + acc1;
+    }
   } else {
     for (int rr = (int)threadIdx.x; rr < nrows; rr += WG) {
       const int ra = rp[r0 + rr] - p0;
@@ -195,8 +222,7 @@ __device__ __forceinline__ void stream_tile(const int32_t *__restrict__ rp,
     long_row<P, NT>(col, val, p0, p0 + nnz, row_ids ? row_ids[r0] : r0, x, y, s_prod);
     return;
   }
-  RowSlot<X> slot{};
-  if (nrows <= WG) slot = row_slot<X, false>(rp, row_ids, r0, nrows, p0, y);
+  const RowSlot<X> slot = row_slot<X, false>(rp, row_ids, r0, nrows, p0, y);
   if (nnz > 0) {
     int c[E];
     V v[E];
@@ -524,25 +550,34 @@ __global__ void k_batch_reset(int32_t *counter) {
   if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
 }
 
-// Persistent grid: each workgroup takes the next tile from the counter
-// until the queue is empty; every workgroup reaches the exit test.
+// Persistent grid: each workgroup claims `chunk` consecutive tiles at a
+// time from the counter; the claim for the next chunk is issued before the
+// current chunk is processed and only read after it, so the atomic's round
+// trip overlaps with work.  Every workgroup reaches the exit test.
 template <int P, int E, bool NT>
 __global__ __launch_bounds__(WG) void k_batch_persistent(const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ col,
                                                          const void *val, const BatchDesc *desc,
                                                          const BatchTile *tiles, int64_t n_tiles,
-                                                         int32_t *counter, const void *xv,
-                                                         void *yv) {
+                                                         int32_t *counter, int chunk,
+                                                         const void *xv, void *yv) {
   using X = typename Ty<P>::X;
   __shared__ X s_prod[WG * E];
   __shared__ int32_t s_t;
-  for (;;) {
-    if (threadIdx.x == 0) s_t = atomicAdd(counter, 1);
+  if (threadIdx.x == 0) s_t = atomicAdd(counter, chunk);
+  __syncthreads();
+  int32_t t0 = s_t;
+  while (t0 < n_tiles) {
+    int32_t next = 0;
+    if (threadIdx.x == 0) next = atomicAdd(counter, chunk);
+    const int32_t t1 = (int32_t)min((int64_t)t0 + chunk, n_tiles);
+    for (int32_t t = t0; t < t1; ++t) {
+      const BatchTile T = tiles[t];
+      batch_tile<P, E, NT>(rp, col, val, desc, T, xv, yv, s_prod);
+    }
+    if (threadIdx.x == 0) s_t = next;
     __syncthreads();
-    const int32_t t = s_t;
-    if (t >= n_tiles) break;
-    const BatchTile T = tiles[t];
-    batch_tile<P, E, NT>(rp, col, val, desc, T, xv, yv, s_prod);
+    t0 = s_t;
     __syncthreads();
   }
 }
@@ -678,12 +713,15 @@ template <int P, int E>
 hipError_t run_persistent(const int32_t *rp, const int32_t *col, const void *val,
                           const BatchDesc *desc, const BatchTile *tiles, int64_t n_tiles, int nt,
                           int32_t *counter, int grid, const void *x, void *y, hipStream_t s) {
+  // about eight claims per workgroup, at most 16 tiles per claim
+  int64_t chunk = n_tiles / ((int64_t)grid * 8);
+  chunk = chunk < 1 ? 1 : (chunk > 16 ? 16 : chunk);
   if (nt)
     hipLaunchKernelGGL((k_batch_persistent<P, E, true>), dim3(grid), dim3(WG), 0, s, rp, col, val,
-                       desc, tiles, n_tiles, counter, x, y);
+                       desc, tiles, n_tiles, counter, (int)chunk, x, y);
   else
     hipLaunchKernelGGL((k_batch_persistent<P, E, false>), dim3(grid), dim3(WG), 0, s, rp, col, val,
-                       desc, tiles, n_tiles, counter, x, y);
+                       desc, tiles, n_tiles, counter, (int)chunk, x, y);
   return hipGetLastError();
 }
 

@@ -1,5 +1,5 @@
 // Measurement probes.
-//   copy / triad: the bandwidth ceiling the spMV is compared with, in the
+//   copy / triad / read: the bandwidth ceilings the spMV is compared with, in the
 //     role the STREAM triad plays in Sect. 2 of Schubert, Fehske, Hager,
 //     Wellein 2011 (GPU stores do not write-allocate, so no 4/3 scaling);
 //   spin: a workgroup that stays busy for a given time without touching
@@ -14,42 +14,68 @@ namespace spmv {
 namespace {
 
 constexpr int WG = 256;
-constexpr int PER = 4;  // double2 per thread
+constexpr int PER = 4;  // 16-byte elements per thread
 
-__global__ __launch_bounds__(WG) void k_copy(double2 *__restrict__ dst,
-                                             const double2 *__restrict__ src, int64_t n2) {
+typedef double dv2 __attribute__((ext_vector_type(2)));
+
+// Copy and triad use nontemporal loads and stores (the fastest of the
+// variants measured on MI355X), four 16-byte elements per thread.
+__global__ __launch_bounds__(WG) void k_copy(dv2 *__restrict__ dst, const dv2 *__restrict__ src,
+                                             int64_t n2) {
   const int64_t base = ((int64_t)blockIdx.x * WG * PER) + threadIdx.x;
-  double2 v[PER];
+  dv2 v[PER];
 #pragma unroll
   for (int e = 0; e < PER; ++e) {
     const int64_t i = base + (int64_t)e * WG;
-    if (i < n2) v[e] = src[i];
+    if (i < n2) v[e] = __builtin_nontemporal_load(src + i);
   }
 #pragma unroll
   for (int e = 0; e < PER; ++e) {
     const int64_t i = base + (int64_t)e * WG;
-    if (i < n2) dst[i] = v[e];
+    if (i < n2) __builtin_nontemporal_store(v[e], dst + i);
   }
 }
 
-__global__ __launch_bounds__(WG) void k_triad(double2 *__restrict__ a,
-                                              const double2 *__restrict__ b,
-                                              const double2 *__restrict__ c, double s, int64_t n2) {
+__global__ __launch_bounds__(WG) void k_triad(dv2 *__restrict__ a, const dv2 *__restrict__ b,
+                                              const dv2 *__restrict__ c, double s, int64_t n2) {
   const int64_t base = ((int64_t)blockIdx.x * WG * PER) + threadIdx.x;
-  double2 vb[PER], vc[PER];
+  dv2 vb[PER], vc[PER];
 #pragma unroll
   for (int e = 0; e < PER; ++e) {
     const int64_t i = base + (int64_t)e * WG;
     if (i < n2) {
-      vb[e] = b[i];
-      vc[e] = c[i];
+      vb[e] = __builtin_nontemporal_load(b + i);
+      vc[e] = __builtin_nontemporal_load(c + i);
     }
   }
 #pragma unroll
   for (int e = 0; e < PER; ++e) {
     const int64_t i = base + (int64_t)e * WG;
-    if (i < n2) a[i] = make_double2(vb[e].x + s * vc[e].x, vb[e].y + s * vc[e].y);
+    if (i < n2) __builtin_nontemporal_store(vb[e] + s * vc[e], a + i);
   }
+}
+
+// Read-only stream: sums the input; one value per workgroup is written.
+__global__ __launch_bounds__(WG) void k_read(const dv2 *__restrict__ src, int64_t n2,
+                                             double *__restrict__ sums) {
+  __shared__ double s_red[WG];
+  const int64_t base = ((int64_t)blockIdx.x * WG * PER) + threadIdx.x;
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < PER; ++e) {
+    const int64_t i = base + (int64_t)e * WG;
+    if (i < n2) {
+      const dv2 v = __builtin_nontemporal_load(src + i);
+      acc += v.x + v.y;
+    }
+  }
+  s_red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = WG / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s_red[threadIdx.x] += s_red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = s_red[0];
 }
 
 // Scalar tail for odd n (element n-1).
@@ -74,8 +100,8 @@ hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t s)
   const int64_t n2 = n / 2;
   if (n2 > 0) {
     const int64_t nb = (n2 + WG * PER - 1) / (WG * PER);
-    hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(WG), 0, s,
-                       reinterpret_cast<double2 *>(dst), reinterpret_cast<const double2 *>(src), n2);
+    hipLaunchKernelGGL(k_copy, dim3((unsigned)nb), dim3(WG), 0, s, reinterpret_cast<dv2 *>(dst),
+                       reinterpret_cast<const dv2 *>(src), n2);
   }
   if (n % 2) hipLaunchKernelGGL(k_copy_tail, dim3(1), dim3(64), 0, s, dst, src, n - 1);
   return hipGetLastError();
@@ -86,11 +112,22 @@ hipError_t launch_triad(double *a, const double *b, const double *c, double sc, 
   const int64_t n2 = n / 2;
   if (n2 > 0) {
     const int64_t nb = (n2 + WG * PER - 1) / (WG * PER);
-    hipLaunchKernelGGL(k_triad, dim3((unsigned)nb), dim3(WG), 0, s, reinterpret_cast<double2 *>(a),
-                       reinterpret_cast<const double2 *>(b), reinterpret_cast<const double2 *>(c),
-                       sc, n2);
+    hipLaunchKernelGGL(k_triad, dim3((unsigned)nb), dim3(WG), 0, s, reinterpret_cast<dv2 *>(a),
+                       reinterpret_cast<const dv2 *>(b), reinterpret_cast<const dv2 *>(c), sc, n2);
   }
   if (n % 2) hipLaunchKernelGGL(k_triad_tail, dim3(1), dim3(64), 0, s, a, b, c, sc, n - 1);
+  return hipGetLastError();
+}
+
+int64_t read_sums_needed(int64_t n) { return (n / 2 + WG * PER - 1) / (WG * PER) + 1; }
+
+hipError_t launch_read(const double *src, int64_t n, double *sums, hipStream_t s) {
+  const int64_t n2 = n / 2;
+  if (n2 > 0) {
+    const int64_t nb = (n2 + WG * PER - 1) / (WG * PER);
+    hipLaunchKernelGGL(k_read, dim3((unsigned)nb), dim3(WG), 0, s,
+                       reinterpret_cast<const dv2 *>(src), n2, sums);
+  }
   return hipGetLastError();
 }
 

@@ -125,6 +125,9 @@ hipError_t panel_fill(int prec, const int32_t *row_ptr, const int32_t *col, cons
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t s);
 hipError_t launch_triad(double *a, const double *b, const double *c, double sc, int64_t n,
                         hipStream_t s);
-hipError_t launch_spin(int64_t cycles, hipStream_t s);
+hipError_t launch_spin(int64_t nanoseconds, hipStream_t s);
+// sums must hold read_sums_needed(n) doubles
+int64_t read_sums_needed(int64_t n);
+hipError_t launch_read(const double *src, int64_t n, double *sums, hipStream_t s);
 
 }  // namespace spmv

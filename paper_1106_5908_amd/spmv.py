@@ -68,7 +68,7 @@ EXPORTED = [
     "spmv_create_crs", "spmv_split_local_nonlocal", "spmv_run", "spmv_run_block",
     "spmv_destroy", "spmv_last_error", "spmv_create_batch", "spmv_get_plan",
     "spmv_set_plan", "spmv_tune", "spmv_get_info", "spmv_export", "spmv_probe_copy",
-    "spmv_probe_triad", "spmv_probe_spin", "spmv_set_schedule",
+    "spmv_probe_triad", "spmv_probe_read", "spmv_probe_spin", "spmv_set_schedule",
 ]
 
 
@@ -126,6 +126,7 @@ def load():
         "spmv_probe_copy": [_vp, _vp, _i64, _vp],
         "spmv_probe_triad": [_vp, _vp, _vp, ctypes.c_double, _i64, _vp],
         "spmv_probe_spin": [_i64, _vp],
+        "spmv_probe_read": [_vp, _i64, _vp, _i64, _vp],
         "spmv_set_schedule": [_vp, _i32],
     }
     for name, args in sig.items():
@@ -374,6 +375,16 @@ def spmv_probe_triad(a, b, c, s: float, stream=None) -> None:
         raise ValueError("triad operands differ in length")
     _check(load().spmv_probe_triad(_dev(a, "float64", "a"), _dev(b, "float64", "b"),
                                    _dev(c, "float64", "c"), s, a.numel(), _stream(stream)))
+
+
+def spmv_probe_read(src, sums, stream=None) -> None:
+    """Read-only stream over src (float64); per-workgroup sums into sums."""
+    _check(load().spmv_probe_read(_dev(src, "float64", "src"), src.numel(),
+                                  _dev(sums, "float64", "sums"), sums.numel(), _stream(stream)))
+
+
+def read_sums_needed(n: int) -> int:
+    return (n // 2 + 1023) // 1024 + 1
 
 
 def spmv_probe_spin(nanoseconds: int, stream=None) -> None:

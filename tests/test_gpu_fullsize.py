@@ -1,0 +1,159 @@
+"""Parity at the benchmark sizes, in the launch configuration the benchmark
+times (plans picked by the autotuner): every output entry is compared with
+the oracle, except for the block products, where 2000 sampled rows are
+recomputed one by one."""
+from __future__ import annotations
+
+import numpy as np
+import pytest
+
+import oracle
+from gpu_util import FP64_TOL, assert_close, prec_bounds, rounded_inputs, to_dev
+from paper_1106_5908_amd import spmv
+from workloads import gen
+
+pytestmark = pytest.mark.gpu
+
+NOTUNE = spmv.SPMV_FLAG_NO_TUNE_CACHE
+
+
+@pytest.fixture(scope="module")
+def c2():
+    A, x = gen.workload_c2()
+    ref = oracle.spmv(A.row_ptr, A.col_idx, A.val, x)
+    den = oracle.abs_spmv(A.row_ptr, A.col_idx, A.val, x)
+    return A, x, ref, den
+
+
+@pytest.fixture(scope="module")
+def c3():
+    A, x = gen.workload_c3()
+    ref = oracle.spmv(A.row_ptr, A.col_idx, A.val, x)
+    den = oracle.abs_spmv(A.row_ptr, A.col_idx, A.val, x)
+    return A, x, ref, den
+
+
+def _tuned_run(A, x, prec="f64", runs=1):
+    import torch
+
+    h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, prec=prec, flags=NOTUNE)
+    try:
+        spmv.spmv_tune(h, 1)
+        plan = spmv.spmv_get_plan(h)
+        B = to_dev(x, prec)
+        C = torch.zeros(A.n_rows, dtype=B.dtype, device="cuda")
+        for _ in range(runs):
+            spmv.spmv_run(h, B, C)
+        torch.cuda.synchronize()
+        return C.cpu().numpy().astype(np.float64), plan
+    finally:
+        spmv.spmv_destroy(h)
+
+
+def test_27pt160_fp64(c2):
+    A, x, ref, den = c2
+    got, plan = _tuned_run(A, x)
+    assert_close(got, ref, den, FP64_TOL, f"27-point 160^3 FP64, plan {plan}")
+
+
+def test_27pt160_integer_bit_exact():
+    A = gen.stencil_27pt_3d(160)
+    x = gen.integer_vector(A.n_cols, gen.rng_for(2, 9), vmax=8)
+    got, _ = _tuned_run(A, x, runs=2)
+    assert np.array_equal(got, 2 * oracle.spmv(A.row_ptr, A.col_idx, A.val, x))
+
+
+def test_irregular8M_fp64(c3):
+    A, x, ref, den = c3
+    got, plan = _tuned_run(A, x)
+    assert_close(got, ref, den, FP64_TOL, f"irregular 8M FP64, plan {plan}")
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16", "f32f64"])
+@pytest.mark.parametrize("which", ["27pt160", "irregular8M"])
+def test_precision_modes_fullsize(prec, which, c2, c3):
+    A, x, ref, den = c2 if which == "27pt160" else c3
+    got, plan = _tuned_run(A, x, prec)
+    b_orig, b_same = prec_bounds(prec, int(np.diff(A.row_ptr).max()))
+    assert_close(got, ref, den, b_orig, f"{which} {prec} vs FP64 oracle, plan {plan}")
+    rows = np.random.default_rng(3).integers(0, A.n_rows, size=20000)
+    v, xr = rounded_inputs(A, x, prec)
+    ref2 = oracle.spmv_rows(rows, A.row_ptr, A.col_idx, v, xr)
+    den2 = oracle.spmv_rows(rows, A.row_ptr, A.col_idx, np.abs(v), np.abs(xr))
+    assert_close(got[rows], ref2, den2, b_same, f"{which} {prec} vs oracle on rounded inputs")
+
+
+def test_irregular8M_split_overlap(c3):
+    import torch
+
+    A, x, ref, den = c3
+    hb = gen.halo_begin(A.n_cols)
+    a = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, flags=NOTUNE)
+    s = spmv.spmv_split_local_nonlocal(a, hb)
+    try:
+        spmv.spmv_tune(s, 1)
+        halo = torch.from_numpy(np.ascontiguousarray(x[hb:])).pin_memory()
+        Bh = x.copy()
+        Bh[hb:] = np.nan
+        B = to_dev(Bh, "f64")
+        C = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+        spmv.spmv_run(s, B, C, halo)
+        torch.cuda.synchronize()
+        assert_close(C.cpu().numpy(), ref, den, FP64_TOL, "split with overlapped halo copy")
+        info = spmv.spmv_get_info(s)
+        parts = oracle.split(A.row_ptr, A.col_idx, A.val, hb)
+        assert info["nnz_nonlocal"] == parts["nl_col"].size
+        assert info["n_nonlocal_rows"] == parts["nl_rows"].size
+    finally:
+        spmv.spmv_destroy(s)
+        spmv.spmv_destroy(a)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32"])
+@pytest.mark.parametrize("k", [4, 8, 16])
+def test_block_irregular8M_sampled(k, prec, c3):
+    import torch
+
+    A, _, _, _ = c3
+    X = gen.block_rhs(A.n_cols, k)
+    h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, prec=prec, flags=NOTUNE)
+    try:
+        spmv.spmv_tune(h, k)
+        dt = torch.float64 if prec == "f64" else torch.float32
+        B = torch.from_numpy(X).to("cuda", dtype=dt)
+        C = torch.zeros((A.n_rows, k), dtype=dt, device="cuda")
+        spmv.spmv_run_block(h, B, C)
+        torch.cuda.synchronize()
+        rows = np.random.default_rng(11).integers(0, A.n_rows, size=2000)
+        got = C[torch.from_numpy(rows).cuda()].cpu().numpy().astype(np.float64)
+    finally:
+        spmv.spmv_destroy(h)
+    b_orig, _ = prec_bounds(prec, int(np.diff(A.row_ptr).max()))
+    for t in range(k):
+        xt = np.ascontiguousarray(X[:, t])
+        ref = oracle.spmv_rows(rows, A.row_ptr, A.col_idx, A.val, xt)
+        den = oracle.spmv_rows(rows, A.row_ptr, A.col_idx, np.abs(A.val), np.abs(xt))
+        assert_close(got[:, t], ref, den, b_orig, f"block k={k} {prec} column {t}")
+
+
+def test_batch_512_stencils():
+    import torch
+
+    mem = gen.workload_c5_batch()
+    h = spmv.spmv_create_batch([(A.row_ptr, A.col_idx, A.val, A.n_cols) for A, _ in mem], flags=NOTUNE)
+    try:
+        spmv.spmv_tune(h, 1)
+        B = to_dev(np.concatenate([x for _, x in mem]), "f64")
+        C = torch.zeros(sum(A.n_rows for A, _ in mem), dtype=torch.float64, device="cuda")
+        spmv.spmv_run(h, B, C)  # HIP-graph replay path
+        torch.cuda.synchronize()
+        got = C.cpu().numpy()
+    finally:
+        spmv.spmv_destroy(h)
+    off = 0
+    for m, (A, x) in enumerate(mem):
+        sl = slice(off, off + A.n_rows)
+        ref = oracle.spmv(A.row_ptr, A.col_idx, A.val, x)
+        den = oracle.abs_spmv(A.row_ptr, A.col_idx, A.val, x)
+        assert_close(got[sl], ref, den, FP64_TOL, f"batch member {m}")
+        off += A.n_rows

@@ -646,6 +646,11 @@ def test_probes():
     torch.cuda.synchronize()
     assert torch.equal(dst, src)
     assert torch.allclose(a, src + 3.0 * c, rtol=0, atol=1e-12)
+    sums = torch.full((spmv.read_sums_needed(n),), float("nan"), dtype=torch.float64, device="cuda")
+    spmv.spmv_probe_read(src, sums)
+    torch.cuda.synchronize()
+    nb = ((n // 2) + 1023) // 1024
+    assert torch.allclose(sums[:nb].sum(), src[: 2 * (n // 2)].sum(), rtol=1e-9)
     t0 = time.perf_counter()
     spmv.spmv_probe_spin(20_000_000)  # 20 ms
     torch.cuda.synchronize()
