@@ -92,10 +92,12 @@ struct DevBuf {
     const int64_t lim = fault_alloc_after();
     if (lim >= 0 && g_alloc_count.fetch_add(1) >= lim)
       fail(SPMV_ERR_ALLOC, std::string(what) + ": allocation failure injected (SPMV_FAULT_ALLOC_AFTER)");
-    // Never zero bytes, so every array has a valid address.
-    const size_t want = std::max<size_t>(n, 256);
+    // Never zero bytes, so every array has a valid address; 64 bytes of tail
+    // padding let paired loads read one entry past the end.
+    const size_t want = std::max<size_t>(n + 64, 256);
     hip_ok(hipMalloc(&p, want), what);
     bytes = n;
+    hip_ok(hipMemset(static_cast<char *>(p) + n, 0, want - n), what);  // padding reads as 0
   }
   template <class T> T *as() const { return static_cast<T *>(p); }
 };
@@ -199,11 +201,13 @@ RowStats row_stats(const int32_t *rp, int64_t n) {
   return s;
 }
 
-// Greedy tiles of consecutive rows holding at most `tile` entries and at
-// most 512 rows (two per lane of the workgroup, whose bounds the kernel
-// prefetches); a row longer than `tile` gets a tile of its own.
-std::vector<int32_t> make_tiles(const int32_t *rp, int64_t n, int64_t tile) {
+// Greedy tiles of consecutive rows holding at most `tile` - 2 entries (room
+// for the kernel's paired loads to start one entry early) and at most 512
+// rows (two per lane of the workgroup, whose bounds the kernel prefetches);
+// a row longer than that gets a tile of its own.
+std::vector<int32_t> make_tiles(const int32_t *rp, int64_t n, int64_t tile_items) {
   constexpr int64_t kMaxRows = 2 * kWG;
+  const int64_t tile = tile_items - 2;
   std::vector<int32_t> t;
   t.reserve(size_t(n / std::max<int64_t>(1, std::min(tile / 16, kMaxRows)) + 2));
   t.push_back(0);

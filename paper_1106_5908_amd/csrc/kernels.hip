@@ -97,6 +97,38 @@ __device__ __forceinline__ void load_cv(const int32_t *__restrict__ col,
   }
 }
 
+// Paired form of load_cv: lane tid takes entry pairs (2k, 2k+1) counted from
+// the even entry base = p0 - off, k = tid, tid + 256, ..., so each load moves
+// two adjacent entries (16 bytes of FP64 values, 8 bytes of indices).  Pairs
+// past the tile are clamped to its last pair.  The first entry of a pair is
+// always a stored entry (index <= p0 + nnz - 1); the second may lie one past
+// the tile -- for the part's last tile, in the arrays' tail padding -- so its
+// column is replaced by the first entry's column and it is never used as a
+// gather index.  Needs nnz + off <= 256 * E.
+template <class V> struct Pair;
+template <> struct Pair<double> { typedef double T __attribute__((ext_vector_type(2))); };
+template <> struct Pair<float> { typedef float T __attribute__((ext_vector_type(2))); };
+template <> struct Pair<uint16_t> { typedef uint16_t T __attribute__((ext_vector_type(2))); };
+typedef int32_t IPair __attribute__((ext_vector_type(2)));
+
+template <int E, bool NT, class V>
+__device__ __forceinline__ void load_cv_pairs(const int32_t *__restrict__ col,
+                                              const V *__restrict__ val, int base, int nnz, int off,
+                                              int (&c)[E], V (&v)[E]) {
+  using PV = typename Pair<V>::T;
+  const int lastp = (nnz + off - 1) >> 1;
+#pragma unroll
+  for (int e = 0; e < E / 2; ++e) {
+    const int k = min(e * WG + (int)threadIdx.x, lastp);
+    const IPair cp = ld<IPair, NT>(reinterpret_cast<const IPair *>(col + base + 2 * k));
+    const PV vp = ld<PV, NT>(reinterpret_cast<const PV *>(val + base + 2 * k));
+    c[2 * e] = cp.x;
+    c[2 * e + 1] = (2 * k + 1 < nnz + off) ? cp.y : cp.x;
+    v[2 * e] = vp.x;
+    v[2 * e + 1] = vp.y;
+  }
+}
+
 // A row longer than a tile (the planner gives it a tile of its own): the
 // workgroup strides through it and reduces in LDS.  Ends with a barrier.
 template <int P, bool NT>
@@ -249,7 +281,9 @@ __device__ __forceinline__ void stream_tile(const int32_t *__restrict__ rp,
 // compiler's wait counts never have to drain the prefetch early.  The kernel
 // is only launched for parts with at least one entry.
 // One tile per workgroup (tiles_per_group == 1): the plain form of the
-// stream kernel, with no prefetch state.
+// stream kernel, with no prefetch state.  Entries are loaded in pairs from
+// the even entry at or below the tile start (see load_cv_pairs); products go
+// to LDS slot (entry - base), so phase 2 reads relative to base.
 template <int P, int E, bool NT, bool IND>
 __global__ __launch_bounds__(WG) void k_stream1(CsrDev A, const TileRP *__restrict__ tiles,
                                                 int64_t n_tiles, int remap, const void *xv,
@@ -265,23 +299,29 @@ __global__ __launch_bounds__(WG) void k_stream1(CsrDev A, const TileRP *__restri
   const TileRP m0 = tiles[t], m1 = tiles[t + 1];
   const int nnz = m1.p - m0.p;
   const int nrows = m1.r - m0.r;
-  if (nnz > TILE) {
+  if (nnz > TILE - 2) {
     long_row<P, NT>(A.col, val, m0.p, m1.p, IND ? (int64_t)A.row_ids[m0.r] : (int64_t)m0.r, x, y,
                     s_prod);
     return;
   }
   if (nnz == 0) return;  // only empty rows: C stays as it is
+  const int off = m0.p & 1;
+  const int base = m0.p - off;
   int c[E];
   V v[E];
-  load_cv<E, NT>(A.col, val, m0.p, nnz, c, v);
-  const RowSlot<X> slot = row_slot<X, IND>(A.row_ptr, A.row_ids, m0.r, nrows, m0.p, y);
+  load_cv_pairs<E, NT>(A.col, val, base, nnz, off, c, v);
+  const RowSlot<X> slot = row_slot<X, IND>(A.row_ptr, A.row_ids, m0.r, nrows, base, y);
   X xg[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) xg[e] = x[c[e]];
 #pragma unroll
-  for (int e = 0; e < E; ++e) s_prod[e * WG + threadIdx.x] = widen<X>(v[e]) * xg[e];
+  for (int e = 0; e < E / 2; ++e) {
+    const int k = e * WG + (int)threadIdx.x;
+    s_prod[2 * k] = widen<X>(v[2 * e]) * xg[2 * e];
+    s_prod[2 * k + 1] = widen<X>(v[2 * e + 1]) * xg[2 * e + 1];
+  }
   __syncthreads();
-  tile_reduce<X, IND>(A.row_ptr, A.row_ids, m0.r, nrows, m0.p, slot, y, s_prod);
+  tile_reduce<X, IND>(A.row_ptr, A.row_ids, m0.r, nrows, base, slot, y, s_prod);
 }
 
 template <int P, int E, bool NT, bool IND>

@@ -88,7 +88,7 @@ def _long_row_matrix(long_len, n_short=300, n_cols=20000, seed=3):
     return gen._finish(counts.size, n_cols, counts, cols, vals)
 
 
-@pytest.mark.parametrize("long_len", [1023, 1024, 1025, 2048, 2049, 4096, 4097, 50_000])
+@pytest.mark.parametrize("long_len", [1021, 1022, 1023, 1024, 1025, 2046, 2047, 2048, 2049, 4094, 4095, 4096, 4097, 50_000])
 @pytest.mark.parametrize("plan", [dict(kernel=1, tile_items=e) for e in (4, 8, 16)] +
                          [dict(kernel=1, tile_items=e, tiles_per_group=t) for e in (4, 8)
                           for t in (3, 16)] +
