@@ -281,9 +281,8 @@ struct Part {
   std::vector<int32_t> h_row_ptr;  // host copy (0-based), for tiling
   RowStats stats;
   spmv_plan_t plan = default_plan();
-  // diagonal panels of this part (built when plan.panels > 1)
-  std::vector<std::unique_ptr<Part>> panels;
-  int panels_built = 1;
+  // diagonal panels of this part, one set per panel count K > 1
+  std::map<int, std::vector<std::unique_ptr<Part>>> panel_sets;
   int64_t d_min = 0, d_max = 0;
   std::map<int, std::pair<DevBuf, int64_t>> tiles;  // tile_items -> (tile starts, count)
 
@@ -342,6 +341,7 @@ struct spmv_handle_s {
   int g_items = -1, g_nt = -1;
   std::vector<BatchTile> h_btiles;
   std::vector<BatchDesc> h_desc;
+  std::map<int, spmv_plan_t> block_plans;  // k -> plan chosen by spmv_tune
 
   ~spmv_handle_s() {
     if (copy_stream) (void)hipStreamSynchronize(copy_stream);
@@ -615,7 +615,7 @@ void encode(int64_t n_rows, int64_t nnz, const int32_t *rp, const int32_t *col, 
   }
 }
 
-void build_panels(spmv_handle_s *h, Part &p, int K);
+std::vector<std::unique_ptr<Part>> &build_panels(spmv_handle_s *h, Part &p, int K);
 
 void choose_plan(spmv_handle_s *h, Part &p, const char *part_name) {
   p.plan = default_plan();
@@ -845,7 +845,7 @@ extern "C" spmv_status_t spmv_create_batch(int32_t count, const int64_t *n_rows,
     upload(M.col, col_all.data(), col_all.size() * 4, "batch col_idx");
     upload(M.val, val_all.data(), val_all.size(), "batch val");
     upload(h->b_desc, h->h_desc.data(), h->h_desc.size() * sizeof(BatchDesc), "batch descriptors");
-    h->b_counter.alloc(sizeof(int32_t), "batch counter");
+    h->b_counter.alloc(8 * sizeof(int32_t), "batch queue counters");
     choose_plan(h.get(), M, "batch");
     hip_ok(hipStreamCreateWithFlags(&h->cap_stream, hipStreamNonBlocking), "capture stream");
     register_handle(h.get());
@@ -937,11 +937,10 @@ bool is_pinned_host(const void *p) {
 // Diagonal panels of a part without a row list: entries grouped by their
 // offset d = col - row into K equal slices of the part's offset range, each
 // slice a CRS over all rows (built on the device; synchronous).
-void build_panels(spmv_handle_s *h, Part &p, int K) {
-  if (p.panels_built == K) return;
-  p.panels.clear();
-  p.panels_built = 1;
-  if (K <= 1) return;
+std::vector<std::unique_ptr<Part>> &build_panels(spmv_handle_s *h, Part &p, int K) {
+  auto found = p.panel_sets.find(K);
+  if (found != p.panel_sets.end()) return found->second;
+  if (K <= 1) fail(SPMV_ERR_INVALID_ARG, "panel count must exceed 1");
   if (p.row_ids.p) fail(SPMV_ERR_UNSUPPORTED, "diagonal panels need a part that covers all rows");
   hipStream_t s = nullptr;
   hip_ok(hipStreamCreateWithFlags(&s, hipStreamNonBlocking), "hipStreamCreate");
@@ -988,18 +987,27 @@ void build_panels(spmv_handle_s *h, Part &p, int K) {
                     span, K, counts.as<int32_t>(), out, s),
          "panel fill");
   hip_ok(hipStreamSynchronize(s), "panels");
-  p.panels = std::move(ps);
-  p.panels_built = K;
+  return p.panel_sets.emplace(K, std::move(ps)).first->second;
+}
+
+// Drops panel sets no chosen plan uses (each is a full copy of the part).
+void prune_panels(Part &p, const std::vector<int> &keep) {
+  for (auto it = p.panel_sets.begin(); it != p.panel_sets.end();) {
+    if (std::find(keep.begin(), keep.end(), it->first) == keep.end())
+      it = p.panel_sets.erase(it);
+    else
+      ++it;
+  }
 }
 
 void run_part(spmv_handle_s *h, Part &p, const void *B, void *C, hipStream_t s) {
   if (p.n_rows == 0 || p.nnz == 0) return;
   if (p.plan.panels > 1) {
-    build_panels(h, p, p.plan.panels);
+    auto &set = build_panels(h, p, p.plan.panels);
     spmv_plan_t sub = p.plan;
     sub.panels = 1;
     const PlanDev pl = to_dev(sub);
-    for (auto &q : p.panels) {
+    for (auto &q : set) {
       if (q->nnz == 0) continue;
       auto t = q->tiles_for(sub.tile_items);
       hip_ok(launch_spmv(h->prec, q->dev(), pl, t.first, t.second, B, C, s), "kernel launch");
@@ -1070,9 +1078,16 @@ int default_kt(int k) {
   return 16;
 }
 
-void run_block_part(spmv_handle_s *h, Part &p, int kt, int nt, int remap, int k, const void *B,
-                    int64_t ldb, void *C, int64_t ldc, hipStream_t s) {
+// Block product over a part, or over its diagonal panels in turn when
+// `panels` > 1 (the panels are shared with the single-vector plan).
+void run_block_part(spmv_handle_s *h, Part &p, int kt, int nt, int remap, int panels, int k,
+                    const void *B, int64_t ldb, void *C, int64_t ldc, hipStream_t s) {
   if (p.n_rows == 0 || p.nnz == 0) return;
+  if (panels > 1) {
+    for (auto &q : build_panels(h, p, panels))
+      run_block_part(h, *q, kt, nt, remap, 1, k, B, ldb, C, ldc, s);
+    return;
+  }
   auto t = p.tiles_for(4);
   hip_ok(launch_spmv_block(h->prec, p.dev(), t.first, t.second, 4, nt, remap, kt, k, B, ldb, C,
                            ldc, s),
@@ -1093,16 +1108,26 @@ extern "C" spmv_status_t spmv_run_block(spmv_handle_t h_, int32_t k, const void 
     if (B && C && B == C) fail(SPMV_ERR_INVALID_ARG, "C must not alias B");
     DeviceGuard dg(h->device);
     Part &p = h->main;
-    int kt = p.plan.block_kt;
-    if (kt == 0) {
+    // per-k choices made by spmv_tune for this handle, else the cache, else defaults
+    int kt = p.plan.block_kt, nt = p.plan.nontemporal, panels = p.plan.panels;
+    auto it = h->block_plans.find(k);
+    if (it != h->block_plans.end()) {
+      kt = it->second.block_kt;
+      nt = it->second.nontemporal;
+      panels = it->second.panels;
+    } else if (kt == 0) {
       spmv_plan_t c;
       kt = default_kt(k);
       if (!(h->flags & SPMV_FLAG_NO_TUNE_CACHE) &&
           cache_lookup(tune_key(h->device, h->prec, k, "block", p.n_rows, p.stats), &c) &&
-          c.block_kt)
+          c.block_kt) {
         kt = c.block_kt;
+        nt = c.nontemporal;
+        panels = c.panels;
+        h->block_plans[k] = c;
+      }
     }
-    run_block_part(h, p, kt, p.plan.nontemporal, p.plan.xcd_remap, k, B, ldb, C, ldc,
+    run_block_part(h, p, kt, nt, p.plan.xcd_remap, panels, k, B, ldb, C, ldc,
                    static_cast<hipStream_t>(stream));
   });
 }
@@ -1194,7 +1219,7 @@ std::vector<spmv_plan_t> candidates() {
 std::vector<spmv_plan_t> panel_candidates() {
   std::vector<spmv_plan_t> c;
   for (int k : {2, 4, 8})
-    for (int e : {4, 8})
+    for (int e : {4, 8, 16})
       for (int rm : {0, 1}) {
         spmv_plan_t p = default_plan();
         p.panels = k;
@@ -1202,6 +1227,13 @@ std::vector<spmv_plan_t> panel_candidates() {
         p.xcd_remap = rm;
         c.push_back(p);
       }
+  for (int k : {4, 8}) {
+    spmv_plan_t p = default_plan();
+    p.panels = k;
+    p.tile_items = 8;
+    p.tiles_per_group = 4;
+    c.push_back(p);
+  }
   return c;
 }
 
@@ -1233,10 +1265,10 @@ void tune_part(spmv_handle_s *h, Part &p, const char *name, void *x, void *y, hi
   p.plan = best_p;
   (void)p.tiles_for(p.plan.tile_items);
   if (p.plan.panels > 1) build_panels(h, p, p.plan.panels);
-  else {
-    p.panels.clear();  // free the device copies of panels that lost
-    p.panels_built = 1;
-  }
+  // free the device copies of panel sets no chosen plan uses
+  std::vector<int> keep{p.plan.panels};
+  for (auto &bp : h->block_plans) keep.push_back(bp.second.panels);
+  prune_panels(p, keep);
   if (std::getenv("SPMV_LOG"))
     std::fprintf(stderr, "libspmv: tuned %s part: kernel=%d tile_items=%d lanes=%d nt=%d remap=%d "
                          "(%.1f us)\n",
@@ -1272,10 +1304,8 @@ extern "C" spmv_status_t spmv_set_plan(spmv_handle_t h_, int32_t part, const spm
     p.plan = *plan;
     if (h->kind != SPMV_KIND_BATCH) {
       (void)p.tiles_for(p.plan.tile_items);
-      if (p.plan.panels > 1) {
-        build_panels(h, p, p.plan.panels);
-        for (auto &q : p.panels) (void)q->tiles_for(p.plan.tile_items);
-      }
+      if (p.plan.panels > 1)
+        for (auto &q : build_panels(h, p, p.plan.panels)) (void)q->tiles_for(p.plan.tile_items);
     }
   });
 }
@@ -1327,25 +1357,32 @@ extern "C" spmv_status_t spmv_tune(spmv_handle_t h_, int32_t k, void *stream) {
     if (h->kind != SPMV_KIND_PLAIN) fail(SPMV_ERR_UNSUPPORTED, "block tuning needs a plain handle");
     Part &p = h->main;
     float best = 1e30f;
-    int best_kt = default_kt(k), best_nt = p.plan.nontemporal;
-    for (int kt : {4, 8, 16}) {
-      if (kt > 2 * k && kt != 4) continue;
-      for (int nt : {1, 0}) {
-        const float ms = tm.median_ms(
-            [&] { run_block_part(h, p, kt, nt, p.plan.xcd_remap, k, x.p, k, y.p, k, s); }, s);
-        if (ms < best) {
-          best = ms;
-          best_kt = kt;
-          best_nt = nt;
+    int best_kt = default_kt(k), best_nt = p.plan.nontemporal, best_pn = 1;
+    for (int pn : {1, 2, 4, 8})
+      for (int kt : {4, 8, 16}) {
+        if (kt > 2 * k && kt != 4) continue;
+        for (int nt : {1, 0}) {
+          const float ms = tm.median_ms(
+              [&] { run_block_part(h, p, kt, nt, p.plan.xcd_remap, pn, k, x.p, k, y.p, k, s); }, s);
+          if (ms < best * 0.99f) {
+            best = ms;
+            best_kt = kt;
+            best_nt = nt;
+            best_pn = pn;
+          }
         }
       }
-    }
     spmv_plan_t c = p.plan;
     c.block_kt = best_kt;
     c.nontemporal = best_nt;
+    c.panels = best_pn;
+    h->block_plans[k] = c;
+    std::vector<int> keep{p.plan.panels};
+    for (auto &bp : h->block_plans) keep.push_back(bp.second.panels);
+    prune_panels(p, keep);
     if (std::getenv("SPMV_LOG"))
-      std::fprintf(stderr, "libspmv: tuned block k=%d: kt=%d nt=%d (%.1f us)\n", k, best_kt,
-                   best_nt, best * 1000.0f);
+      std::fprintf(stderr, "libspmv: tuned block k=%d: kt=%d nt=%d panels=%d (%.1f us)\n", k,
+                   best_kt, best_nt, best_pn, best * 1000.0f);
     if (!(h->flags & SPMV_FLAG_NO_TUNE_CACHE))
       cache_store(tune_key(h->device, h->prec, k, "block", p.n_rows, p.stats), c);
   });

@@ -13,8 +13,9 @@
 //     and combine their partial sums with cross-lane shuffles.
 //   * block kernel: k right-hand sides; a tile's col_idx / val are staged in
 //     LDS once and each row is handled by KT/VW lanes holding VW columns.
-//   * batch kernels: many matrices; tiles of all members form one queue that
-//     a persistent grid drains through an atomic counter.
+//   * batch kernels: many matrices; the tiles of all members are cut into
+//     eight per-XCD work queues that a persistent grid drains through atomic
+//     counters (with stealing once a workgroup's own queue is empty).
 // val and col_idx are read with the nontemporal hint so the single-use
 // matrix stream does not evict B from L2 / MALL.  Tile numbers can be
 // remapped so that each of the eight XCDs (each with a private L2) gets a
@@ -236,40 +237,6 @@ __device__ __forceinline__ void tile_reduce(const int32_t *__restrict__ rp,
   }
 }
 
-// One tile, not pipelined (used by the batch kernels).  Ends with a barrier.
-template <int P, int E, bool NT>
-__device__ __forceinline__ void stream_tile(const int32_t *__restrict__ rp,
-                                            const int32_t *__restrict__ col,
-                                            const typename Ty<P>::V *__restrict__ val,
-                                            const int32_t *__restrict__ row_ids, int r0, int r1,
-                                            const typename Ty<P>::X *__restrict__ x,
-                                            typename Ty<P>::X *__restrict__ y,
-                                            typename Ty<P>::X *s_prod) {
-  using V = typename Ty<P>::V;
-  using X = typename Ty<P>::X;
-  const int p0 = rp[r0];
-  const int nnz = rp[r1] - p0;
-  const int nrows = r1 - r0;
-  if (nnz > WG * E) {
-    long_row<P, NT>(col, val, p0, p0 + nnz, row_ids ? row_ids[r0] : r0, x, y, s_prod);
-    return;
-  }
-  const RowSlot<X> slot = row_slot<X, false>(rp, row_ids, r0, nrows, p0, y);
-  if (nnz > 0) {
-    int c[E];
-    V v[E];
-    load_cv<E, NT>(col, val, p0, nnz, c, v);
-    X xv[E];
-#pragma unroll
-    for (int e = 0; e < E; ++e) xv[e] = x[c[e]];
-#pragma unroll
-    for (int e = 0; e < E; ++e) s_prod[e * WG + threadIdx.x] = widen<X>(v[e]) * xv[e];
-  }
-  lds_barrier();
-  tile_reduce<X, false>(rp, row_ids, r0, nrows, p0, slot, y, s_prod);
-  lds_barrier();
-}
-
 // Stream kernel: workgroup g takes tiles [g*tpw, min((g+1)*tpw, n_tiles)) in
 // order.  While a tile's products are reduced, the next tile's col_idx and
 // val are already in flight (issued before the current tile's barrier).
@@ -280,37 +247,37 @@ __device__ __forceinline__ void stream_tile(const int32_t *__restrict__ rp,
 // or a missing next tile, reads entry 0 of the part instead), so the
 // compiler's wait counts never have to drain the prefetch early.  The kernel
 // is only launched for parts with at least one entry.
-// One tile per workgroup (tiles_per_group == 1): the plain form of the
-// stream kernel, with no prefetch state.  Entries are loaded in pairs from
-// the even entry at or below the tile start (see load_cv_pairs); products go
-// to LDS slot (entry - base), so phase 2 reads relative to base.
+// One tile with paired loads.  Entries are loaded in pairs starting at the
+// entry whose index in the underlying allocation is even (`bias` is the
+// parity of element 0 of `col` / `val` within their allocation), so every
+// paired load is aligned; products go to LDS slot (entry - base) and phase 2
+// reads relative to base.  Ends without a trailing barrier.
 template <int P, int E, bool NT, bool IND>
-__global__ __launch_bounds__(WG) void k_stream1(CsrDev A, const TileRP *__restrict__ tiles,
-                                                int64_t n_tiles, int remap, const void *xv,
-                                                void *yv) {
+__device__ __forceinline__ void tile_paired(const int32_t *__restrict__ rp,
+                                            const int32_t *__restrict__ col,
+                                            const typename Ty<P>::V *__restrict__ val,
+                                            const int32_t *__restrict__ row_ids, TileRP m0,
+                                            TileRP m1, int bias,
+                                            const typename Ty<P>::X *__restrict__ x,
+                                            typename Ty<P>::X *__restrict__ y,
+                                            typename Ty<P>::X *s_prod) {
   using V = typename Ty<P>::V;
   using X = typename Ty<P>::X;
   constexpr int TILE = WG * E;
-  __shared__ X s_prod[TILE];
-  const V *__restrict__ val = static_cast<const V *>(A.val);
-  const X *__restrict__ x = static_cast<const X *>(xv);
-  X *__restrict__ y = static_cast<X *>(yv);
-  const int64_t t = xcd_tile(blockIdx.x, n_tiles, remap);
-  const TileRP m0 = tiles[t], m1 = tiles[t + 1];
   const int nnz = m1.p - m0.p;
   const int nrows = m1.r - m0.r;
   if (nnz > TILE - 2) {
-    long_row<P, NT>(A.col, val, m0.p, m1.p, IND ? (int64_t)A.row_ids[m0.r] : (int64_t)m0.r, x, y,
+    long_row<P, NT>(col, val, m0.p, m1.p, IND ? (int64_t)row_ids[m0.r] : (int64_t)m0.r, x, y,
                     s_prod);
     return;
   }
   if (nnz == 0) return;  // only empty rows: C stays as it is
-  const int off = m0.p & 1;
+  const int off = (m0.p + bias) & 1;
   const int base = m0.p - off;
   int c[E];
   V v[E];
-  load_cv_pairs<E, NT>(A.col, val, base, nnz, off, c, v);
-  const RowSlot<X> slot = row_slot<X, IND>(A.row_ptr, A.row_ids, m0.r, nrows, base, y);
+  load_cv_pairs<E, NT>(col, val, base, nnz, off, c, v);
+  const RowSlot<X> slot = row_slot<X, IND>(rp, row_ids, m0.r, nrows, base, y);
   X xg[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) xg[e] = x[c[e]];
@@ -321,7 +288,22 @@ __global__ __launch_bounds__(WG) void k_stream1(CsrDev A, const TileRP *__restri
     s_prod[2 * k + 1] = widen<X>(v[2 * e + 1]) * xg[2 * e + 1];
   }
   __syncthreads();
-  tile_reduce<X, IND>(A.row_ptr, A.row_ids, m0.r, nrows, base, slot, y, s_prod);
+  tile_reduce<X, IND>(rp, row_ids, m0.r, nrows, base, slot, y, s_prod);
+}
+
+// One tile per workgroup (tiles_per_group == 1): the plain form of the
+// stream kernel, with no prefetch state.
+template <int P, int E, bool NT, bool IND>
+__global__ __launch_bounds__(WG) void k_stream1(CsrDev A, const TileRP *__restrict__ tiles,
+                                                int64_t n_tiles, int remap, const void *xv,
+                                                void *yv) {
+  using V = typename Ty<P>::V;
+  using X = typename Ty<P>::X;
+  __shared__ X s_prod[WG * E];
+  const int64_t t = xcd_tile(blockIdx.x, n_tiles, remap);
+  tile_paired<P, E, NT, IND>(A.row_ptr, A.col, static_cast<const V *>(A.val), A.row_ids, tiles[t],
+                             tiles[t + 1], 0, static_cast<const X *>(xv), static_cast<X *>(yv),
+                             s_prod);
 }
 
 template <int P, int E, bool NT, bool IND>
@@ -581,44 +563,54 @@ __device__ __forceinline__ void batch_tile(const int32_t *rp, const int32_t *col
   using V = typename Ty<P>::V;
   using X = typename Ty<P>::X;
   const BatchDesc D = desc[T.member];
-  stream_tile<P, E, NT>(rp + D.rp_off, col + D.nz_off, static_cast<const V *>(val) + D.nz_off,
-                        nullptr, T.r0, T.r1, static_cast<const X *>(xv) + D.x_off,
-                        static_cast<X *>(yv) + D.y_off, s_prod);
+  const int32_t *mrp = rp + D.rp_off;
+  const TileRP m0{T.r0, mrp[T.r0]}, m1{T.r1, mrp[T.r1]};
+  tile_paired<P, E, NT, false>(mrp, col + D.nz_off, static_cast<const V *>(val) + D.nz_off, nullptr,
+                               m0, m1, (int)(D.nz_off & 1), static_cast<const X *>(xv) + D.x_off,
+                               static_cast<X *>(yv) + D.y_off, s_prod);
 }
 
-__global__ void k_batch_reset(int32_t *counter) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) counter[0] = 0;
+__global__ void k_batch_reset(int32_t *counters) {
+  if (threadIdx.x < NXCD && blockIdx.x == 0) counters[threadIdx.x] = 0;
 }
 
-// Persistent grid: each workgroup claims `chunk` consecutive tiles at a
-// time from the counter; the claim for the next chunk is issued before the
-// current chunk is processed and only read after it, so the atomic's round
-// trip overlaps with work.  Every workgroup reaches the exit test.
+// Persistent grid with one work queue per XCD.  The tiles are cut into eight
+// contiguous ranges (as xcd_tile does); workgroup g, placed on XCD g % 8,
+// claims `chunk` consecutive tiles at a time from its XCD's range through
+// that range's counter, so each XCD's L2 sees one compact stretch of the
+// batch.  When its own range is used up a workgroup claims from the other
+// ranges in turn; it exits once all eight are used up (counters only grow,
+// so every workgroup reaches the exit).
 template <int P, int E, bool NT>
 __global__ __launch_bounds__(WG) void k_batch_persistent(const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ col,
                                                          const void *val, const BatchDesc *desc,
                                                          const BatchTile *tiles, int64_t n_tiles,
-                                                         int32_t *counter, int chunk,
+                                                         int32_t *counters, int chunk,
                                                          const void *xv, void *yv) {
   using X = typename Ty<P>::X;
   __shared__ X s_prod[WG * E];
-  __shared__ int32_t s_t;
-  if (threadIdx.x == 0) s_t = atomicAdd(counter, chunk);
-  __syncthreads();
-  int32_t t0 = s_t;
-  while (t0 < n_tiles) {
-    int32_t next = 0;
-    if (threadIdx.x == 0) next = atomicAdd(counter, chunk);
-    const int32_t t1 = (int32_t)min((int64_t)t0 + chunk, n_tiles);
-    for (int32_t t = t0; t < t1; ++t) {
+  __shared__ int32_t s_claim;
+  const int64_t q = n_tiles / NXCD, r = n_tiles % NXCD;
+  int xq = (int)(blockIdx.x % NXCD);
+  for (int tried = 0; tried < NXCD;) {
+    const int64_t start = xq * q + (xq < r ? xq : r);
+    const int64_t size = q + (xq < r ? 1 : 0);
+    if (threadIdx.x == 0) s_claim = atomicAdd(&counters[xq], chunk);
+    __syncthreads();
+    const int64_t c0 = s_claim;
+    __syncthreads();
+    if (c0 >= size) {
+      xq = (xq + 1) % NXCD;
+      ++tried;
+      continue;
+    }
+    const int64_t c1 = min(c0 + chunk, size);
+    for (int64_t t = start + c0; t < start + c1; ++t) {
       const BatchTile T = tiles[t];
       batch_tile<P, E, NT>(rp, col, val, desc, T, xv, yv, s_prod);
+      __syncthreads();
     }
-    if (threadIdx.x == 0) s_t = next;
-    __syncthreads();
-    t0 = s_t;
-    __syncthreads();
   }
 }
 
@@ -754,7 +746,7 @@ hipError_t run_persistent(const int32_t *rp, const int32_t *col, const void *val
                           const BatchDesc *desc, const BatchTile *tiles, int64_t n_tiles, int nt,
                           int32_t *counter, int grid, const void *x, void *y, hipStream_t s) {
   // about eight claims per workgroup, at most 16 tiles per claim
-  int64_t chunk = n_tiles / ((int64_t)grid * 8);
+  int64_t chunk = n_tiles / ((int64_t)grid * 8);  // grid workgroups share n_tiles
   chunk = chunk < 1 ? 1 : (chunk > 16 ? 16 : chunk);
   if (nt)
     hipLaunchKernelGGL((k_batch_persistent<P, E, true>), dim3(grid), dim3(WG), 0, s, rp, col, val,

@@ -66,7 +66,8 @@ hipError_t launch_spmv_block(int prec, const CsrDev &A, const TileRP *tiles, int
                              int tile_items, int nontemporal, int xcd_remap, int kt, int k,
                              const void *B, int64_t ldb, void *C, int64_t ldc, hipStream_t s);
 
-hipError_t launch_batch_reset(int32_t *counter, hipStream_t s);
+// counters: one int32 per XCD (8)
+hipError_t launch_batch_reset(int32_t *counters, hipStream_t s);
 
 hipError_t launch_batch_persistent(int prec, const int32_t *rp, const int32_t *col, const void *val,
                                    const BatchDesc *desc, const BatchTile *tiles, int64_t n_tiles,

@@ -462,6 +462,33 @@ def test_block_tiles_integer_exact(kt, k):
     assert np.array_equal(got, oracle.spmv_block(A.row_ptr, A.col_idx, A.val, X))
 
 
+@pytest.mark.parametrize("panels", [2, 8])
+@pytest.mark.parametrize("k", [3, 16])
+def test_block_with_panels(k, panels):
+    import torch
+
+    A, _ = mats()["irregular"]
+    X = gen.block_rhs(A.n_cols, k, extra=7)
+    h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, flags=NOTUNE)
+    try:
+        spmv.spmv_set_plan(h, panels=panels)
+        B = torch.from_numpy(X).cuda()
+        C = torch.zeros((A.n_rows, k), dtype=torch.float64, device="cuda")
+        spmv.spmv_run_block(h, B, C)
+        c1 = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+        spmv.spmv_run(h, B[:, 0].contiguous(), c1)  # single-vector path shares the panels
+        torch.cuda.synchronize()
+        got = C.cpu().numpy()
+    finally:
+        spmv.spmv_destroy(h)
+    ref = oracle.spmv_block(A.row_ptr, A.col_idx, A.val, X)
+    for t in range(k):
+        den = oracle.abs_spmv(A.row_ptr, A.col_idx, A.val, X[:, t])
+        assert_close(got[:, t], ref[:, t], den, FP64_TOL, f"block k={k} panels={panels} col {t}")
+    den = oracle.abs_spmv(A.row_ptr, A.col_idx, A.val, X[:, 0])
+    assert_close(c1.cpu().numpy(), ref[:, 0], den, FP64_TOL, "single vector with panels")
+
+
 def test_block_rejects_split_and_bad_k():
     import torch
 
