@@ -405,13 +405,20 @@ def batch_paths(steps, warmup):
            "max_normalized_err_first64": worst, "plan": spmv.spmv_get_plan(h)}
     flops = 2.0 * nnz
     mb = algorithmic_bytes(n_rows, n_cols, nnz, "f64") + 4 * len(mem)
-    for name, sch in (("graph", spmv.SPMV_SCHEDULE_BATCH_GRAPH), ("direct", spmv.SPMV_SCHEDULE_BATCH_DIRECT),
-                      ("flat", spmv.SPMV_SCHEDULE_BATCH_FLAT)):
-        spmv.spmv_set_schedule(h, sch)
-        tm = time_launches(lambda: spmv.spmv_run(h, B, C), steps, warmup)
-        res[f"{name}_ms"] = tm["p50_ms"]
-        res[f"{name}_gflops"] = flops / (tm["ms_per_step"] * 1e6)
-        res[f"{name}_model_GBs"] = mb / (tm["ms_per_step"] * 1e6)
+    tuned = spmv.spmv_get_plan(h)
+    for kname, kern in (("queue", spmv.SPMV_KERNEL_STREAM), ("tilegrid", spmv.SPMV_KERNEL_TILE_GRID)):
+        spmv.spmv_set_plan(h, kernel=kern)
+        for name, sch in (("graph", spmv.SPMV_SCHEDULE_BATCH_GRAPH), ("direct", spmv.SPMV_SCHEDULE_BATCH_DIRECT)):
+            spmv.spmv_set_schedule(h, sch)
+            tm = time_launches(lambda: spmv.spmv_run(h, B, C), steps, warmup)
+            res[f"{kname}_{name}_ms"] = tm["p50_ms"]
+            res[f"{kname}_{name}_gflops"] = flops / (tm["ms_per_step"] * 1e6)
+    spmv.spmv_set_plan(h, **tuned)
+    spmv.spmv_set_schedule(h, spmv.SPMV_SCHEDULE_BATCH_GRAPH)
+    tm = time_launches(lambda: spmv.spmv_run(h, B, C), steps, warmup)
+    res["graph_ms"] = tm["p50_ms"]
+    res["graph_gflops"] = flops / (tm["ms_per_step"] * 1e6)
+    res["graph_model_GBs"] = mb / (tm["ms_per_step"] * 1e6)
     spmv.spmv_destroy(h)
     # baseline: one plain launch per member
     hs = [make_handle(A, "f64", tune=False) for A, _ in mem]
@@ -433,8 +440,10 @@ def batch_paths(steps, warmup):
     res["model_bytes"] = mb
     for hh in hs:
         spmv.spmv_destroy(hh)
-    log(f"batch: graph {res['graph_ms']*1e3:.0f} us ({res['graph_gflops']:.0f} GFlop/s), direct "
-        f"{res['direct_ms']*1e3:.0f} us, flat {res['flat_ms']*1e3:.0f} us, per-member launches "
+    log(f"batch: tuned graph {res['graph_ms']*1e3:.0f} us ({res['graph_gflops']:.0f} GFlop/s, "
+        f"kernel {res['plan']['kernel']}); queue graph {res['queue_graph_ms']*1e3:.0f} us, "
+        f"queue direct {res['queue_direct_ms']*1e3:.0f} us, tile-grid graph {res['tilegrid_graph_ms']*1e3:.0f} us, "
+        f"tile-grid direct {res['tilegrid_direct_ms']*1e3:.0f} us, per-member launches "
         f"{res['per_member_launches_ms']*1e3:.0f} us")
     del B, C, views
     torch.cuda.empty_cache()

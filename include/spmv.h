@@ -193,9 +193,12 @@ spmv_status_t spmv_create_batch(int32_t count, const int64_t *n_rows, const int6
  *   kernel       SPMV_KERNEL_STREAM: rows are grouped into tiles of at most
  *                256 * tile_items stored entries; a 256-thread workgroup
  *                streams a tile's val and col_idx with coalesced loads, forms
- *                the products in LDS and reduces each row there.
+ *                the products in LDS and reduces each row there.  For batch
+ *                handles: a persistent grid drains per-XCD tile queues.
  *                SPMV_KERNEL_VECTOR: `lanes` lanes of a wavefront share one
- *                row and reduce it with cross-lane shuffles.
+ *                row and reduce it with cross-lane shuffles (not for batches).
+ *                SPMV_KERNEL_TILE_GRID: batch handles only; one workgroup per
+ *                tile of the whole batch in a single launch.
  *   tile_items   4, 8 or 16 (stream kernel)
  *   lanes        2, 4, 8, 16, 32 or 64 (vector kernel)
  *   nontemporal  1: val and col_idx are loaded with the streaming hint so
@@ -216,6 +219,7 @@ spmv_status_t spmv_create_batch(int32_t count, const int64_t *n_rows, const int6
  * ------------------------------------------------------------------------- */
 #define SPMV_KERNEL_STREAM 1
 #define SPMV_KERNEL_VECTOR 2
+#define SPMV_KERNEL_TILE_GRID 3
 #define SPMV_PART_MAIN 0
 #define SPMV_PART_NONLOCAL 1
 

@@ -201,13 +201,13 @@ RowStats row_stats(const int32_t *rp, int64_t n) {
   return s;
 }
 
-// Greedy tiles of consecutive rows holding at most `tile` - 2 entries (room
-// for the kernel's paired loads to start one entry early) and at most 512
-// rows (two per lane of the workgroup, whose bounds the kernel prefetches);
-// a row longer than that gets a tile of its own.
+// Greedy tiles of consecutive rows holding at most `tile` - 4 entries (room
+// for the kernel's grouped loads to start up to three entries early) and at
+// most 512 rows (two per lane of the workgroup, whose bounds the kernel
+// prefetches); a row longer than that gets a tile of its own.
 std::vector<int32_t> make_tiles(const int32_t *rp, int64_t n, int64_t tile_items) {
   constexpr int64_t kMaxRows = 2 * kWG;
-  const int64_t tile = tile_items - 2;
+  const int64_t tile = tile_items - 4;
   std::vector<int32_t> t;
   t.reserve(size_t(n / std::max<int64_t>(1, std::min(tile / 16, kMaxRows)) + 2));
   t.push_back(0);
@@ -239,8 +239,9 @@ spmv_plan_t default_plan() {
 }
 
 void check_plan(const spmv_plan_t &p) {
-  if (p.kernel != SPMV_KERNEL_STREAM && p.kernel != SPMV_KERNEL_VECTOR)
-    fail(SPMV_ERR_INVALID_ARG, "plan.kernel must be SPMV_KERNEL_STREAM or SPMV_KERNEL_VECTOR");
+  if (p.kernel != SPMV_KERNEL_STREAM && p.kernel != SPMV_KERNEL_VECTOR &&
+      p.kernel != SPMV_KERNEL_TILE_GRID)
+    fail(SPMV_ERR_INVALID_ARG, "plan.kernel must be SPMV_KERNEL_STREAM, _VECTOR or _TILE_GRID");
   if (p.tile_items != 4 && p.tile_items != 8 && p.tile_items != 16)
     fail(SPMV_ERR_INVALID_ARG, "plan.tile_items must be 4, 8 or 16");
   if (p.lanes < 2 || p.lanes > 64 || (p.lanes & (p.lanes - 1)))
@@ -338,7 +339,7 @@ struct spmv_handle_s {
   hipGraphExec_t gexec = nullptr;
   const void *g_B = nullptr;
   void *g_C = nullptr;
-  int g_items = -1, g_nt = -1;
+  int g_items = -1, g_nt = -1, g_kernel = -1;
   std::vector<BatchTile> h_btiles;
   std::vector<BatchDesc> h_desc;
   std::map<int, spmv_plan_t> block_plans;  // k -> plan chosen by spmv_tune
@@ -876,6 +877,10 @@ void batch_prepare(spmv_handle_s *h) {
 }
 
 hipError_t batch_launch_direct(spmv_handle_s *h, const void *B, void *C, hipStream_t s) {
+  if (h->main.plan.kernel == SPMV_KERNEL_TILE_GRID)
+    return launch_batch_flat(h->prec, h->main.row_ptr.as<int32_t>(), h->main.col.as<int32_t>(),
+                             h->main.val.p, h->b_desc.as<BatchDesc>(), h->b_tiles.as<BatchTile>(),
+                             h->b_ntiles, h->b_tiles_items, h->main.plan.nontemporal, B, C, s);
   hipError_t e = launch_batch_reset(h->b_counter.as<int32_t>(), s);
   if (e != hipSuccess) return e;
   return launch_batch_persistent(h->prec, h->main.row_ptr.as<int32_t>(), h->main.col.as<int32_t>(),
@@ -902,7 +907,7 @@ void batch_run(spmv_handle_s *h, const void *B, void *C, hipStream_t s) {
   // Graph: the counter reset and the persistent launch are captured once per
   // (B, C, plan) and replayed.
   if (!h->gexec || h->g_B != B || h->g_C != C || h->g_items != h->b_tiles_items ||
-      h->g_nt != h->main.plan.nontemporal) {
+      h->g_nt != h->main.plan.nontemporal || h->g_kernel != h->main.plan.kernel) {
     if (h->gexec) (void)hipGraphExecDestroy(h->gexec);
     if (h->graph) (void)hipGraphDestroy(h->graph);
     h->gexec = nullptr;
@@ -919,6 +924,7 @@ void batch_run(spmv_handle_s *h, const void *B, void *C, hipStream_t s) {
     h->g_C = C;
     h->g_items = h->b_tiles_items;
     h->g_nt = h->main.plan.nontemporal;
+    h->g_kernel = h->main.plan.kernel;
   }
   hip_ok(hipGraphLaunch(h->gexec, s), "graph launch");
 }
@@ -1293,8 +1299,10 @@ extern "C" spmv_status_t spmv_set_plan(spmv_handle_t h_, int32_t part, const spm
     spmv_handle_s *h = live(h_);
     if (!plan) fail(SPMV_ERR_INVALID_ARG, "plan is null");
     check_plan(*plan);
-    if (h->kind == SPMV_KIND_BATCH && plan->kernel != SPMV_KERNEL_STREAM)
-      fail(SPMV_ERR_UNSUPPORTED, "batch handles run the stream kernel only");
+    if (h->kind == SPMV_KIND_BATCH && plan->kernel == SPMV_KERNEL_VECTOR)
+      fail(SPMV_ERR_UNSUPPORTED, "batch handles run the stream or tile-grid kernel");
+    if (h->kind != SPMV_KIND_BATCH && plan->kernel == SPMV_KERNEL_TILE_GRID)
+      fail(SPMV_ERR_UNSUPPORTED, "the tile-grid kernel serves batch handles only");
     if (h->kind == SPMV_KIND_BATCH && plan->panels != 1)
       fail(SPMV_ERR_UNSUPPORTED, "batch handles do not use diagonal panels");
     Part &p = part_of(h, part);
@@ -1331,10 +1339,11 @@ extern "C" spmv_status_t spmv_tune(spmv_handle_t h_, int32_t k, void *stream) {
       spmv_plan_t best_p = keep;
       const int saved_sched = h->schedule;
       h->schedule = SPMV_SCHEDULE_BATCH_DIRECT;
+      for (int kern : {SPMV_KERNEL_STREAM, SPMV_KERNEL_TILE_GRID})
       for (int e : {4, 8, 16})
         for (int nt : {1, 0}) {
           p.plan = keep;
-          p.plan.kernel = SPMV_KERNEL_STREAM;
+          p.plan.kernel = kern;
           p.plan.tile_items = e;
           p.plan.nontemporal = nt;
           const float ms = tm.median_ms([&] { batch_run(h, x.p, y.p, s); }, s);

@@ -98,35 +98,43 @@ __device__ __forceinline__ void load_cv(const int32_t *__restrict__ col,
   }
 }
 
-// Paired form of load_cv: lane tid takes entry pairs (2k, 2k+1) counted from
-// the even entry base = p0 - off, k = tid, tid + 256, ..., so each load moves
-// two adjacent entries (16 bytes of FP64 values, 8 bytes of indices).  Pairs
-// past the tile are clamped to its last pair.  The first entry of a pair is
-// always a stored entry (index <= p0 + nnz - 1); the second may lie one past
-// the tile -- for the part's last tile, in the arrays' tail padding -- so its
-// column is replaced by the first entry's column and it is never used as a
-// gather index.  Needs nnz + off <= 256 * E.
-template <class V> struct Pair;
-template <> struct Pair<double> { typedef double T __attribute__((ext_vector_type(2))); };
-template <> struct Pair<float> { typedef float T __attribute__((ext_vector_type(2))); };
-template <> struct Pair<uint16_t> { typedef uint16_t T __attribute__((ext_vector_type(2))); };
-typedef int32_t IPair __attribute__((ext_vector_type(2)));
+// Grouped form of load_cv: lane tid takes groups of G adjacent entries
+// (G = 2 for 8-byte values, 4 for 4- and 2-byte values), group g covering
+// entries base + G*g .. base + G*g + G - 1 with g = tid, tid + 256, ...;
+// base = p0 - off is the entry at or below the tile start whose index in the
+// allocation is a multiple of G, so each group is one aligned vector load of
+// indices (8 or 16 bytes) and one of values (16 or 8 bytes).  Groups past the
+// tile are clamped to its last group.  The first entry of a group is always a
+// stored entry; later ones may lie past the tile -- for the part's last tile,
+// in the arrays' tail padding -- so their columns are replaced by the group's
+// first column and never used as gather indices.  Needs nnz + off <= 256 * E.
+template <class V> constexpr int group_of() { return sizeof(V) == 8 ? 2 : 4; }
+template <class V, int G> struct VecOf;
+template <> struct VecOf<double, 2> { typedef double T __attribute__((ext_vector_type(2))); };
+template <> struct VecOf<float, 4> { typedef float T __attribute__((ext_vector_type(4))); };
+template <> struct VecOf<uint16_t, 4> { typedef uint16_t T __attribute__((ext_vector_type(4))); };
+template <int G> struct IdxOf;
+template <> struct IdxOf<2> { typedef int32_t T __attribute__((ext_vector_type(2))); };
+template <> struct IdxOf<4> { typedef int32_t T __attribute__((ext_vector_type(4))); };
 
 template <int E, bool NT, class V>
-__device__ __forceinline__ void load_cv_pairs(const int32_t *__restrict__ col,
-                                              const V *__restrict__ val, int base, int nnz, int off,
-                                              int (&c)[E], V (&v)[E]) {
-  using PV = typename Pair<V>::T;
-  const int lastp = (nnz + off - 1) >> 1;
+__device__ __forceinline__ void load_cv_groups(const int32_t *__restrict__ col,
+                                               const V *__restrict__ val, int base, int nnz, int off,
+                                               int (&c)[E], V (&v)[E]) {
+  constexpr int G = group_of<V>();
+  using VV = typename VecOf<V, G>::T;
+  using IV = typename IdxOf<G>::T;
+  const int lastg = (nnz + off - 1) / G;
 #pragma unroll
-  for (int e = 0; e < E / 2; ++e) {
-    const int k = min(e * WG + (int)threadIdx.x, lastp);
-    const IPair cp = ld<IPair, NT>(reinterpret_cast<const IPair *>(col + base + 2 * k));
-    const PV vp = ld<PV, NT>(reinterpret_cast<const PV *>(val + base + 2 * k));
-    c[2 * e] = cp.x;
-    c[2 * e + 1] = (2 * k + 1 < nnz + off) ? cp.y : cp.x;
-    v[2 * e] = vp.x;
-    v[2 * e + 1] = vp.y;
+  for (int e = 0; e < E / G; ++e) {
+    const int g = min(e * WG + (int)threadIdx.x, lastg);
+    const IV ci = ld<IV, NT>(reinterpret_cast<const IV *>(col + base + G * g));
+    const VV vi = ld<VV, NT>(reinterpret_cast<const VV *>(val + base + G * g));
+#pragma unroll
+    for (int j = 0; j < G; ++j) {
+      c[G * e + j] = (j == 0 || G * g + j < nnz + off) ? ci[j] : ci[0];
+      v[G * e + j] = vi[j];
+    }
   }
 }
 
@@ -247,13 +255,12 @@ __device__ __forceinline__ void tile_reduce(const int32_t *__restrict__ rp,
 // or a missing next tile, reads entry 0 of the part instead), so the
 // compiler's wait counts never have to drain the prefetch early.  The kernel
 // is only launched for parts with at least one entry.
-// One tile with paired loads.  Entries are loaded in pairs starting at the
-// entry whose index in the underlying allocation is even (`bias` is the
-// parity of element 0 of `col` / `val` within their allocation), so every
-// paired load is aligned; products go to LDS slot (entry - base) and phase 2
-// reads relative to base.  Ends without a trailing barrier.
+// One tile with grouped loads (see load_cv_groups).  `bias` is the index of
+// element 0 of `col` / `val` within their allocation modulo the group size,
+// so every grouped load is aligned; products go to LDS slot (entry - base)
+// and phase 2 reads relative to base.  Ends without a trailing barrier.
 template <int P, int E, bool NT, bool IND>
-__device__ __forceinline__ void tile_paired(const int32_t *__restrict__ rp,
+__device__ __forceinline__ void tile_grouped(const int32_t *__restrict__ rp,
                                             const int32_t *__restrict__ col,
                                             const typename Ty<P>::V *__restrict__ val,
                                             const int32_t *__restrict__ row_ids, TileRP m0,
@@ -266,28 +273,29 @@ __device__ __forceinline__ void tile_paired(const int32_t *__restrict__ rp,
   constexpr int TILE = WG * E;
   const int nnz = m1.p - m0.p;
   const int nrows = m1.r - m0.r;
-  if (nnz > TILE - 2) {
+  constexpr int G = group_of<V>();
+  if (nnz > TILE - (G - 1)) {
     long_row<P, NT>(col, val, m0.p, m1.p, IND ? (int64_t)row_ids[m0.r] : (int64_t)m0.r, x, y,
                     s_prod);
     return;
   }
   if (nnz == 0) return;  // only empty rows: C stays as it is
-  const int off = (m0.p + bias) & 1;
+  const int off = (m0.p + bias) % G;
   const int base = m0.p - off;
   int c[E];
   V v[E];
-  load_cv_pairs<E, NT>(col, val, base, nnz, off, c, v);
+  load_cv_groups<E, NT>(col, val, base, nnz, off, c, v);
   const RowSlot<X> slot = row_slot<X, IND>(rp, row_ids, m0.r, nrows, base, y);
   X xg[E];
 #pragma unroll
   for (int e = 0; e < E; ++e) xg[e] = x[c[e]];
 #pragma unroll
-  for (int e = 0; e < E / 2; ++e) {
-    const int k = e * WG + (int)threadIdx.x;
-    s_prod[2 * k] = widen<X>(v[2 * e]) * xg[2 * e];
-    s_prod[2 * k + 1] = widen<X>(v[2 * e + 1]) * xg[2 * e + 1];
+  for (int e = 0; e < E / G; ++e) {
+    const int g = e * WG + (int)threadIdx.x;
+#pragma unroll
+    for (int j = 0; j < G; ++j) s_prod[G * g + j] = widen<X>(v[G * e + j]) * xg[G * e + j];
   }
-  __syncthreads();
+  lds_barrier();
   tile_reduce<X, IND>(rp, row_ids, m0.r, nrows, base, slot, y, s_prod);
 }
 
@@ -301,7 +309,7 @@ __global__ __launch_bounds__(WG) void k_stream1(CsrDev A, const TileRP *__restri
   using X = typename Ty<P>::X;
   __shared__ X s_prod[WG * E];
   const int64_t t = xcd_tile(blockIdx.x, n_tiles, remap);
-  tile_paired<P, E, NT, IND>(A.row_ptr, A.col, static_cast<const V *>(A.val), A.row_ids, tiles[t],
+  tile_grouped<P, E, NT, IND>(A.row_ptr, A.col, static_cast<const V *>(A.val), A.row_ids, tiles[t],
                              tiles[t + 1], 0, static_cast<const X *>(xv), static_cast<X *>(yv),
                              s_prod);
 }
@@ -565,8 +573,9 @@ __device__ __forceinline__ void batch_tile(const int32_t *rp, const int32_t *col
   const BatchDesc D = desc[T.member];
   const int32_t *mrp = rp + D.rp_off;
   const TileRP m0{T.r0, mrp[T.r0]}, m1{T.r1, mrp[T.r1]};
-  tile_paired<P, E, NT, false>(mrp, col + D.nz_off, static_cast<const V *>(val) + D.nz_off, nullptr,
-                               m0, m1, (int)(D.nz_off & 1), static_cast<const X *>(xv) + D.x_off,
+  tile_grouped<P, E, NT, false>(mrp, col + D.nz_off, static_cast<const V *>(val) + D.nz_off, nullptr,
+                               m0, m1, (int)(D.nz_off % group_of<V>()),
+                               static_cast<const X *>(xv) + D.x_off,
                                static_cast<X *>(yv) + D.y_off, s_prod);
 }
 
@@ -597,19 +606,21 @@ __global__ __launch_bounds__(WG) void k_batch_persistent(const int32_t *__restri
     const int64_t start = xq * q + (xq < r ? xq : r);
     const int64_t size = q + (xq < r ? 1 : 0);
     if (threadIdx.x == 0) s_claim = atomicAdd(&counters[xq], chunk);
-    __syncthreads();
+    lds_barrier();
     const int64_t c0 = s_claim;
-    __syncthreads();
+    lds_barrier();
     if (c0 >= size) {
       xq = (xq + 1) % NXCD;
       ++tried;
       continue;
     }
     const int64_t c1 = min(c0 + chunk, size);
+    // LDS-only barriers: the previous tile's stores of C need not complete
+    // before the next tile starts (each tile writes its own rows)
     for (int64_t t = start + c0; t < start + c1; ++t) {
       const BatchTile T = tiles[t];
       batch_tile<P, E, NT>(rp, col, val, desc, T, xv, yv, s_prod);
-      __syncthreads();
+      lds_barrier();
     }
   }
 }

@@ -43,6 +43,7 @@ SPMV_FLAG_NO_TUNE_CACHE = 0x2
 
 SPMV_KERNEL_STREAM = 1
 SPMV_KERNEL_VECTOR = 2
+SPMV_KERNEL_TILE_GRID = 3
 SPMV_PART_MAIN = 0
 SPMV_PART_NONLOCAL = 1
 

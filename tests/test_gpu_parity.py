@@ -516,17 +516,18 @@ def _batch(count=40, nmax=30000, seed_extra=1):
     return gen.workload_c5_batch(count=count, nmin=1000, nmax=nmax, seed_extra=seed_extra)
 
 
+@pytest.mark.parametrize("kernel", [spmv.SPMV_KERNEL_STREAM, spmv.SPMV_KERNEL_TILE_GRID])
 @pytest.mark.parametrize("schedule", [spmv.SPMV_SCHEDULE_BATCH_GRAPH, spmv.SPMV_SCHEDULE_BATCH_DIRECT,
                                       spmv.SPMV_SCHEDULE_BATCH_FLAT])
 @pytest.mark.parametrize("tile_items", [4, 8, 16])
-def test_batch_matches_members(schedule, tile_items):
+def test_batch_matches_members(schedule, tile_items, kernel):
     import torch
 
     mem = _batch()
     h = spmv.spmv_create_batch([(A.row_ptr, A.col_idx, A.val, A.n_cols) for A, _ in mem], flags=NOTUNE)
     try:
         spmv.spmv_set_schedule(h, schedule)
-        spmv.spmv_set_plan(h, tile_items=tile_items)
+        spmv.spmv_set_plan(h, tile_items=tile_items, kernel=kernel)
         xs = np.concatenate([x for _, x in mem])
         c0 = gen.uniform_vector(sum(A.n_rows for A, _ in mem), gen.rng_for(18, 0))
         B = to_dev(xs, "f64")
@@ -544,7 +545,8 @@ def test_batch_matches_members(schedule, tile_items):
         off += A.n_rows
 
 
-def test_batch_graph_replays_and_recapture():
+@pytest.mark.parametrize("kernel", [spmv.SPMV_KERNEL_STREAM, spmv.SPMV_KERNEL_TILE_GRID])
+def test_batch_graph_replays_and_recapture(kernel):
     import torch
 
     mem = _batch(count=24, seed_extra=2)
@@ -557,6 +559,7 @@ def test_batch_graph_replays_and_recapture():
     exact = np.concatenate(exact)
     h = spmv.spmv_create_batch([(A.row_ptr, A.col_idx, A.val, A.n_cols) for A, _ in mem], flags=NOTUNE)
     try:
+        spmv.spmv_set_plan(h, kernel=kernel)
         B = to_dev(xs, "f64")
         C = torch.zeros(exact.size, dtype=torch.float64, device="cuda")
         for r in range(1, 5):
@@ -644,7 +647,7 @@ def test_set_plan_validation():
     A, _ = mats()["irregular"]
     h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, flags=NOTUNE)
     try:
-        for bad in (dict(kernel=3), dict(tile_items=5), dict(lanes=3), dict(block_kt=2),
+        for bad in (dict(kernel=4), dict(kernel=3), dict(tile_items=5), dict(lanes=3), dict(block_kt=2),
                     dict(tiles_per_group=0), dict(tiles_per_group=65), dict(panels=3)):
             with pytest.raises(spmv.SpmvError):
                 spmv.spmv_set_plan(h, **bad)
