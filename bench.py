@@ -17,9 +17,11 @@ includes row_ptr (4 bytes per row) and C is read and written once (no
 write-allocate): nnz*(s_val + 4) + 4*(N+1) + n_cols*k*s_x + 2*N*k*s_c.
 
 Usage: python bench.py [--gpus 1] [--steps K] [--warmup W] [--only headline]
-       python bench.py --pmc-pass        (headline kernel + copy calibration,
-                                          for rocprofv3 --pmc runs)
-       python bench.py --summarize-pmc FETCH_DIR WRITE_DIR OUT
+       python bench.py --only headline --plan '{...}'   (headline with a fixed plan)
+       python bench.py --pmc-pass --plan '{...}'         (headline kernel + copy
+                                          calibration, for rocprofv3 --pmc runs)
+       python bench.py --summarize-pmc FETCH_DIR WRITE_DIR OUT PLAN
+       python bench.py --summarize-stats STATS_CSV OUT COMMAND
 """
 from __future__ import annotations
 
@@ -198,13 +200,16 @@ def bound(prec: str, n: int) -> float:
             "f32f64": u32 + (n + 2) * u64}[prec]
 
 
-def run_spmv_path(A, x, prec, steps, warmup, label, ref=None, den=None, tune=True):
-    """Time spmv_run on one matrix in one precision; check the first result."""
+def run_spmv_path(A, x, prec, steps, warmup, label, ref=None, den=None, tune=True, plan=None):
+    """Time spmv_run on one matrix in one precision; check the first result.
+    With `plan` given the autotuner is skipped and that plan is used."""
     import torch
 
     from paper_1106_5908_amd import spmv
 
-    h = make_handle(A, prec, tune)
+    h = make_handle(A, prec, tune and plan is None)
+    if plan is not None:
+        spmv.spmv_set_plan(h, **plan)
     B = dev_vec(x, prec)
     C = torch.zeros(A.n_rows, dtype=B.dtype, device="cuda")
     spmv.spmv_run(h, B, C)
@@ -644,7 +649,8 @@ def main():
     ap.add_argument("--only", choices=["all", "headline"], default="all")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--pmc-pass", action="store_true")
-    ap.add_argument("--plan", default=None, help="plan (JSON) for --pmc-pass")
+    ap.add_argument("--plan", default=None,
+                    help="plan (JSON) for the headline product instead of the autotuner's")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "OUT", "PLAN_JSON"))
     ap.add_argument("--summarize-stats", nargs=3, metavar=("STATS_CSV", "OUT", "COMMAND"))
     args = ap.parse_args()
@@ -678,7 +684,8 @@ def main():
     t0 = time.time()
     A2, x2 = gen.workload_c2()
     log(f"27-point 160^3 generated in {time.time() - t0:.1f}s ({A2.nnz} entries)")
-    head, ref2, den2 = run_spmv_path(A2, x2, "f64", args.steps, args.warmup, "27pt160")
+    head, ref2, den2 = run_spmv_path(A2, x2, "f64", args.steps, args.warmup, "27pt160",
+                                     plan=json.loads(args.plan) if args.plan else None)
     flops = 2.0 * A2.nnz
     mb = head["model_bytes"]
     traffic = read_traffic(head["plan"])
