@@ -31,6 +31,7 @@ import hashlib
 import json
 import math
 import os
+import subprocess
 import sys
 import time
 
@@ -523,6 +524,97 @@ def cpu_baseline(A, x, budget_s: float = 12.0):
                       f"({el:.1f} s, one thread)"}
 
 
+def cold_headline(A, x, plan, reps: int = 20):
+    """The headline product with caches flushed before every call: a 1 GiB
+    buffer (four times the 256 MB MALL) is overwritten between calls,
+    outside the timed interval; each call is timed alone with an event pair."""
+    import torch
+
+    from paper_1106_5908_amd import spmv
+
+    h = make_handle(A, "f64", tune=False)
+    spmv.spmv_set_plan(h, **plan)
+    B = dev_vec(x, "f64")
+    C = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+    scrub = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+    s = torch.cuda.current_stream()
+    times = []
+    for i in range(reps + 2):
+        scrub.fill_(float(i))
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(s)
+        spmv.spmv_run(h, B, C)
+        e1.record(s)
+        torch.cuda.synchronize()
+        if i >= 2:
+            times.append(e0.elapsed_time(e1))
+    spmv.spmv_destroy(h)
+    del B, C, scrub
+    torch.cuda.empty_cache()
+    t = np.array(times)
+    med = float(np.median(t))
+    mb = algorithmic_bytes(A.n_rows, A.n_cols, A.nnz, "f64")
+    out = {"median_ms": med, "p10_ms": float(np.percentile(t, 10)),
+           "p90_ms": float(np.percentile(t, 90)), "gflops": 2.0 * A.nnz / (med * 1e6),
+           "model_GBs": mb / (med * 1e6), "scrub_bytes": 1 << 30, "calls": reps, "plan": plan}
+    log(f"27pt160 cold: {out['gflops']:.0f} GFlop/s ({med * 1e3:.1f} us)")
+    return out
+
+
+OMP_SRC = os.path.join(ROOT, "bench_omp.c")
+OMP_LIB = os.path.join(ROOT, "bench_omp.so")
+
+
+def build_omp(force: bool = False) -> str:
+    """Compile the OpenMP CPU baseline (bench_omp.c) with gcc."""
+    if force or not os.path.exists(OMP_LIB) or os.path.getmtime(OMP_LIB) < os.path.getmtime(OMP_SRC):
+        tmp = OMP_LIB + ".tmp%d" % os.getpid()
+        subprocess.check_call(["gcc", "-O3", "-fopenmp", "-Wall", "-shared", "-fPIC", "-o", tmp,
+                               OMP_SRC])
+        os.replace(tmp, OMP_LIB)
+    return OMP_LIB
+
+
+def cpu_omp(A, x, ref, den, reps: int = 10, triad_n: int = 1 << 26):
+    """The paper's node-level CRS (OpenMP rows, static schedule, first touch)
+    and the triad on all host threads; kappa of the host from the two."""
+    import ctypes
+
+    import oracle
+
+    lib = ctypes.CDLL(build_omp())
+    lib.omp_crs_bench.restype = ctypes.c_double
+    lib.omp_crs_bench.argtypes = [ctypes.c_int64, ctypes.c_int64] + [ctypes.c_void_p] * 4 + [
+        ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]
+    lib.omp_triad_bench.restype = ctypes.c_double
+    lib.omp_triad_bench.argtypes = [ctypes.c_int64, ctypes.c_int, ctypes.c_void_p]
+    rp = np.ascontiguousarray(A.row_ptr, dtype=np.int32)
+    ci = np.ascontiguousarray(A.col_idx, dtype=np.int32)
+    va = np.ascontiguousarray(A.val, dtype=np.float64)
+    xv = np.ascontiguousarray(x, dtype=np.float64)
+    y = np.zeros(A.n_rows, dtype=np.float64)
+    nt = ctypes.c_int(0)
+    sec = lib.omp_crs_bench(A.n_rows, A.n_cols, rp.ctypes.data, ci.ctypes.data, va.ctypes.data,
+                            xv.ctypes.data, reps, y.ctypes.data, ctypes.byref(nt))
+    if sec <= 0:
+        return None
+    nt2 = ctypes.c_int(0)
+    triad = lib.omp_triad_bench(triad_n, 10, ctypes.byref(nt2))
+    perf = 2.0 * A.nnz / sec / 1e9
+    nnzr = A.nnz / A.n_rows
+    wa = triad * 4.0 / 3.0
+    err = float(oracle.normalized_error(y, ref, den).max())
+    out = {"gflops": perf, "median_ms": sec * 1e3, "threads": nt.value,
+           "cores_visible": len(os.sched_getaffinity(0)),
+           "model_GBs": algorithmic_bytes(A.n_rows, A.n_cols, A.nnz, "f64") / sec / 1e9,
+           "triad_GBs": triad, "triad_GBs_with_write_allocate": wa,
+           "kappa": kappa_from(wa, perf, nnzr), "max_normalized_err": err,
+           "schedule": "OpenMP static over rows, first-touch placement"}
+    log(f"cpu OpenMP CRS: {perf:.2f} GFlop/s on {nt.value} threads, triad {triad:.1f} GB/s")
+    return out
+
+
 # ----------------------------------------------------------------------------
 # rocprofv3 counter passes
 # ----------------------------------------------------------------------------
@@ -702,6 +794,7 @@ def main():
         paths["headline_detail"]["kappa_gpu"] = kappa_gpu(traffic, flops, mb)
 
     if args.only == "all":
+        paths["headline_cold"] = cold_headline(A2, x2, head["plan"])
         prec_rows = []
         for prec in ("f32", "bf16", "f32f64"):
             r, _, _ = run_spmv_path(A2, x2, prec, args.steps, args.warmup, "27pt160", ref2, den2)
@@ -711,6 +804,7 @@ def main():
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline(A2, x2)
+        paths["cpu_omp_27pt160"] = cpu_omp(A2, x2, ref2, den2)
     del A2, x2, ref2, den2
 
     if args.only == "all":

@@ -213,6 +213,23 @@ __device__ __forceinline__ RowSlot<X> row_slot(const int32_t *__restrict__ rp,
   return s;
 }
 
+// s[a] + s[a + L] + ... (indices below b) with four independent partial
+// sums, so that four LDS reads are in flight at a time instead of one.
+// Every partial sum starts at -0.0 (see above).
+template <class X>
+__device__ __forceinline__ X lds_row_sum(const X *s, int a, int b, int L) {
+  X p0 = neg_zero<X>(), p1 = neg_zero<X>(), p2 = neg_zero<X>(), p3 = neg_zero<X>();
+  int j = a;
+  for (; j + 3 * L < b; j += 4 * L) {
+    p0 += s[j];
+    p1 += s[j + L];
+    p2 += s[j + 2 * L];
+    p3 += s[j + 3 * L];
+  }
+  for (; j < b; j += L) p0 += s[j];
+  return (p0 + p1) + (p2 + p3);
+}
+
 // Phase 2: every row of the tile summed out of LDS and added to C.
 template <class X, bool IND>
 __device__ __forceinline__ void tile_reduce(const int32_t *__restrict__ rp,
@@ -220,13 +237,11 @@ __device__ __forceinline__ void tile_reduce(const int32_t *__restrict__ rp,
                                             int p0, const RowSlot<X> &s, X *__restrict__ y,
                                             const X *s_prod) {
   if (nrows <= 2 * WG) {
-    X acc = neg_zero<X>();
-    for (int j = s.a0 + s.lane; j < s.b0; j += s.L) acc += s_prod[j];
+    X acc = lds_row_sum(s_prod, s.a0 + s.lane, s.b0, s.L);
     for (int off = s.L >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
     if (s.lane == 0 && s.b0 > s.a0) y[s.o0] = s.c0 + acc;
     if (nrows > WG) {
-      X acc1 = neg_zero<X>();
-      for (int j = s.a1; j < s.b1; ++j) acc1 += s_prod[j];
+      const X acc1 = lds_row_sum(s_prod, s.a1, s.b1, 1);
       if (s.b1 > s.a1) y[s.o1] = s.c1 + acc1;
     }
   } else {
@@ -234,8 +249,7 @@ __device__ __forceinline__ void tile_reduce(const int32_t *__restrict__ rp,
       const int ra = rp[r0 + rr] - p0;
       const int rb = rp[r0 + rr + 1] - p0;
       if (rb > ra) {
-        X acc = neg_zero<X>();
-        for (int j = ra; j < rb; ++j) acc += s_prod[j];
+        const X acc = lds_row_sum(s_prod, ra, rb, 1);
         int64_t oo;
         if constexpr (IND) oo = row_ids[r0 + rr];
         else oo = (int64_t)(r0 + rr);
