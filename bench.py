@@ -263,7 +263,8 @@ def measure_bandwidth(steps=20):
 def split_paths(A, x, steps, warmup):
     """The three schedules of Fig. 5 on one GPU: (a) blocking halo copy then
     the unsplit kernel, (b) split kernels with the copy serialised on the
-    compute stream, (c) split kernels with the copy overlapped."""
+    compute stream, (c) split kernels with the copy overlapped; then the full
+    exchange cycle with the send side, overlapped (d) and serialised (e)."""
     import torch
 
     import oracle
@@ -324,6 +325,29 @@ def split_paths(A, x, steps, warmup):
     log(f"split: (a) {ta['p50_ms']*1e3:.0f} us, (b) {tb['p50_ms']*1e3:.0f} us, "
         f"(c) {tc['p50_ms']*1e3:.0f} us, kernels only {tk['p50_ms']*1e3:.0f} us, "
         f"unsplit {tu['p50_ms']*1e3:.0f} us")
+
+    # (d) / (e): the whole exchange cycle of task mode (Sect. 3.5): the send
+    # list of the symmetric matrix is packed and copied to pinned host memory
+    # beside the halo copy and the local part (d), or all in order (e)
+    n_send = spmv.spmv_send_list_symmetric(s)
+    send = torch.empty(n_send, dtype=torch.float64).pin_memory()
+    idx = spmv.spmv_export(s, spmv.SPMV_ARR_SEND_IDX)
+    spmv.spmv_run_exchange(s, B, C, halo, send)
+    torch.cuda.synchronize()
+    exact = bool(np.array_equal(send.numpy().view(np.uint64),
+                                oracle.pack(idx, x).view(np.uint64)))
+    td = time_launches(lambda: spmv.spmv_run_exchange(s, B, C, halo, send), steps, warmup)
+    spmv.spmv_set_schedule(s, spmv.SPMV_SCHEDULE_SERIAL)
+    te = time_launches(lambda: spmv.spmv_run_exchange(s, B, C, halo, send), steps, warmup)
+    spmv.spmv_set_schedule(s, spmv.SPMV_SCHEDULE_OVERLAP)
+    res.update({
+        "n_send": n_send, "send_bytes": 8 * n_send, "send_buffer_bit_exact": exact,
+        "d_exchange_overlap_ms": td["p50_ms"], "e_exchange_serial_ms": te["p50_ms"],
+        "exchange_cost_over_c": td["p50_ms"] / tc["p50_ms"] - 1.0,
+        "exchange_overlap_speedup_vs_e": te["p50_ms"] / td["p50_ms"],
+    })
+    log(f"exchange: (d) {td['p50_ms']*1e3:.0f} us overlapped, (e) {te['p50_ms']*1e3:.0f} us "
+        f"serial, {n_send} elements sent, bit-exact {exact}")
     spmv.spmv_destroy(s)
     spmv.spmv_destroy(a)
     del B, C, Bc

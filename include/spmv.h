@@ -152,6 +152,46 @@ spmv_status_t spmv_run(spmv_handle_t h, const void *B, void *C,
                        const void *B_halo_host, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Send side of the exchange (Sect. 3.3: the elements another process needs
+ * are gathered into one contiguous send buffer; Sect. 3.5: in task mode that
+ * gather and the local part run while the communication proceeds).
+ *
+ * spmv_set_send_list (split handles only): send_idx[0 .. n_send) are
+ * positions in B of locally owned elements, each in [0, h) with h the
+ * handle's halo_begin_col, in send order; repeats are allowed.  The list is
+ * copied to device memory owned by the handle; n_send = 0 clears it.
+ * Errors: SPMV_ERR_UNSUPPORTED for plain and batch handles;
+ * SPMV_ERR_INVALID_ARG for n_send < 0, a NULL list with n_send > 0, or an
+ * index outside [0, h) (the message names the first).
+ *
+ * spmv_send_list_symmetric (split handles only): sets the send list for a
+ * structurally symmetric matrix to the rows i < h that hold an entry in a
+ * halo column, ascending.  By symmetry these are exactly the locally owned
+ * elements of B that the rows of the halo columns' owner reference.  *n_send
+ * receives the count.  One-time bookkeeping (synchronous).
+ *
+ * spmv_run_exchange (split handles only): one exchange cycle and the
+ * product, enqueued on `stream`:
+ *   1. send_buf[k] = B[send_idx[k]] (the pack kernel) and the copy of
+ *      send_buf to send_host, on the handle's send stream;
+ *   2. B_halo_host -> B[h:], on the handle's copy stream, as spmv_run does;
+ *   3. the local part on `stream`, while 1 and 2 proceed;
+ *   4. the nonlocal part on `stream`, after 2;
+ *   5. `stream` waits for 1, so send_host is complete once `stream` has
+ *      reached the end of the call.
+ * Under SPMV_SCHEDULE_SERIAL all five steps run in order on `stream`.
+ * send_host holds n_send elements of the handle's vector type (f64 in the
+ * F64 and F32_F64ACC modes, f32 otherwise) in pinned host memory; pageable
+ * memory is rejected as for B_halo_host; it may be NULL only if n_send is 0.
+ * The elements are copied bit for bit.  B_halo_host as for spmv_run.
+ * Errors as for spmv_run, plus SPMV_ERR_UNSUPPORTED for non-split handles.
+ * ------------------------------------------------------------------------- */
+spmv_status_t spmv_set_send_list(spmv_handle_t h, const int32_t *send_idx, int64_t n_send);
+spmv_status_t spmv_send_list_symmetric(spmv_handle_t h, int64_t *n_send);
+spmv_status_t spmv_run_exchange(spmv_handle_t h, const void *B, void *C,
+                                const void *B_halo_host, void *send_host, void *stream);
+
+/* ---------------------------------------------------------------------------
  * a8: block of k right-hand sides, C[:, t] = C[:, t] + A*B[:, t], t < k,
  * with A streamed once per column tile.  B is row-major [n_cols x ldb], C is
  * row-major [n_rows x ldc] (element (r, t) at r*ld + t), 1 <= k <= 64,
@@ -260,6 +300,7 @@ typedef struct spmv_info {
     int64_t n_tiles;       /* stream-kernel tiles of the main part */
     double row_len_mean, row_len_cv;
     int64_t row_len_max;
+    int64_t n_send;        /* split: entries of the send list; else 0 */
 } spmv_info_t;
 
 spmv_status_t spmv_get_info(spmv_handle_t h, spmv_info_t *info);
@@ -268,7 +309,8 @@ spmv_status_t spmv_get_info(spmv_handle_t h, spmv_info_t *info);
  * bytes (synchronous).  If dst is NULL only *size_bytes is set.
  *   SPMV_ARR_ROW_PTR, _COL, _VAL: the matrix (split: the local part), 0-based,
  *     val in storage precision (f64, f32 or bfloat16 codes as uint16);
- *   SPMV_ARR_NL_ROWS, _NL_PTR, _NL_COL, _NL_VAL: the nonlocal part. */
+ *   SPMV_ARR_NL_ROWS, _NL_PTR, _NL_COL, _NL_VAL: the nonlocal part;
+ *   SPMV_ARR_SEND_IDX: the send list (int32). */
 #define SPMV_ARR_ROW_PTR 0
 #define SPMV_ARR_COL 1
 #define SPMV_ARR_VAL 2
@@ -276,6 +318,7 @@ spmv_status_t spmv_get_info(spmv_handle_t h, spmv_info_t *info);
 #define SPMV_ARR_NL_PTR 4
 #define SPMV_ARR_NL_COL 5
 #define SPMV_ARR_NL_VAL 6
+#define SPMV_ARR_SEND_IDX 7
 
 spmv_status_t spmv_export(spmv_handle_t h, int32_t which, void *dst, int64_t bytes,
                           int64_t *size_bytes);

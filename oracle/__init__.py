@@ -7,7 +7,7 @@ from the GPU library.
 
 What each function computes is documented in ``spmv_oracle.c`` with the
 passage of the paper it follows (Listing 1 for the kernel, Sect. 3.4 for the
-local / nonlocal split).
+local / nonlocal split, Sect. 3.3 for the send buffer).
 """
 from __future__ import annotations
 
@@ -44,6 +44,8 @@ _SIGNATURES = {
     "oracle_split_count": [_i64, _p, _p, _i32, _i64, _p, _p, _p],
     "oracle_split_fill": [_i64, _p, _p, _p, _i32, _i64, _p, _p, _p, _p, _p, _p, _p],
     "oracle_spmv_split": [_i64, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p],
+    "oracle_pack": [_i64, _p, _p, _p],
+    "oracle_send_list_symmetric": [_i64, _p, _p, _i32, _i64, _p, _p],
     "oracle_round_f32": [_i64, _p, _p],
     "oracle_round_bf16": [_i64, _p, _p],
     "oracle_bf16_to_f64": [_i64, _p, _p],
@@ -164,6 +166,28 @@ class Oracle:
                                   _ptr(parts["nl_col"]), _ptr(parts["nl_val"]), _ptr(B), _ptr(C))
         return C
 
+    def pack(self, idx, B) -> np.ndarray:
+        """Send buffer B[idx] (Sect. 3.3)."""
+        idx = _c(idx, np.int32)
+        B = _c(B, np.float64)
+        if idx.size and (idx.min() < 0 or idx.max() >= B.size):
+            raise IndexError("send index out of range")
+        out = np.empty(idx.size, np.float64)
+        self._lib.oracle_pack(idx.size, _ptr(idx), _ptr(B), _ptr(out))
+        return out
+
+    def send_list_symmetric(self, row_ptr, col_idx, h: int, base: int = 0) -> np.ndarray:
+        """Rows i < h with an entry in a column >= h (send list of a
+        structurally symmetric matrix split at h)."""
+        row_ptr = _c(row_ptr, np.int32)
+        col_idx = _c(col_idx, np.int32)
+        n = row_ptr.size - 1
+        out = np.empty(max(n, 1), np.int32)
+        cnt = ctypes.c_int64()
+        self._lib.oracle_send_list_symmetric(n, _ptr(row_ptr), _ptr(col_idx), base, h, _ptr(out),
+                                             ctypes.byref(cnt))
+        return out[:cnt.value].copy()
+
     def round_f32(self, x) -> np.ndarray:
         x = _c(x, np.float64)
         out = np.empty(x.size, np.float32)
@@ -217,6 +241,14 @@ def split(*args, **kwargs):
 
 def spmv_split(*args, **kwargs):
     return default().spmv_split(*args, **kwargs)
+
+
+def pack(*args, **kwargs):
+    return default().pack(*args, **kwargs)
+
+
+def send_list_symmetric(*args, **kwargs):
+    return default().send_list_symmetric(*args, **kwargs)
 
 
 def round_f32(*args, **kwargs):

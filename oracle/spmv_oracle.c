@@ -21,6 +21,8 @@
  *   - Local / nonlocal split: Sect. 3.4 (first the part that uses local RHS
  *     elements only, then the remaining part once the halo has arrived; the
  *     result vector is updated twice).
+ *   - Send buffer: Sect. 3.3 (the elements other processes need, gathered
+ *     into one contiguous buffer).
  *
  * Index base: Listing 1 is written with 1-based (Fortran) indices.  Every
  * function takes `base` (0 or 1) and subtracts it from row_ptr and col_idx
@@ -192,6 +194,39 @@ void oracle_spmv_split(int64_t n_rows, const int32_t *loc_row_ptr, const int32_t
         }
         C[i] = c;
     }
+}
+
+/* ---------------------------------------------------------------------------
+ * Send side of the exchange (Sect. 3.3: the RHS elements another process
+ * needs are gathered into one contiguous send buffer before they are
+ * communicated).
+ * ------------------------------------------------------------------------- */
+
+/* The send buffer: out[k] = B[idx[k]] for k < n (0-based positions). */
+void oracle_pack(int64_t n, const int32_t *idx, const double *B, double *out)
+{
+    for (int64_t k = 0; k < n; ++k)
+        out[k] = B[idx[k]];
+}
+
+/* The send list of a structurally symmetric matrix whose columns [h, n_cols)
+ * belong to another process: every row i < h that holds at least one entry
+ * with column >= h, ascending.  An entry (i, j) with i < h <= j means, by
+ * symmetry, that the other process's row j uses column i, i.e. needs B[i].
+ * out has room for n_rows entries; *count receives the list length. */
+void oracle_send_list_symmetric(int64_t n_rows, const int32_t *row_ptr, const int32_t *col_idx,
+                                int32_t base, int64_t h, int32_t *out, int64_t *count)
+{
+    int64_t m = 0;
+    for (int64_t i = 0; i < n_rows && i < h; ++i) {
+        int needed = 0;
+        for (int64_t j = (int64_t)row_ptr[i] - base; j < (int64_t)row_ptr[i + 1] - base; ++j)
+            if ((int64_t)col_idx[j] - base >= h)
+                needed = 1;
+        if (needed)
+            out[m++] = (int32_t)i;
+    }
+    *count = m;
 }
 
 /* ---------------------------------------------------------------------------

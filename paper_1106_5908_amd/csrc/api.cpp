@@ -327,6 +327,11 @@ struct spmv_handle_s {
   int schedule = SPMV_SCHEDULE_OVERLAP;
   hipStream_t copy_stream = nullptr;
   hipEvent_t ev_start = nullptr, ev_copied = nullptr;
+  // split: send side of the exchange
+  DevBuf send_idx, send_buf;
+  int64_t n_send = 0;
+  hipStream_t send_stream = nullptr;
+  hipEvent_t ev_sent = nullptr;
   // batch
   int32_t count = 0;
   std::vector<int64_t> m_rows, m_cols;
@@ -346,6 +351,9 @@ struct spmv_handle_s {
 
   ~spmv_handle_s() {
     if (copy_stream) (void)hipStreamSynchronize(copy_stream);
+    if (send_stream) (void)hipStreamSynchronize(send_stream);
+    if (ev_sent) (void)hipEventDestroy(ev_sent);
+    if (send_stream) (void)hipStreamDestroy(send_stream);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
     if (ev_start) (void)hipEventDestroy(ev_start);
@@ -760,6 +768,8 @@ extern "C" spmv_status_t spmv_split_local_nonlocal(spmv_handle_t a_, int64_t hal
     hip_ok(hipStreamCreateWithFlags(&h->copy_stream, hipStreamNonBlocking), "copy stream");
     hip_ok(hipEventCreateWithFlags(&h->ev_start, hipEventDisableTiming), "event");
     hip_ok(hipEventCreateWithFlags(&h->ev_copied, hipEventDisableTiming), "event");
+    hip_ok(hipStreamCreateWithFlags(&h->send_stream, hipStreamNonBlocking), "send stream");
+    hip_ok(hipEventCreateWithFlags(&h->ev_sent, hipEventDisableTiming), "event");
     register_handle(h.get());
     *out_split = h.release();
   });
@@ -940,6 +950,16 @@ bool is_pinned_host(const void *p) {
   return attr.type == hipMemoryTypeHost;
 }
 
+// Host memory of a copy that must overlap: pinned, unless the handle allows
+// pageable memory (a pageable copy is staged by the runtime and does not
+// proceed beside the kernels; nonblocking is not asynchronous, Sect. 3.1).
+void require_pinned(const spmv_handle_s *h, const void *p, const char *what) {
+  if (!(h->flags & SPMV_FLAG_ALLOW_PAGEABLE_HALO) && !is_pinned_host(p))
+    fail(SPMV_ERR_INVALID_ARG,
+         std::string(what) + " is not pinned host memory (a pageable copy cannot overlap); "
+         "allocate it with hipHostMalloc or create the handle with SPMV_FLAG_ALLOW_PAGEABLE_HALO");
+}
+
 // Diagonal panels of a part without a row list: entries grouped by their
 // offset d = col - row into K equal slices of the part's offset range, each
 // slice a CRS over all rows (built on the device; synchronous).
@@ -1050,10 +1070,7 @@ extern "C" spmv_status_t spmv_run(spmv_handle_t h_, const void *B, void *C,
     const size_t vb = size_t(vec_bytes(h->prec));
     void *recv = static_cast<char *>(const_cast<void *>(B)) + size_t(h->halo_begin) * vb;
     const bool copy = B_halo_host && n_halo > 0;
-    if (copy && !(h->flags & SPMV_FLAG_ALLOW_PAGEABLE_HALO) && !is_pinned_host(B_halo_host))
-      fail(SPMV_ERR_INVALID_ARG,
-           "B_halo_host is not pinned host memory (a pageable copy cannot overlap); allocate it "
-           "with hipHostMalloc or create the handle with SPMV_FLAG_ALLOW_PAGEABLE_HALO");
+    if (copy) require_pinned(h, B_halo_host, "B_halo_host");
     if (copy && h->schedule == SPMV_SCHEDULE_OVERLAP) {
       hip_ok(hipEventRecord(h->ev_start, s), "event record");
       hip_ok(hipStreamWaitEvent(h->copy_stream, h->ev_start, 0), "stream wait");
@@ -1071,6 +1088,122 @@ extern "C" spmv_status_t spmv_run(spmv_handle_t h_, const void *B, void *C,
       run_part(h, h->main, B, C, s);
       run_part(h, h->nl, B, C, s);
     }
+  });
+}
+
+// ==== send side of the exchange (Sect. 3.3, 3.5) =======================================================
+
+namespace {
+
+void set_send_list(spmv_handle_s *h, const int32_t *idx, int64_t n) {
+  // the previous list may still be read by a call in flight
+  hip_ok(hipDeviceSynchronize(), "synchronize before replacing the send list");
+  h->send_idx.release();
+  h->send_buf.release();
+  h->n_send = 0;
+  if (n == 0) return;
+  const size_t vb = size_t(vec_bytes(h->prec));
+  upload(h->send_idx, idx, size_t(n) * 4, "send list");
+  h->send_buf.alloc(size_t(n) * vb, "send buffer");
+  h->n_send = n;
+}
+
+spmv_handle_s *split_handle(spmv_handle_t h_, const char *fn) {
+  spmv_handle_s *h = live(h_);
+  if (h->kind != SPMV_KIND_SPLIT) fail(SPMV_ERR_UNSUPPORTED, std::string(fn) + " needs a split handle");
+  return h;
+}
+
+}  // namespace
+
+extern "C" spmv_status_t spmv_set_send_list(spmv_handle_t h_, const int32_t *send_idx,
+                                            int64_t n_send) {
+  return guarded([&] {
+    spmv_handle_s *h = split_handle(h_, "spmv_set_send_list");
+    if (n_send < 0) fail(SPMV_ERR_INVALID_ARG, "n_send is negative");
+    if (n_send > 0 && !send_idx) fail(SPMV_ERR_INVALID_ARG, "send_idx is null");
+    if (n_send > INT32_MAX) fail(SPMV_ERR_INVALID_ARG, "n_send exceeds 2^31 - 1");
+    for (int64_t k = 0; k < n_send; ++k)
+      if (send_idx[k] < 0 || int64_t(send_idx[k]) >= h->halo_begin)
+        fail(SPMV_ERR_INVALID_ARG, "send_idx[" + std::to_string(k) + "] = " +
+                                       std::to_string(send_idx[k]) + " outside [0, " +
+                                       std::to_string(h->halo_begin) + ")");
+    DeviceGuard dg(h->device);
+    set_send_list(h, send_idx, n_send);
+  });
+}
+
+extern "C" spmv_status_t spmv_send_list_symmetric(spmv_handle_t h_, int64_t *n_send) {
+  return guarded([&] {
+    spmv_handle_s *h = split_handle(h_, "spmv_send_list_symmetric");
+    if (!n_send) fail(SPMV_ERR_INVALID_ARG, "n_send is null");
+    DeviceGuard dg(h->device);
+    // The nonlocal rows are ascending, so the rows below h are a prefix.
+    std::vector<int32_t> rows(size_t(h->nl.n_rows));
+    if (!rows.empty())
+      hip_ok(hipMemcpy(rows.data(), h->nl.row_ids.p, rows.size() * 4, hipMemcpyDeviceToHost),
+             "nonlocal rows readback");
+    const int64_t m = std::lower_bound(rows.begin(), rows.end(), int64_t(h->halo_begin),
+                                       [](int32_t r, int64_t v) { return int64_t(r) < v; }) -
+                      rows.begin();
+    set_send_list(h, rows.data(), m);
+    *n_send = m;
+  });
+}
+
+extern "C" spmv_status_t spmv_run_exchange(spmv_handle_t h_, const void *B, void *C,
+                                           const void *B_halo_host, void *send_host,
+                                           void *stream) {
+  return guarded([&] {
+    spmv_handle_s *h = split_handle(h_, "spmv_run_exchange");
+    if ((!B && h->n_cols > 0) || (!C && h->n_rows > 0)) fail(SPMV_ERR_INVALID_ARG, "B or C is null");
+    if (B && C && B == C) fail(SPMV_ERR_INVALID_ARG, "C must not alias B");
+    const int64_t ns = h->n_send;
+    if (ns > 0 && !send_host)
+      fail(SPMV_ERR_INVALID_ARG, "send_host is null but the send list has " + std::to_string(ns) +
+                                     " entries");
+    if (ns > 0) require_pinned(h, send_host, "send_host");
+    const int64_t n_halo = h->n_cols - h->halo_begin;
+    const size_t vb = size_t(vec_bytes(h->prec));
+    void *recv = static_cast<char *>(const_cast<void *>(B)) + size_t(h->halo_begin) * vb;
+    const bool copy = B_halo_host && n_halo > 0;
+    if (copy) require_pinned(h, B_halo_host, "B_halo_host");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DeviceGuard dg(h->device);
+    if (h->schedule == SPMV_SCHEDULE_SERIAL) {
+      if (ns > 0) {
+        hip_ok(launch_pack(int(vb), B, h->send_idx.as<int32_t>(), ns, h->send_buf.p, s), "pack");
+        hip_ok(hipMemcpyAsync(send_host, h->send_buf.p, size_t(ns) * vb, hipMemcpyDeviceToHost, s),
+               "send copy");
+      }
+      if (copy)
+        hip_ok(hipMemcpyAsync(recv, B_halo_host, size_t(n_halo) * vb, hipMemcpyHostToDevice, s),
+               "halo copy");
+      run_part(h, h->main, B, C, s);
+      run_part(h, h->nl, B, C, s);
+      return;
+    }
+    hip_ok(hipEventRecord(h->ev_start, s), "event record");
+    if (ns > 0) {
+      hip_ok(hipStreamWaitEvent(h->send_stream, h->ev_start, 0), "stream wait");
+      hip_ok(launch_pack(int(vb), B, h->send_idx.as<int32_t>(), ns, h->send_buf.p, h->send_stream),
+             "pack");
+      hip_ok(hipMemcpyAsync(send_host, h->send_buf.p, size_t(ns) * vb, hipMemcpyDeviceToHost,
+                            h->send_stream),
+             "send copy");
+      hip_ok(hipEventRecord(h->ev_sent, h->send_stream), "event record");
+    }
+    if (copy) {
+      hip_ok(hipStreamWaitEvent(h->copy_stream, h->ev_start, 0), "stream wait");
+      hip_ok(hipMemcpyAsync(recv, B_halo_host, size_t(n_halo) * vb, hipMemcpyHostToDevice,
+                            h->copy_stream),
+             "halo copy");
+      hip_ok(hipEventRecord(h->ev_copied, h->copy_stream), "event record");
+    }
+    run_part(h, h->main, B, C, s);
+    if (copy) hip_ok(hipStreamWaitEvent(s, h->ev_copied, 0), "stream wait");
+    run_part(h, h->nl, B, C, s);
+    if (ns > 0) hip_ok(hipStreamWaitEvent(s, h->ev_sent, 0), "stream wait");
   });
 }
 
@@ -1425,6 +1558,7 @@ extern "C" spmv_status_t spmv_get_info(spmv_handle_t h_, spmv_info_t *info) {
     info->row_len_mean = h->main.stats.mean;
     info->row_len_cv = h->main.stats.cv;
     info->row_len_max = h->main.stats.max;
+    info->n_send = h->n_send;
   });
 }
 
@@ -1444,6 +1578,7 @@ extern "C" spmv_status_t spmv_export(spmv_handle_t h_, int32_t which, void *dst,
       case SPMV_ARR_NL_PTR: if (split) { src = &h->nl.row_ptr; n = (h->nl.n_rows + 1) * 4; } break;
       case SPMV_ARR_NL_COL: if (split) { src = &h->nl.col; n = h->nl.nnz * 4; } break;
       case SPMV_ARR_NL_VAL: if (split) { src = &h->nl.val; n = h->nl.nnz * vb; } break;
+      case SPMV_ARR_SEND_IDX: if (split) { src = &h->send_idx; n = h->n_send * 4; } break;
       default: break;
     }
     if (!src) fail(SPMV_ERR_INVALID_ARG, "no such array in this handle");

@@ -122,6 +122,11 @@ hipError_t panel_fill(int prec, const int32_t *row_ptr, const int32_t *col, cons
                       int64_t n_rows, int64_t dmin, int64_t span, int K, const int32_t *starts,
                       const PanelOut &out, hipStream_t s);
 
+// ---- send side of the exchange (exchange.hip) -----------------------------------
+// out[k] = B[idx[k]] for k < n, copying words of word_bytes (4 or 8) bytes.
+hipError_t launch_pack(int word_bytes, const void *B, const int32_t *idx, int64_t n, void *out,
+                       hipStream_t s);
+
 // ---- probes (probes.hip) -------------------------------------------------------
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t s);
 hipError_t launch_triad(double *a, const double *b, const double *c, double sc, int64_t n,

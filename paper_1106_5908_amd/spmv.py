@@ -58,6 +58,7 @@ SPMV_ARR_NL_ROWS = 3
 SPMV_ARR_NL_PTR = 4
 SPMV_ARR_NL_COL = 5
 SPMV_ARR_NL_VAL = 6
+SPMV_ARR_SEND_IDX = 7
 
 SPMV_SCHEDULE_OVERLAP = 0
 SPMV_SCHEDULE_SERIAL = 1
@@ -70,6 +71,7 @@ EXPORTED = [
     "spmv_destroy", "spmv_last_error", "spmv_create_batch", "spmv_get_plan",
     "spmv_set_plan", "spmv_tune", "spmv_get_info", "spmv_export", "spmv_probe_copy",
     "spmv_probe_triad", "spmv_probe_read", "spmv_probe_spin", "spmv_set_schedule",
+    "spmv_set_send_list", "spmv_send_list_symmetric", "spmv_run_exchange",
 ]
 
 
@@ -94,7 +96,7 @@ class spmv_info_t(ctypes.Structure):
         ("nnz_nonlocal", ctypes.c_int64), ("n_nonlocal_rows", ctypes.c_int64),
         ("batch_count", ctypes.c_int32), ("n_tiles", ctypes.c_int64),
         ("row_len_mean", ctypes.c_double), ("row_len_cv", ctypes.c_double),
-        ("row_len_max", ctypes.c_int64),
+        ("row_len_max", ctypes.c_int64), ("n_send", ctypes.c_int64),
     ]
 
 
@@ -129,6 +131,9 @@ def load():
         "spmv_probe_spin": [_i64, _vp],
         "spmv_probe_read": [_vp, _i64, _vp, _i64, _vp],
         "spmv_set_schedule": [_vp, _i32],
+        "spmv_set_send_list": [_vp, _vp, _i64],
+        "spmv_send_list_symmetric": [_vp, _vp],
+        "spmv_run_exchange": [_vp, _vp, _vp, _vp, _vp, _vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -282,10 +287,16 @@ def spmv_run(h: Handle, B, C, B_halo_host=None, stream=None) -> None:
     """spmv_run: C = C + A*B on `stream` (default: torch's current stream).
 
     B_halo_host (split handles only) is a CPU torch tensor, preferably pinned."""
+    bp, cp, hp = _check_vectors(h, B, C, B_halo_host)
+    _check(load().spmv_run(_ptr(h), bp, cp, hp, _stream(stream)))
+
+
+def _check_vectors(h: Handle, B, C, B_halo_host):
+    """Pointers of B, C and the optional halo tensor after the size checks the
+    C side cannot make for device buffers."""
     dt = h.vec_dtype
     bp = _dev(B, dt, "B")
     cp = _dev(C, dt, "C")
-    # the C side cannot see device buffer sizes: check them here
     if B is None or B.numel() != h.n_cols or not B.is_contiguous():
         raise ValueError(f"B must be a contiguous tensor of {h.n_cols} elements")
     if C is None or C.numel() != h.n_rows or not C.is_contiguous():
@@ -297,7 +308,38 @@ def spmv_run(h: Handle, B, C, B_halo_host=None, stream=None) -> None:
         if B_halo_host.numel() != h.n_cols - h.halo_begin:
             raise ValueError(f"B_halo_host must hold {h.n_cols - h.halo_begin} elements")
         hp = ctypes.c_void_p(B_halo_host.data_ptr()) if B_halo_host.numel() else None
-    _check(load().spmv_run(_ptr(h), bp, cp, hp, _stream(stream)))
+    return bp, cp, hp
+
+
+def spmv_set_send_list(h: Handle, send_idx) -> None:
+    """spmv_set_send_list: positions in B (all below the halo start) whose
+    elements spmv_run_exchange sends, in send order."""
+    a = np.ascontiguousarray(send_idx, dtype=np.int32)
+    _check(load().spmv_set_send_list(_ptr(h), _hp(a), a.size))
+
+
+def spmv_send_list_symmetric(h: Handle) -> int:
+    """spmv_send_list_symmetric: send list of a structurally symmetric matrix;
+    returns its length."""
+    n = ctypes.c_int64()
+    _check(load().spmv_send_list_symmetric(_ptr(h), ctypes.byref(n)))
+    return n.value
+
+
+def spmv_run_exchange(h: Handle, B, C, B_halo_host=None, send_host=None, stream=None) -> None:
+    """spmv_run_exchange: pack and send B[send list] into send_host (a pinned
+    CPU tensor of the vector dtype), receive the halo, C = C + A*B."""
+    bp, cp, hp = _check_vectors(h, B, C, B_halo_host)
+    n_send = spmv_get_info(h)["n_send"]
+    sp = None
+    if send_host is not None:
+        dt = h.vec_dtype
+        if send_host.is_cuda or str(send_host.dtype) != "torch." + dt or not send_host.is_contiguous():
+            raise TypeError(f"send_host must be a contiguous CPU tensor of dtype {dt}")
+        if send_host.numel() != n_send:
+            raise ValueError(f"send_host must hold {n_send} elements")
+        sp = ctypes.c_void_p(send_host.data_ptr()) if send_host.numel() else None
+    _check(load().spmv_run_exchange(_ptr(h), bp, cp, hp, sp, _stream(stream)))
 
 
 def spmv_run_block(h: Handle, B, C, stream=None) -> None:
@@ -346,7 +388,7 @@ def spmv_get_info(h: Handle) -> dict:
 
 
 _EXPORT_DTYPE = {SPMV_ARR_ROW_PTR: np.int32, SPMV_ARR_COL: np.int32, SPMV_ARR_NL_ROWS: np.int32,
-                 SPMV_ARR_NL_PTR: np.int32, SPMV_ARR_NL_COL: np.int32}
+                 SPMV_ARR_NL_PTR: np.int32, SPMV_ARR_NL_COL: np.int32, SPMV_ARR_SEND_IDX: np.int32}
 
 
 def spmv_export(h: Handle, which: int) -> np.ndarray:

@@ -323,6 +323,75 @@ def check_split(O):
 
 
 # ----------------------------------------------------------------------------
+# Send side of the exchange (Sect. 3.3): hand-worked lists, the transposed
+# definition on random symmetric structures, bitwise gathers
+# ----------------------------------------------------------------------------
+
+def _grid5_structure(nx: int, ny: int):
+    """CRS structure of the 5-point stencil on an nx x ny grid, row x + nx*y,
+    built here from the neighbour description (no library code)."""
+    rp, ci = [0], []
+    for y in range(ny):
+        for x in range(nx):
+            i = x + nx * y
+            nb = [i]
+            if x > 0:
+                nb.append(i - 1)
+            if x < nx - 1:
+                nb.append(i + 1)
+            if y > 0:
+                nb.append(i - nx)
+            if y < ny - 1:
+                nb.append(i + nx)
+            ci.extend(sorted(nb))
+            rp.append(len(ci))
+    return np.array(rp, np.int32), np.array(ci, np.int32)
+
+
+def check_send(O):
+    g = read_golden("send_small.txt")
+    rp, ci = _grid5_structure(3, 3)
+    for h, key in ((6, "send_h6"), (4, "send_h4"), (9, "send_h9"), (0, "send_h0")):
+        for base in (0, 1):
+            got = O.send_list_symmetric(rp + base, ci + base, h, base=base)
+            assert got.tolist() == [int(v) for v in g[key]], (h, base)
+    out = O.pack([int(v) for v in g["pack_idx"]], [float(v) for v in g["pack_B"]])
+    assert out.tolist() == [float(v) for v in g["pack_out"]]
+
+    rng = gen.rng_for(903, 0)
+    # the send list equals the columns below h used by the rows at or above h
+    for n in (1, 2, 7, 40, 97):
+        for density in (0.05, 0.3):
+            S = rng.random((n, n)) < density
+            S = S | S.T
+            rows, cols = [0], []
+            for i in range(n):
+                c = np.flatnonzero(S[i])
+                rng.shuffle(c)  # storage order need not be sorted
+                cols.extend(c.tolist())
+                rows.append(len(cols))
+            rp2, ci2 = np.array(rows, np.int32), np.array(cols, np.int32)
+            for h in sorted({0, 1, n // 3, n // 2, n - 1, n}):
+                want = [j for j in range(h) if S[h:, j].any()]
+                assert O.send_list_symmetric(rp2, ci2, h).tolist() == want, (n, h)
+
+    # the gather copies bits: signed zeros and NaN payloads survive
+    B = rng.standard_normal(64)
+    B[3] = -0.0
+    B[7] = np.array([0x7FF8DEADBEEF0001], dtype=np.uint64).view(np.float64)[0]
+    B[9] = np.inf
+    ident = O.pack(np.arange(64), B)
+    assert np.array_equal(ident.view(np.uint64), B.view(np.uint64))
+    perm = rng.permutation(64)
+    back = np.empty(64)
+    back[perm] = O.pack(perm, B)
+    assert np.array_equal(back.view(np.uint64), B.view(np.uint64))
+    rep = O.pack(np.full(5, 7), B)
+    assert np.all(rep.view(np.uint64) == B[7:8].view(np.uint64))
+    assert O.pack(np.zeros(0, np.int32), B).size == 0
+
+
+# ----------------------------------------------------------------------------
 # Rounding to the storage precisions: exhaustive enumeration of the targets
 # ----------------------------------------------------------------------------
 
@@ -425,7 +494,7 @@ def check_round_f32(O):
 
 
 ALL_CHECKS = [check_rowsums, check_quadratics, check_sine_modes, check_bruteforce, check_rows,
-              check_block, check_split, check_round_bf16, check_round_f32]
+              check_block, check_split, check_send, check_round_bf16, check_round_f32]
 
 
 def run_all(O) -> list:

@@ -109,6 +109,35 @@ def test_irregular8M_split_overlap(c3):
         spmv.spmv_destroy(a)
 
 
+def test_irregular8M_exchange(c3):
+    """The full exchange cycle at the benchmark size: symmetric send list and
+    send buffer bit for bit, C to the FP64 bound."""
+    import torch
+
+    A, x, ref, den = c3
+    hb = gen.halo_begin(A.n_cols)
+    a = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, flags=NOTUNE)
+    s = spmv.spmv_split_local_nonlocal(a, hb)
+    try:
+        spmv.spmv_tune(s, 1)
+        n = spmv.spmv_send_list_symmetric(s)
+        want = oracle.send_list_symmetric(A.row_ptr, A.col_idx, hb)
+        assert np.array_equal(spmv.spmv_export(s, spmv.SPMV_ARR_SEND_IDX), want)
+        halo = torch.from_numpy(np.ascontiguousarray(x[hb:])).pin_memory()
+        send = torch.full((n,), float("nan"), dtype=torch.float64).pin_memory()
+        Bh = x.copy()
+        Bh[hb:] = np.nan
+        B = to_dev(Bh, "f64")
+        C = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+        spmv.spmv_run_exchange(s, B, C, halo, send)
+        torch.cuda.synchronize()
+        assert np.array_equal(send.numpy().view(np.uint64), oracle.pack(want, x).view(np.uint64))
+        assert_close(C.cpu().numpy(), ref, den, FP64_TOL, "exchange cycle, 8M rows")
+    finally:
+        spmv.spmv_destroy(s)
+        spmv.spmv_destroy(a)
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("k", [4, 8, 16])
 def test_block_irregular8M_sampled(k, prec, c3):

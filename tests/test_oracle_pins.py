@@ -63,6 +63,11 @@ MUTANTS = {
                        ("oracle_split_fill", "if (c < h)", "if (c <= h)")],
     "split_row_id": [("oracle_split_fill", "nl_rows[r] = (int32_t)i;", "nl_rows[r] = (int32_t)(i + 1);")],
     "split_drop_last_nl_row": [("oracle_spmv_split", "r < n_nl_rows;", "r < n_nl_rows - 1;")],
+    "send_boundary": [("oracle_send_list_symmetric", "- base >= h)", "- base > h)")],
+    "send_row_limit": [("oracle_send_list_symmetric", "i < n_rows && i < h;", "i < n_rows && i <= h;")],
+    "send_any_vs_all": [("oracle_send_list_symmetric", "needed = 1;", "needed = needed + 1;"),
+                        ("oracle_send_list_symmetric", "if (needed)", "if (needed == 1)")],
+    "pack_reversed": [("oracle_pack", "out[k] = B[idx[k]];", "out[k] = B[idx[n - 1 - k]];")],
     "bf16_ties_away": [("oracle_round_bf16", "nearbyint(q)", "round(q)")],
     "bf16_precision": [("oracle_round_bf16", "E - 7;", "E - 8;")],
     "bf16_subnormal_threshold": [("oracle_round_bf16", "(E < -126)", "(E < -127)")],
