@@ -260,6 +260,81 @@ def measure_bandwidth(steps=20):
     return out
 
 
+def kpm_path(A, R: int = 8, M: int = 64, reps: int = 5):
+    """Chebyshev moments of the kernel polynomial method (Sect. 1.3's
+    polynomial-expansion methods) on the matrix scaled into [-1, 1] by its
+    largest absolute row sum: R start vectors, M moments, ceil(M/2) block
+    products per call, timed against one block product alone."""
+    import torch
+
+    from paper_1106_5908_amd import spmv
+    from workloads import gen
+
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.row_ptr))
+    g = float(np.bincount(rows, weights=np.abs(A.val), minlength=A.n_rows).max())
+    val = A.val / (1.01 * g)
+    del rows
+    h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, val, A.n_cols,
+                             flags=spmv.SPMV_FLAG_NO_TUNE_CACHE)
+    del val
+    spmv.spmv_tune(h, R)
+    V0 = torch.from_numpy(gen.uniform_vector(A.n_rows * R, gen.rng_for(30, R)).reshape(A.n_rows, R)).to("cuda")
+    W1, W2 = torch.empty_like(V0), torch.empty_like(V0)
+    mu = spmv.spmv_kpm_moments(h, V0, M, W1, W2)
+    torch.cuda.synchronize()
+    norm2 = (V0 * V0).sum(dim=0)
+    bounded = bool(torch.all(mu.abs() <= norm2[None, :] * (1 + 1e-9)).item())
+    t = time_launches(lambda: spmv.spmv_kpm_moments(h, V0, M, W1, W2), reps, 1)
+    tb = time_launches(lambda: spmv.spmv_run_block(h, V0, W1), reps, 1)
+    products = (M + 1) // 2
+    flops = 2.0 * A.nnz * R * products
+    out = {"R": R, "M": M, "products_per_call": products, "ms_per_call": t["p50_ms"],
+           "moments_per_s": M * R / (t["p50_ms"] * 1e-3), "gflops_products": flops / (t["p50_ms"] * 1e6),
+           "block_product_ms": tb["p50_ms"], "frac_time_in_products": products * tb["p50_ms"] / t["p50_ms"],
+           "moments_bounded_by_norm": bounded, "scale": 1.01 * g,
+           "plan_block": spmv.spmv_get_plan(h)}
+    spmv.spmv_destroy(h)
+    del V0, W1, W2, mu
+    torch.cuda.empty_cache()
+    log(f"kpm: {M} moments x {R} vectors in {t['p50_ms']:.2f} ms ({products} block products of "
+        f"{tb['p50_ms']:.2f} ms; {out['frac_time_in_products'] * 100:.0f}% of the time), "
+        f"{out['gflops_products']:.0f} GFlop/s")
+    return out
+
+
+def atomic_probe(nnz27: int, n27: int, head_ms: float, iters: int = 100):
+    """FP64 atomic-add throughput into a 32 MB vector, coalesced and
+    scattered, and what it implies for the transposed half of a symmetric
+    (upper-triangle) product of the 27-point matrix: (nnz - N) / 2
+    contributions scattered into C."""
+    import torch
+
+    from paper_1106_5908_amd import spmv
+
+    C = torch.zeros(1 << 22, dtype=torch.float64, device="cuda")
+    out = {"target_bytes": 8 << 22}
+    for name, sc in (("coalesced", False), ("scattered", True)):
+        C.zero_()
+        made = spmv.spmv_probe_atomic(C, sc, iters)
+        torch.cuda.synchronize()
+        exact = float(C.sum().item()) == float(made)
+        t = time_launches(lambda: spmv.spmv_probe_atomic(C, sc, iters), 5, 2)
+        out[name] = {"atomics": made, "ms": t["p50_ms"], "G_per_s": made / (t["p50_ms"] * 1e6),
+                     "sum_exact": exact}
+    contrib = (nnz27 - n27) // 2
+    out["sym27_transposed_contributions"] = contrib
+    out["sym27_scatter_ms_at_coalesced_rate"] = contrib / (out["coalesced"]["G_per_s"] * 1e6)
+    out["sym27_scatter_ms_at_scattered_rate"] = contrib / (out["scattered"]["G_per_s"] * 1e6)
+    out["full_storage_product_ms"] = head_ms
+    del C
+    torch.cuda.empty_cache()
+    log(f"atomics: coalesced {out['coalesced']['G_per_s']:.1f} G/s, scattered "
+        f"{out['scattered']['G_per_s']:.1f} G/s; symmetric 27-point scatter alone >= "
+        f"{out['sym27_scatter_ms_at_coalesced_rate'] * 1e3:.0f} us vs full product "
+        f"{head_ms * 1e3:.0f} us")
+    return out
+
+
 def split_paths(A, x, steps, warmup):
     """The three schedules of Fig. 5 on one GPU: (a) blocking halo copy then
     the unsplit kernel, (b) split kernels with the copy serialised on the
@@ -819,6 +894,7 @@ def main():
 
     if args.only == "all":
         paths["headline_cold"] = cold_headline(A2, x2, head["plan"])
+        paths["atomic_probe"] = atomic_probe(A2.nnz, A2.n_rows, head["ms_per_step"])
         prec_rows = []
         for prec in ("f32", "bf16", "f32f64"):
             r, _, _ = run_spmv_path(A2, x2, prec, args.steps, args.warmup, "27pt160", ref2, den2)
@@ -848,6 +924,7 @@ def main():
         paths["split_irregular8M"] = sp
         paths["overlap_probe"] = overlap_probe()
         paths["block_irregular8M"] = block_paths(A3, max(10, args.steps // 4), 3, r3["ms_per_step"])
+        paths["kpm_irregular8M"] = kpm_path(A3)
         del A3, x3
         paths["batch_512_stencils"] = batch_paths(max(10, args.steps // 4), 3)
 

@@ -200,6 +200,34 @@ spmv_status_t spmv_run_exchange(spmv_handle_t h, const void *B, void *C,
 spmv_status_t spmv_run_block(spmv_handle_t h, int32_t k, const void *B, int64_t ldb,
                              void *C, int64_t ldc, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Chebyshev moments of the kernel polynomial method: the polynomial-expansion
+ * methods for spectral properties that the paper names among the algorithms
+ * whose time goes into spMVM (Sect. 1.3).  For R start vectors v0 (the
+ * columns of V0) and a matrix H whose spectrum the caller has scaled into
+ * [-1, 1]:
+ *   mu[m*R + r] = v0_r . T_m(H) v0_r,   m = 0 .. M-1,
+ * with the Chebyshev recursion v_{n+1} = 2 H v_n - v_{n-1} (v_1 = H v0) and
+ * the product relations mu_{2n} = 2 v_n.v_n - mu_0 and
+ * mu_{2n+1} = 2 v_{n+1}.v_n - mu_1, so M moments cost ceil(M/2) block
+ * products (spmv_run_block with k = R).
+ *
+ * h: plain SPMV_PREC_F64 handle of a square matrix.  R: a power of two in
+ * [1, 64].  1 <= M <= 2^20.  V0, W1, W2: device blocks of n_rows x R
+ * doubles, row-major (element (i, r) at i*R + r); V0 is read only, W1 and W2
+ * are work space overwritten by the call (on return they hold the last two
+ * vectors of the recursion, scaled).  mu: device array of M*R doubles.
+ * Everything is enqueued on `stream`; the dot products are reduced in a fixed
+ * order, so repeated calls give identical moments.  The handle keeps a small
+ * device buffer of partial sums (grown on the first call with a larger R,
+ * after a device synchronisation).
+ * Errors: SPMV_ERR_UNSUPPORTED for split, batch or non-F64 handles;
+ * SPMV_ERR_INVALID_ARG for a non-square matrix, R or M out of range, null or
+ * equal buffers.
+ * ------------------------------------------------------------------------- */
+spmv_status_t spmv_kpm_moments(spmv_handle_t h, int32_t R, int32_t M, const double *V0,
+                               double *W1, double *W2, double *mu, void *stream);
+
 /* Releases a handle and its device memory after waiting for the handle's
  * internal copy stream.  spmv_destroy(NULL) is SPMV_OK; a destroyed or
  * foreign handle gives SPMV_ERR_STATE. */
@@ -335,6 +363,11 @@ spmv_status_t spmv_export(spmv_handle_t h, int32_t which, void *dst, int64_t byt
  *                     the capacity of sums in doubles
  *   spmv_probe_spin   one wavefront waits `nanoseconds` on the GPU's constant-rate
  *                     clock without touching memory (at most 10 s)
+ *   spmv_probe_atomic 524288 threads each add 1.0 `iters` times (1 <= iters <=
+ *                     4096) into C[0, n) with FP64 atomics, n a power of two in
+ *                     [64, 2^31]; scattered = 0: each wavefront's 64 lanes hit
+ *                     64 consecutive elements, 1: hashed positions.  The sum
+ *                     of C grows by exactly 524288 * iters.
  * ------------------------------------------------------------------------- */
 spmv_status_t spmv_probe_copy(double *dst, const double *src, int64_t n, void *stream);
 spmv_status_t spmv_probe_triad(double *a, const double *b, const double *c, double s,
@@ -342,6 +375,8 @@ spmv_status_t spmv_probe_triad(double *a, const double *b, const double *c, doub
 spmv_status_t spmv_probe_read(const double *src, int64_t n, double *sums, int64_t sums_len,
                               void *stream);
 spmv_status_t spmv_probe_spin(int64_t nanoseconds, void *stream);
+spmv_status_t spmv_probe_atomic(double *C, int64_t n, int32_t scattered, int32_t iters,
+                                void *stream);
 
 /* Schedule used by spmv_run (for measurement and for callers that need it).
  * Split handles:

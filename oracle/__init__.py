@@ -44,6 +44,7 @@ _SIGNATURES = {
     "oracle_split_count": [_i64, _p, _p, _i32, _i64, _p, _p, _p],
     "oracle_split_fill": [_i64, _p, _p, _p, _i32, _i64, _p, _p, _p, _p, _p, _p, _p],
     "oracle_spmv_split": [_i64, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p],
+    "oracle_kpm_moments": [_i64, _p, _p, _p, _i32, _i32, _i32, _p, _p],
     "oracle_pack": [_i64, _p, _p, _p],
     "oracle_send_list_symmetric": [_i64, _p, _p, _i32, _i64, _p, _p],
     "oracle_round_f32": [_i64, _p, _p],
@@ -73,6 +74,7 @@ class Oracle:
             fn = getattr(lib, name)
             fn.argtypes = args
             fn.restype = None
+        lib.oracle_kpm_moments.restype = ctypes.c_int
         self._lib = lib
 
     def spmv(self, row_ptr, col_idx, val, B, C0=None, base: int = 0) -> np.ndarray:
@@ -166,6 +168,22 @@ class Oracle:
                                   _ptr(parts["nl_col"]), _ptr(parts["nl_val"]), _ptr(B), _ptr(C))
         return C
 
+    def kpm_moments(self, row_ptr, col_idx, val, V0, M: int, base: int = 0) -> np.ndarray:
+        """Chebyshev moments mu[m, r] = V0[:, r] . T_m(H) V0[:, r] by the plain
+        recursion (Sect. 1.3 applications); V0 is [n_rows x R]."""
+        row_ptr = _c(row_ptr, np.int32)
+        col_idx = _c(col_idx, np.int32)
+        val = _c(val, np.float64)
+        V0 = _c(V0, np.float64)
+        n = row_ptr.size - 1
+        assert V0.ndim == 2 and V0.shape[0] == n
+        R = V0.shape[1]
+        mu = np.empty((M, R), np.float64)
+        if self._lib.oracle_kpm_moments(n, _ptr(row_ptr), _ptr(col_idx), _ptr(val), base, R, M,
+                                        _ptr(V0), _ptr(mu)) != 0:
+            raise MemoryError("oracle_kpm_moments")
+        return mu
+
     def pack(self, idx, B) -> np.ndarray:
         """Send buffer B[idx] (Sect. 3.3)."""
         idx = _c(idx, np.int32)
@@ -241,6 +259,10 @@ def split(*args, **kwargs):
 
 def spmv_split(*args, **kwargs):
     return default().spmv_split(*args, **kwargs)
+
+
+def kpm_moments(*args, **kwargs):
+    return default().kpm_moments(*args, **kwargs)
 
 
 def pack(*args, **kwargs):

@@ -23,6 +23,8 @@
  *     result vector is updated twice).
  *   - Send buffer: Sect. 3.3 (the elements other processes need, gathered
  *     into one contiguous buffer).
+ *   - Chebyshev moments: the polynomial-expansion methods named in Sect. 1.3,
+ *     from the three-term recursion of the Chebyshev polynomials.
  *
  * Index base: Listing 1 is written with 1-based (Fortran) indices.  Every
  * function takes `base` (0 or 1) and subtracts it from row_ptr and col_idx
@@ -36,6 +38,7 @@
  */
 #include <math.h>
 #include <stdint.h>
+#include <stdlib.h>
 #include <string.h>
 
 /* Listing 1 over all rows: C[i] <- C[i] + sum_j val[j] * B[col_idx[j]]. */
@@ -194,6 +197,52 @@ void oracle_spmv_split(int64_t n_rows, const int32_t *loc_row_ptr, const int32_t
         }
         C[i] = c;
     }
+}
+
+/* ---------------------------------------------------------------------------
+ * Chebyshev moments of the kernel polynomial method (the polynomial-expansion
+ * methods for spectral properties the paper lists among the applications of
+ * spMVM, Sect. 1.3), by the plain definition: for each start vector v0 (column
+ * r of the row-major block V0, n_rows x R),
+ *   v_1 = H v0,  v_{m+1} = 2 H v_m - v_{m-1},  mu_m = v0 . v_m,
+ * with every product H v computed by the Listing 1 loop from a zero vector
+ * and every dot product summed in index order.  Returns 0, or -1 if memory
+ * for the three work vectors cannot be allocated.
+ * ------------------------------------------------------------------------- */
+int oracle_kpm_moments(int64_t n_rows, const int32_t *row_ptr, const int32_t *col_idx,
+                       const double *val, int32_t base, int32_t R, int32_t M,
+                       const double *V0, double *mu)
+{
+    size_t n = (size_t)(n_rows > 0 ? n_rows : 1);
+    double *prev = calloc(n, sizeof(double));
+    double *cur = calloc(n, sizeof(double));
+    double *hv = calloc(n, sizeof(double));
+    if (!prev || !cur || !hv) {
+        free(prev); free(cur); free(hv);
+        return -1;
+    }
+    for (int32_t r = 0; r < R; ++r) {
+        for (int64_t i = 0; i < n_rows; ++i)
+            cur[i] = V0[i * R + r];
+        for (int32_t m = 0; m < M; ++m) {
+            double d = 0.0;
+            for (int64_t i = 0; i < n_rows; ++i)
+                d = d + V0[i * R + r] * cur[i];
+            mu[(int64_t)m * R + r] = d;
+            if (m + 1 == M)
+                break;
+            for (int64_t i = 0; i < n_rows; ++i)
+                hv[i] = 0.0;
+            oracle_spmv(n_rows, row_ptr, col_idx, val, base, cur, hv);
+            for (int64_t i = 0; i < n_rows; ++i) {
+                double next = (m == 0) ? hv[i] : 2.0 * hv[i] - prev[i];
+                prev[i] = cur[i];
+                cur[i] = next;
+            }
+        }
+    }
+    free(prev); free(cur); free(hv);
+    return 0;
 }
 
 /* ---------------------------------------------------------------------------

@@ -348,6 +348,7 @@ struct spmv_handle_s {
   std::vector<BatchTile> h_btiles;
   std::vector<BatchDesc> h_desc;
   std::map<int, spmv_plan_t> block_plans;  // k -> plan chosen by spmv_tune
+  DevBuf kpm_part;                          // per-workgroup partial dot products
 
   ~spmv_handle_s() {
     if (copy_stream) (void)hipStreamSynchronize(copy_stream);
@@ -1233,19 +1234,9 @@ void run_block_part(spmv_handle_s *h, Part &p, int kt, int nt, int remap, int pa
          "block kernel launch");
 }
 
-}  // namespace
-
-extern "C" spmv_status_t spmv_run_block(spmv_handle_t h_, int32_t k, const void *B, int64_t ldb,
-                                        void *C, int64_t ldc, void *stream) {
-  return guarded([&] {
-    spmv_handle_s *h = live(h_);
-    if (h->kind != SPMV_KIND_PLAIN)
-      fail(SPMV_ERR_UNSUPPORTED, "spmv_run_block serves plain handles only");
-    if (k < 1 || k > 64) fail(SPMV_ERR_INVALID_ARG, "k must be in [1, 64]");
-    if (ldb < k || ldc < k) fail(SPMV_ERR_INVALID_ARG, "ldb and ldc must be >= k");
-    if ((!B && h->n_cols > 0) || (!C && h->n_rows > 0)) fail(SPMV_ERR_INVALID_ARG, "B or C is null");
-    if (B && C && B == C) fail(SPMV_ERR_INVALID_ARG, "C must not alias B");
-    DeviceGuard dg(h->device);
+// C = C + A*B for k columns of a plain handle (arguments already checked).
+void block_product(spmv_handle_s *h, int k, const void *B, int64_t ldb, void *C, int64_t ldc,
+                   hipStream_t s) {
     Part &p = h->main;
     // per-k choices made by spmv_tune for this handle, else the cache, else defaults
     int kt = p.plan.block_kt, nt = p.plan.nontemporal, panels = p.plan.panels;
@@ -1266,8 +1257,61 @@ extern "C" spmv_status_t spmv_run_block(spmv_handle_t h_, int32_t k, const void 
         h->block_plans[k] = c;
       }
     }
-    run_block_part(h, p, kt, nt, p.plan.xcd_remap, panels, k, B, ldb, C, ldc,
-                   static_cast<hipStream_t>(stream));
+    run_block_part(h, p, kt, nt, p.plan.xcd_remap, panels, k, B, ldb, C, ldc, s);
+}
+
+}  // namespace
+
+extern "C" spmv_status_t spmv_run_block(spmv_handle_t h_, int32_t k, const void *B, int64_t ldb,
+                                        void *C, int64_t ldc, void *stream) {
+  return guarded([&] {
+    spmv_handle_s *h = live(h_);
+    if (h->kind != SPMV_KIND_PLAIN)
+      fail(SPMV_ERR_UNSUPPORTED, "spmv_run_block serves plain handles only");
+    if (k < 1 || k > 64) fail(SPMV_ERR_INVALID_ARG, "k must be in [1, 64]");
+    if (ldb < k || ldc < k) fail(SPMV_ERR_INVALID_ARG, "ldb and ldc must be >= k");
+    if ((!B && h->n_cols > 0) || (!C && h->n_rows > 0)) fail(SPMV_ERR_INVALID_ARG, "B or C is null");
+    if (B && C && B == C) fail(SPMV_ERR_INVALID_ARG, "C must not alias B");
+    DeviceGuard dg(h->device);
+    block_product(h, k, B, ldb, C, ldc, static_cast<hipStream_t>(stream));
+  });
+}
+
+// ==== Chebyshev moments (kernel polynomial method) ======================================================
+
+extern "C" spmv_status_t spmv_kpm_moments(spmv_handle_t h_, int32_t R, int32_t M, const double *V0,
+                                          double *W1, double *W2, double *mu, void *stream) {
+  return guarded([&] {
+    spmv_handle_s *h = live(h_);
+    if (h->kind != SPMV_KIND_PLAIN)
+      fail(SPMV_ERR_UNSUPPORTED, "spmv_kpm_moments serves plain handles only");
+    if (h->prec != P_F64) fail(SPMV_ERR_UNSUPPORTED, "spmv_kpm_moments needs an SPMV_PREC_F64 handle");
+    if (h->n_rows != h->n_cols) fail(SPMV_ERR_INVALID_ARG, "the matrix must be square");
+    if (R < 1 || R > 64 || (R & (R - 1)) != 0)
+      fail(SPMV_ERR_INVALID_ARG, "R must be a power of two in [1, 64]");
+    if (M < 1 || M > (1 << 20)) fail(SPMV_ERR_INVALID_ARG, "M must be in [1, 2^20]");
+    if (!mu) fail(SPMV_ERR_INVALID_ARG, "mu is null");
+    if (h->n_rows > 0 && (!V0 || !W1 || !W2)) fail(SPMV_ERR_INVALID_ARG, "V0, W1 or W2 is null");
+    if (h->n_rows > 0 && (V0 == W1 || V0 == W2 || W1 == W2))
+      fail(SPMV_ERR_INVALID_ARG, "V0, W1 and W2 must be distinct");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DeviceGuard dg(h->device);
+    const size_t need = size_t(2) * KPM_GRID * size_t(R) * sizeof(double);
+    if (h->kpm_part.bytes < need) {
+      hip_ok(hipDeviceSynchronize(), "synchronize before growing the moment scratch");
+      h->kpm_part.alloc(need, "moment partial sums");
+    }
+    double *part = h->kpm_part.as<double>();
+    const int64_t n = h->n_rows;
+    hip_ok(launch_kpm_zero(W1, n * R, s), "zero fill");
+    block_product(h, R, V0, R, W1, R, s);  // W1 = H v0 = v1
+    hip_ok(launch_kpm_first(V0, W1, W2, n, R, part, M, mu, s), "moment kernels");
+    double *X = W1, *P = W2;  // X = v_n, P = -v_{n-1} / 2
+    for (int step = 1; 2 * step < M; ++step) {
+      block_product(h, R, X, R, P, R, s);  // P = H v_n - v_{n-1} / 2
+      hip_ok(launch_kpm_step(X, P, n, R, part, step, M, mu, s), "moment kernels");
+      std::swap(X, P);
+    }
   });
 }
 
@@ -1643,5 +1687,17 @@ extern "C" spmv_status_t spmv_probe_spin(int64_t nanoseconds, void *stream) {
     if (nanoseconds < 0 || nanoseconds > int64_t(10) * 1000 * 1000 * 1000)
       fail(SPMV_ERR_INVALID_ARG, "spin time must be in [0, 10 s]");
     hip_ok(launch_spin(nanoseconds, static_cast<hipStream_t>(stream)), "spin launch");
+  });
+}
+
+extern "C" spmv_status_t spmv_probe_atomic(double *C, int64_t n, int32_t scattered, int32_t iters,
+                                           void *stream) {
+  return guarded([&] {
+    if (!C) fail(SPMV_ERR_INVALID_ARG, "C is null");
+    if (n < 64 || n > (int64_t(1) << 31) || (n & (n - 1)) != 0)
+      fail(SPMV_ERR_INVALID_ARG, "n must be a power of two in [64, 2^31]");
+    if (scattered != 0 && scattered != 1) fail(SPMV_ERR_INVALID_ARG, "scattered must be 0 or 1");
+    if (iters < 1 || iters > 4096) fail(SPMV_ERR_INVALID_ARG, "iters must be in [1, 4096]");
+    hip_ok(launch_atomic(C, n, scattered, iters, static_cast<hipStream_t>(stream)), "atomic launch");
   });
 }

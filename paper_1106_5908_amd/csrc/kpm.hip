@@ -1,0 +1,148 @@
+// Vector kernels of the Chebyshev-moment loop of the kernel polynomial method
+// (the polynomial-expansion methods for spectral properties that Schubert,
+// Fehske, Hager, Wellein 2011 name as an application whose cost is the
+// spMV, Sect. 1.3).  The product itself is the block kernel; these kernels
+// do the O(N) work between products.
+//
+// Vectors are blocks of R columns stored row-major (element (i, r) at
+// i*R + r), R a power of two <= 64, as the block product reads and writes
+// them.  Every dot product is reduced in a fixed order (per-thread partial
+// sums, a per-workgroup tree, then one pass over the workgroups), so results
+// are reproducible from run to run.
+#include <hip/hip_runtime.h>
+
+#include "spmv_internal.h"
+
+namespace spmv {
+namespace {
+
+constexpr int WG = 256;
+
+// Thread t of the grid touches elements t, t + S, t + 2S, ... with the grid
+// size S a multiple of R, so all of them lie in column t % R.
+__device__ __forceinline__ void wg_column_sums(double a, double b, int R, double *s_a, double *s_b,
+                                               double *out_a, double *out_b) {
+  const int tid = threadIdx.x;
+  s_a[tid] = a;
+  s_b[tid] = b;
+  __syncthreads();
+  for (int off = WG / 2; off >= R; off >>= 1) {
+    if (tid < off) {
+      s_a[tid] += s_a[tid + off];
+      s_b[tid] += s_b[tid + off];
+    }
+    __syncthreads();
+  }
+  if (tid < R) {
+    out_a[(int64_t)blockIdx.x * R + tid] = s_a[tid];
+    out_b[(int64_t)blockIdx.x * R + tid] = s_b[tid];
+  }
+}
+
+// First step: with W1 = H v0 (v0 = V0), partial sums of <v0|v0> and
+// <W1|v0> per column, and W2 = -v0 / 2 (the scaled previous vector the
+// next product accumulates onto).
+__global__ __launch_bounds__(WG) void k_kpm_first(const double *__restrict__ V0,
+                                                  const double *__restrict__ W1,
+                                                  double *__restrict__ W2, int64_t n, int R,
+                                                  double *__restrict__ part_a,
+                                                  double *__restrict__ part_b) {
+  __shared__ double s_a[WG], s_b[WG];
+  const int64_t stride = (int64_t)gridDim.x * WG;
+  double a = 0.0, b = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x; e < n; e += stride) {
+    const double v = V0[e];
+    a += v * v;
+    b += W1[e] * v;
+    W2[e] = -0.5 * v;
+  }
+  wg_column_sums(a, b, R, s_a, s_b, part_a, part_b);
+}
+
+// Step n >= 1: X = v_n, P = H v_n - v_{n-1} / 2.  Sets P = 2 P = v_{n+1}
+// (exact scaling), takes partial sums of <v_n|v_n> and <v_{n+1}|v_n>, and
+// sets X = -v_n / 2 for the following product.
+__global__ __launch_bounds__(WG) void k_kpm_step(double *__restrict__ X, double *__restrict__ P,
+                                                 int64_t n, int R, double *__restrict__ part_a,
+                                                 double *__restrict__ part_b) {
+  __shared__ double s_a[WG], s_b[WG];
+  const int64_t stride = (int64_t)gridDim.x * WG;
+  double a = 0.0, b = 0.0;
+  for (int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x; e < n; e += stride) {
+    const double x = X[e];
+    const double p = 2.0 * P[e];
+    a += x * x;
+    b += p * x;
+    P[e] = p;
+    X[e] = -0.5 * x;
+  }
+  wg_column_sums(a, b, R, s_a, s_b, part_a, part_b);
+}
+
+// Sums the per-workgroup partials of each column in workgroup order and
+// writes the moments: first step (first != 0): mu[0] = <v0|v0>,
+// mu[1] = <v1|v0>; step n: mu[2n] = 2 <v_n|v_n> - mu[0],
+// mu[2n+1] = 2 <v_{n+1}|v_n> - mu[1]; moments at or past M are not written.
+// One workgroup; thread r < R handles column r.
+__global__ __launch_bounds__(64) void k_kpm_finish(const double *__restrict__ part_a,
+                                                   const double *__restrict__ part_b, int n_parts,
+                                                   int R, int first, int step, int M,
+                                                   double *__restrict__ mu) {
+  const int r = threadIdx.x;
+  if (r >= R) return;
+  double a = 0.0, b = 0.0;
+  for (int w = 0; w < n_parts; ++w) {
+    a += part_a[(int64_t)w * R + r];
+    b += part_b[(int64_t)w * R + r];
+  }
+  if (first) {
+    mu[r] = a;
+    if (M > 1) mu[(int64_t)R + r] = b;
+  } else {
+    const int m0 = 2 * step, m1 = 2 * step + 1;
+    if (m0 < M) mu[(int64_t)m0 * R + r] = 2.0 * a - mu[r];
+    if (m1 < M) mu[(int64_t)m1 * R + r] = 2.0 * b - mu[(int64_t)R + r];
+  }
+}
+
+__global__ __launch_bounds__(WG) void k_zero(double *__restrict__ p, int64_t n) {
+  const int64_t stride = (int64_t)gridDim.x * WG;
+  for (int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x; e < n; e += stride) p[e] = 0.0;
+}
+
+unsigned grid_for(int64_t n) {
+  const int64_t want = (n + WG - 1) / WG;
+  return (unsigned)(want < KPM_GRID ? (want > 0 ? want : 1) : KPM_GRID);
+}
+
+}  // namespace
+
+hipError_t launch_kpm_zero(double *p, int64_t n, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(k_zero, dim3(grid_for(n)), dim3(WG), 0, s, p, n);
+  return hipGetLastError();
+}
+
+hipError_t launch_kpm_first(const double *V0, const double *W1, double *W2, int64_t n_rows, int R,
+                            double *part, int M, double *mu, hipStream_t s) {
+  const int64_t n = n_rows * R;
+  const unsigned g = grid_for(n);
+  hipLaunchKernelGGL(k_kpm_first, dim3(g), dim3(WG), 0, s, V0, W1, W2, n, R, part,
+                     part + (int64_t)KPM_GRID * R);
+  hipLaunchKernelGGL(k_kpm_finish, dim3(1), dim3(64), 0, s, part, part + (int64_t)KPM_GRID * R,
+                     (int)g, R, 1, 0, M, mu);
+  return hipGetLastError();
+}
+
+hipError_t launch_kpm_step(double *X, double *P, int64_t n_rows, int R, double *part, int step,
+                           int M, double *mu, hipStream_t s) {
+  const int64_t n = n_rows * R;
+  const unsigned g = grid_for(n);
+  hipLaunchKernelGGL(k_kpm_step, dim3(g), dim3(WG), 0, s, X, P, n, R, part,
+                     part + (int64_t)KPM_GRID * R);
+  hipLaunchKernelGGL(k_kpm_finish, dim3(1), dim3(64), 0, s, part, part + (int64_t)KPM_GRID * R,
+                     (int)g, R, 0, step, M, mu);
+  return hipGetLastError();
+}
+
+}  // namespace spmv

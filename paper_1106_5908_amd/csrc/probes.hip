@@ -2,6 +2,9 @@
 //   copy / triad / read: the bandwidth ceilings the spMV is compared with, in the
 //     role the STREAM triad plays in Sect. 2 of Schubert, Fehske, Hager,
 //     Wellein 2011 (GPU stores do not write-allocate, so no 4/3 scaling);
+//   atomic: throughput of FP64 atomic adds into HBM, coalesced or scattered
+//     (what a scatter into C, such as the transposed half of a symmetric
+//     product, would pay per contribution);
 //   spin: a workgroup that stays busy for a given time without touching
 //     memory, the device-side "do_work" of the asynchrony test of Listing 2
 //     (Sect. 3.1), used to check that a host-to-device copy on another stream
@@ -86,6 +89,30 @@ __global__ void k_triad_tail(double *a, const double *b, const double *c, double
   if (threadIdx.x == 0) a[i] = b[i] + s * c[i];
 }
 
+// FP64 atomic adds of 1.0 into C[0, n) (n a power of two): each thread adds
+// `iters` times, at position (wave-block * 64 + lane) for the coalesced
+// pattern (a wave's 64 lanes hit 512 consecutive bytes) or at a hashed
+// position for the scattered one.  Vector global atomics only.
+__device__ __forceinline__ uint32_t mix32(uint32_t a) {
+  a ^= a >> 16;
+  a *= 0x7feb352du;
+  a ^= a >> 15;
+  a *= 0x846ca68bu;
+  a ^= a >> 16;
+  return a;
+}
+
+__global__ __launch_bounds__(WG) void k_atomic(double *__restrict__ C, uint32_t mask, int scattered,
+                                               int iters) {
+  const uint32_t g = blockIdx.x * (uint32_t)WG + threadIdx.x;
+  const uint32_t lane = threadIdx.x & 63u, wave = g >> 6;
+  for (int i = 0; i < iters; ++i) {
+    const uint32_t idx = scattered ? (mix32(g * 1009u + (uint32_t)i) & mask)
+                                   : (((wave * 977u + (uint32_t)i * 131u) * 64u + lane) & mask);
+    unsafeAtomicAdd(C + idx, 1.0);
+  }
+}
+
 // Busy-waits until `ticks` ticks of the constant-rate wall clock have passed.
 __global__ void k_spin(int64_t ticks) {
   const int64_t t0 = wall_clock64();
@@ -128,6 +155,12 @@ hipError_t launch_read(const double *src, int64_t n, double *sums, hipStream_t s
     hipLaunchKernelGGL(k_read, dim3((unsigned)nb), dim3(WG), 0, s,
                        reinterpret_cast<const dv2 *>(src), n2, sums);
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_atomic(double *C, int64_t n, int scattered, int iters, hipStream_t s) {
+  hipLaunchKernelGGL(k_atomic, dim3(ATOMIC_BLOCKS), dim3(WG), 0, s, C, (uint32_t)(n - 1),
+                     scattered, iters);
   return hipGetLastError();
 }
 

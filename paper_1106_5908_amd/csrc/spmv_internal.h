@@ -127,6 +127,15 @@ hipError_t panel_fill(int prec, const int32_t *row_ptr, const int32_t *col, cons
 hipError_t launch_pack(int word_bytes, const void *B, const int32_t *idx, int64_t n, void *out,
                        hipStream_t s);
 
+// ---- Chebyshev moments (kpm.hip) -----------------------------------------------
+// Blocks of R columns, row-major; part holds 2 * KPM_GRID * R doubles.
+constexpr int KPM_GRID = 1024;
+hipError_t launch_kpm_zero(double *p, int64_t n, hipStream_t s);
+hipError_t launch_kpm_first(const double *V0, const double *W1, double *W2, int64_t n_rows, int R,
+                            double *part, int M, double *mu, hipStream_t s);
+hipError_t launch_kpm_step(double *X, double *P, int64_t n_rows, int R, double *part, int step,
+                           int M, double *mu, hipStream_t s);
+
 // ---- probes (probes.hip) -------------------------------------------------------
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t s);
 hipError_t launch_triad(double *a, const double *b, const double *c, double sc, int64_t n,
@@ -135,5 +144,9 @@ hipError_t launch_spin(int64_t nanoseconds, hipStream_t s);
 // sums must hold read_sums_needed(n) doubles
 int64_t read_sums_needed(int64_t n);
 hipError_t launch_read(const double *src, int64_t n, double *sums, hipStream_t s);
+// ATOMIC_BLOCKS * 256 threads each add 1.0 `iters` times into C[0, n), n a
+// power of two >= 64.
+constexpr int ATOMIC_BLOCKS = 2048;
+hipError_t launch_atomic(double *C, int64_t n, int scattered, int iters, hipStream_t s);
 
 }  // namespace spmv

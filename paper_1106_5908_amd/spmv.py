@@ -71,7 +71,8 @@ EXPORTED = [
     "spmv_destroy", "spmv_last_error", "spmv_create_batch", "spmv_get_plan",
     "spmv_set_plan", "spmv_tune", "spmv_get_info", "spmv_export", "spmv_probe_copy",
     "spmv_probe_triad", "spmv_probe_read", "spmv_probe_spin", "spmv_set_schedule",
-    "spmv_set_send_list", "spmv_send_list_symmetric", "spmv_run_exchange",
+    "spmv_set_send_list", "spmv_send_list_symmetric", "spmv_run_exchange", "spmv_probe_atomic",
+    "spmv_kpm_moments",
 ]
 
 
@@ -134,6 +135,8 @@ def load():
         "spmv_set_send_list": [_vp, _vp, _i64],
         "spmv_send_list_symmetric": [_vp, _vp],
         "spmv_run_exchange": [_vp, _vp, _vp, _vp, _vp, _vp],
+        "spmv_probe_atomic": [_vp, _i64, _i32, _i32, _vp],
+        "spmv_kpm_moments": [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -356,6 +359,27 @@ def spmv_run_block(h: Handle, B, C, stream=None) -> None:
                                  C.stride(0), _stream(stream)))
 
 
+def spmv_kpm_moments(h: Handle, V0, M: int, W1=None, W2=None, stream=None):
+    """spmv_kpm_moments: Chebyshev moments mu[m, r] = v0_r . T_m(H) v0_r for
+    the columns of V0 (a CUDA float64 tensor [n_rows x R], row-major).  Work
+    blocks are allocated when not given.  Returns mu as a CUDA tensor [M x R]."""
+    import torch
+
+    if V0.dim() != 2 or V0.shape[0] != h.n_rows or not V0.is_contiguous():
+        raise ValueError(f"V0 must be a contiguous [{h.n_rows} x R] tensor")
+    R = V0.shape[1]
+    W1 = torch.empty_like(V0) if W1 is None else W1
+    W2 = torch.empty_like(V0) if W2 is None else W2
+    for name, W in (("W1", W1), ("W2", W2)):
+        if W.shape != V0.shape or not W.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous tensor shaped like V0")
+    mu = torch.empty((M, R), dtype=torch.float64, device=V0.device)
+    _check(load().spmv_kpm_moments(_ptr(h), R, M, _dev(V0, "float64", "V0"), _dev(W1, "float64", "W1"),
+                                   _dev(W2, "float64", "W2"), _dev(mu, "float64", "mu"),
+                                   _stream(stream)))
+    return mu
+
+
 def spmv_destroy(h: Handle) -> None:
     if h is None or not h.ptr:
         return
@@ -428,6 +452,17 @@ def spmv_probe_read(src, sums, stream=None) -> None:
 
 def read_sums_needed(n: int) -> int:
     return (n // 2 + 1023) // 1024 + 1
+
+
+ATOMIC_THREADS = 2048 * 256
+
+
+def spmv_probe_atomic(C, scattered: bool, iters: int, stream=None) -> int:
+    """FP64 atomic adds of 1.0 into C (float64, power-of-two length); returns
+    how many were made (ATOMIC_THREADS * iters)."""
+    _check(load().spmv_probe_atomic(_dev(C, "float64", "C"), C.numel(), int(bool(scattered)),
+                                    int(iters), _stream(stream)))
+    return ATOMIC_THREADS * int(iters)
 
 
 def spmv_probe_spin(nanoseconds: int, stream=None) -> None:

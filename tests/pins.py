@@ -392,6 +392,53 @@ def check_send(O):
 
 
 # ----------------------------------------------------------------------------
+# Chebyshev moments: exact sequences and the spectral closed form of the
+# Dirichlet Laplacian (eigenvectors are sine modes)
+# ----------------------------------------------------------------------------
+
+def _cheb(m: int, t: np.ndarray) -> np.ndarray:
+    return np.cos(m * np.arccos(np.clip(t, -1.0, 1.0)))
+
+
+def check_kpm(O):
+    # 1 x 1 matrix [0.5], v0 = 1: v_m = T_m(1/2) = cos(m pi / 3), every step exact
+    one = O.kpm_moments(np.array([0, 1], np.int32), np.array([0], np.int32), np.array([0.5]),
+                        np.ones((1, 1)), 13)
+    assert one[:, 0].tolist() == [[1.0, 0.5, -0.5, -1.0, -0.5, 0.5][m % 6] for m in range(13)]
+    # 1 x 1 matrix [-1], v0 = 3: mu_m = 9 (-1)^m; index base 1
+    neg = O.kpm_moments(np.array([1, 2], np.int32), np.array([1], np.int32), np.array([-1.0]),
+                        np.full((1, 1), 3.0), 6, base=1)
+    assert neg[:, 0].tolist() == [9.0 * (-1) ** m for m in range(6)]
+
+    # H = (L - 4 I) / 4.25 for the 5-point Laplacian L (4 / -1) on an n x n grid:
+    # eigenvalues -(2 cos(j pi/(n+1)) + 2 cos(k pi/(n+1))) / 4.25 with
+    # orthonormal eigenvectors s_j(x) s_k(y), s_j(x) = sqrt(2/(n+1)) sin(j pi (x+1)/(n+1))
+    n = 12
+    rp, ci = _grid5_structure(n, n)
+    rows = np.repeat(np.arange(n * n), np.diff(rp))
+    val = np.where(ci == rows, 0.0, -1.0 / 4.25)
+    rng = gen.rng_for(904, 0)
+    R, M = 3, 40
+    V0 = rng.standard_normal((n * n, R))
+    mu = O.kpm_moments(rp, ci, val, V0, M)
+    idx = np.arange(1, n + 1)
+    S = np.sqrt(2.0 / (n + 1)) * np.sin(np.pi * np.outer(idx, idx) / (n + 1))  # S[j-1, x]
+    lam = 2.0 * np.cos(idx * np.pi / (n + 1))
+    theta = -(lam[:, None] + lam[None, :]) / 4.25  # [k-1 (y), j-1 (x)]
+    for r in range(R):
+        c = S @ V0[:, r].reshape(n, n) @ S.T  # [k-1, j-1]: coefficient of mode (j, k)
+        norm2 = float(V0[:, r] @ V0[:, r])
+        for m in range(M):
+            want = float(np.sum(c * c * _cheb(m, theta)))
+            assert abs(mu[m, r] - want) <= 1e-12 * norm2, (r, m, mu[m, r], want)
+    # the moments of a start vector that is one eigenvector are T_m(theta) exactly in form
+    e = (S[2][:, None] * S[4][None, :]).T.reshape(-1)  # mode j = 3 (x), k = 5 (y)
+    mu_e = O.kpm_moments(rp, ci, val, e[:, None], 25)
+    th = -(lam[2] + lam[4]) / 4.25
+    assert np.allclose(mu_e[:, 0], _cheb(np.arange(25), th), rtol=0, atol=1e-13)
+
+
+# ----------------------------------------------------------------------------
 # Rounding to the storage precisions: exhaustive enumeration of the targets
 # ----------------------------------------------------------------------------
 
@@ -494,7 +541,7 @@ def check_round_f32(O):
 
 
 ALL_CHECKS = [check_rowsums, check_quadratics, check_sine_modes, check_bruteforce, check_rows,
-              check_block, check_split, check_send, check_round_bf16, check_round_f32]
+              check_block, check_split, check_send, check_kpm, check_round_bf16, check_round_f32]
 
 
 def run_all(O) -> list:

@@ -138,6 +138,30 @@ def test_irregular8M_exchange(c3):
         spmv.spmv_destroy(a)
 
 
+def test_irregular8M_kpm_moments(c3):
+    """Chebyshev moments at the benchmark size (two start vectors, four
+    moments; the oracle runs the plain recursion) to the bound derived in
+    test_gpu_kpm.py."""
+    import torch
+
+    A = c3[0]
+    rows = np.repeat(np.arange(A.n_rows), np.diff(A.row_ptr))
+    g = np.bincount(rows, weights=np.abs(A.val), minlength=A.n_rows).max()
+    val = A.val / (1.01 * g)
+    R, M = 2, 4
+    V0 = gen.uniform_vector(A.n_rows * R, gen.rng_for(31, 0)).reshape(A.n_rows, R)
+    h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, val, A.n_cols, flags=NOTUNE)
+    try:
+        spmv.spmv_tune(h, R)
+        mu = spmv.spmv_kpm_moments(h, torch.from_numpy(V0).to("cuda"), M).cpu().numpy()
+    finally:
+        spmv.spmv_destroy(h)
+    ref = oracle.kpm_moments(A.row_ptr, A.col_idx, val, V0, M)
+    nmax = int(np.diff(A.row_ptr).max())
+    tol = (4 * M * M * (nmax + 3) + 2 * A.n_rows) * 2.0 ** -53 * np.sum(V0 * V0, axis=0)
+    assert np.all(np.abs(mu - ref) <= tol[None, :]), np.abs(mu - ref).max()
+
+
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("k", [4, 8, 16])
 def test_block_irregular8M_sampled(k, prec, c3):

@@ -685,3 +685,16 @@ def test_probes():
     spmv.spmv_probe_spin(20_000_000)  # 20 ms
     torch.cuda.synchronize()
     assert time.perf_counter() - t0 >= 0.015
+    # atomic adds: every one lands (integer sums of 1.0 are exact)
+    for scattered in (False, True):
+        C = torch.zeros(1 << 16, dtype=torch.float64, device="cuda")
+        made = spmv.spmv_probe_atomic(C, scattered, 3)
+        torch.cuda.synchronize()
+        assert made == spmv.ATOMIC_THREADS * 3 and C.sum().item() == float(made)
+        if not scattered:
+            # each wavefront covers 64 consecutive slots per step: all slots are hit equally
+            assert torch.all(C == C[0]).item()
+    with pytest.raises(spmv.SpmvError):
+        spmv.spmv_probe_atomic(torch.zeros(100, dtype=torch.float64, device="cuda"), False, 1)
+    with pytest.raises(spmv.SpmvError):
+        spmv.spmv_probe_atomic(torch.zeros(64, dtype=torch.float64, device="cuda"), False, 0)

@@ -20,10 +20,10 @@ def test_pin(check):
 
 
 def _function_span(src: str, name: str):
-    m = re.search(r"^void %s\(" % re.escape(name), src, flags=re.M)
+    m = re.search(r"^(void|int) %s\(" % re.escape(name), src, flags=re.M)
     assert m, name
     start = m.start()
-    nxt = re.search(r"^(void|/\*) ", src[m.end():], flags=re.M)
+    nxt = re.search(r"^(void|int|/\*) ", src[m.end():], flags=re.M)
     end = m.end() + nxt.start() if nxt else len(src)
     return start, end
 
@@ -68,6 +68,11 @@ MUTANTS = {
     "send_any_vs_all": [("oracle_send_list_symmetric", "needed = 1;", "needed = needed + 1;"),
                         ("oracle_send_list_symmetric", "if (needed)", "if (needed == 1)")],
     "pack_reversed": [("oracle_pack", "out[k] = B[idx[k]];", "out[k] = B[idx[n - 1 - k]];")],
+    "kpm_no_factor_two": [("oracle_kpm_moments", ": 2.0 * hv[i] - prev[i];", ": hv[i] - prev[i];")],
+    "kpm_sign": [("oracle_kpm_moments", ": 2.0 * hv[i] - prev[i];", ": 2.0 * hv[i] + prev[i];")],
+    "kpm_first_step_doubled": [("oracle_kpm_moments", "(m == 0) ? hv[i]", "(m == 0) ? 2.0 * hv[i]")],
+    "kpm_dot_with_prev": [("oracle_kpm_moments", "d = d + V0[i * R + r] * cur[i];",
+                           "d = d + V0[i * R + r] * prev[i];")],
     "bf16_ties_away": [("oracle_round_bf16", "nearbyint(q)", "round(q)")],
     "bf16_precision": [("oracle_round_bf16", "E - 7;", "E - 8;")],
     "bf16_subnormal_threshold": [("oracle_round_bf16", "(E < -126)", "(E < -127)")],
