@@ -423,6 +423,38 @@ def split_paths(A, x, steps, warmup):
     })
     log(f"exchange: (d) {td['p50_ms']*1e3:.0f} us overlapped, (e) {te['p50_ms']*1e3:.0f} us "
         f"serial, {n_send} elements sent, bit-exact {exact}")
+
+    # per-phase events (copy, local, nonlocal, send) of schedules (c) and (d)
+    def phases(call, reps=20):
+        spmv.spmv_set_phase_timing(s, True)
+        rows = []
+        for _ in range(reps):
+            call()
+            torch.cuda.synchronize()
+            rows.append(spmv.spmv_phase_times(s))
+        spmv.spmv_set_phase_timing(s, False)
+        out = {}
+        for ph in spmv.PHASES:
+            spans = [r[ph] for r in rows if r[ph]]
+            if spans:
+                out[ph + "_ms"] = float(np.median([b - a for a, b in spans]))
+        for ph in ("copy", "send"):
+            ov = []
+            for r in rows:
+                if r[ph] and r["local"]:
+                    (a0, a1), (l0, l1) = r[ph], r["local"]
+                    ov.append(max(0.0, min(a1, l1) - max(a0, l0)) / max(a1 - a0, 1e-9))
+            if ov:
+                out[ph + "_share_during_local"] = float(np.median(ov))
+        out["call_ms"] = float(np.median([max(v[1] for v in r.values() if v) for r in rows]))
+        return out
+
+    res["phases_c"] = phases(lambda: spmv.spmv_run(s, B, C, halo))
+    res["phases_d"] = phases(lambda: spmv.spmv_run_exchange(s, B, C, halo, send))
+    pc, pd = res["phases_c"], res["phases_d"]
+    log(f"phases (c): copy {pc['copy_ms']*1e3:.0f} us ({pc['copy_share_during_local']*100:.0f}% under the "
+        f"local part {pc['local_ms']*1e3:.0f} us), nonlocal {pc['nonlocal_ms']*1e3:.0f} us; (d): send "
+        f"{pd['send_ms']*1e3:.0f} us ({pd['send_share_during_local']*100:.0f}% under the local part)")
     spmv.spmv_destroy(s)
     spmv.spmv_destroy(a)
     del B, C, Bc
@@ -747,6 +779,148 @@ def pmc_pass(steps: int, plan_json: str | None):
                       "copy_bytes_written": 8 * n}), flush=True)
 
 
+def trace_pass(steps: int):
+    """The split product of the irregular 8M matrix for a rocprofv3
+    --kernel-trace --memory-copy-trace run: `steps` calls of schedule (c)
+    (halo copy overlapped with the local part) and then `steps` calls of the
+    exchange cycle (d), each call alone between synchronisations, each
+    series preceded by a 2 ms spin kernel that marks it in the trace."""
+    import time
+
+    import torch
+
+    from paper_1106_5908_amd import spmv
+    from workloads import gen
+
+    A, x = gen.workload_c3()
+    hb = gen.halo_begin(A.n_cols)
+    a = make_handle(A, "f64", tune=False)
+    s = spmv.spmv_split_local_nonlocal(a, hb)
+    spmv.spmv_tune(s, 1)
+    n_send = spmv.spmv_send_list_symmetric(s)
+    halo = torch.from_numpy(np.ascontiguousarray(x[hb:])).pin_memory()
+    send = torch.empty(n_send, dtype=torch.float64).pin_memory()
+    B = dev_vec(x, "f64")
+    C = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+    for call in (lambda: spmv.spmv_run(s, B, C, halo),
+                 lambda: spmv.spmv_run_exchange(s, B, C, halo, send)):
+        call()
+        torch.cuda.synchronize()
+        spmv.spmv_probe_spin(2_000_000)
+        torch.cuda.synchronize()
+        for _ in range(steps):
+            time.sleep(0.002)
+            call()
+            torch.cuda.synchronize()
+    print(json.dumps({"trace_pass": "done", "steps": steps, "halo_bytes": 8 * (A.n_cols - hb),
+                      "send_bytes": 8 * n_send,
+                      "plans": {"local": spmv.spmv_get_plan(s, spmv.SPMV_PART_MAIN),
+                                "nonlocal": spmv.spmv_get_plan(s, spmv.SPMV_PART_NONLOCAL)}}),
+          flush=True)
+
+
+def _template_args(name: str):
+    i = name.find("<")
+    if i < 0:
+        return []
+    depth, j = 0, i
+    for j in range(i, len(name)):
+        depth += name[j] == "<"
+        depth -= name[j] == ">"
+        if depth == 0:
+            break
+    return [t.strip() for t in name[i + 1:j].split(",")]
+
+
+def summarize_trace(trace_dir, out_path, command):
+    """Per call of the two series in a trace_pass trace: the halo copy
+    (host to device), the send copy (device to host), the local-part kernels
+    (everything launched before the first nonlocal-part kernel) and the
+    nonlocal-part kernels (stream kernels with a row list), with how much of
+    each copy ran while local kernels ran."""
+    import csv
+
+    def load(pattern):
+        files = glob.glob(os.path.join(trace_dir, "**", pattern), recursive=True)
+        if not files:
+            raise SystemExit(f"no {pattern} under {trace_dir}")
+        return list(csv.DictReader(open(files[0])))
+
+    kern = load("*kernel_trace.csv")
+    copies = load("*memory_copy_trace.csv")
+    ev = []
+    for r in kern:
+        ev.append(("k", r["Kernel_Name"], int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    dcol = next((c for c in copies[0].keys() if c.lower() in ("direction", "operation", "kind")), None)
+    for r in copies:
+        d = (r.get(dcol, "") if dcol else "").upper()
+        kind = "h2d" if "HOST_TO_DEVICE" in d else ("d2h" if "DEVICE_TO_HOST" in d else "copy:" + d)
+        ev.append((kind, d, int(r["Start_Timestamp"]), int(r["End_Timestamp"])))
+    ev.sort(key=lambda e: e[2])
+    marks = [i for i, e in enumerate(ev) if e[0] == "k" and "k_spin" in e[1]]
+    if len(marks) < 2:
+        raise SystemExit("trace lacks the two marker spins")
+    series = {"c_split_overlap": ev[marks[0] + 1:marks[1]], "d_exchange": ev[marks[1] + 1:]}
+    lines = ["# Halo copy against the local part: rocprofv3 kernel and memory-copy trace",
+             f"# command: {command}",
+             "# per call: copy durations, local-part span, the share of each copy that ran while "
+             "local kernels ran, and the gap from the halo copy's end to the first nonlocal kernel"]
+    result = {}
+    for name, evs in series.items():
+        calls, cur, last_end = [], [], None
+        for e in evs:
+            if last_end is not None and e[2] - last_end > 1_000_000:  # 1 ms gap between calls
+                calls.append(cur)
+                cur = []
+            cur.append(e)
+            last_end = max(last_end or 0, e[3])
+        if cur:
+            calls.append(cur)
+        rows = []
+        for c in calls:
+            ks = [e for e in c if e[0] == "k"]
+            nl = [e for e in ks if "k_stream" in e[1] and _template_args(e[1])[-1:] == ["true"]]
+            first_nl = min((e[2] for e in nl), default=None)
+            loc = [e for e in ks if first_nl is None or e[2] < first_nl]
+            loc = [e for e in loc if "k_pack" not in e[1]]
+            h2d = [e for e in c if e[0] == "h2d"]
+            d2h = [e for e in c if e[0] == "d2h"]
+            if not loc or not h2d:
+                continue
+            l0, l1 = min(e[2] for e in loc), max(e[3] for e in loc)
+
+            def overlap(cp):
+                tot = sum(e[3] - e[2] for e in cp)
+                ov = sum(max(0, min(e[3], l1) - max(e[2], l0)) for e in cp)
+                return tot, (ov / tot if tot else 0.0)
+
+            th, oh = overlap(h2d)
+            td, od = overlap(d2h) if d2h else (0, 0.0)
+            gap = (first_nl - max(e[3] for e in h2d)) if first_nl is not None else None
+            span = max(e[3] for e in c) - min(e[2] for e in c)
+            rows.append((th, oh, td, od, l1 - l0, gap, span))
+        if not rows:
+            continue
+        a = np.array([[r[0], r[1], r[2], r[3], r[4], r[6]] for r in rows], dtype=float)
+        gaps = [r[5] for r in rows if r[5] is not None]
+        med = np.median(a, axis=0)
+        result[name] = {"calls": len(rows), "h2d_us": med[0] / 1e3, "h2d_overlap": med[1],
+                        "d2h_us": med[2] / 1e3, "d2h_overlap": med[3], "local_span_us": med[4] / 1e3,
+                        "call_span_us": med[5] / 1e3,
+                        "min_gap_copy_end_to_nonlocal_us": (min(gaps) / 1e3 if gaps else None)}
+        lines.append(f"{name}: {len(rows)} calls (medians)")
+        lines.append(f"  halo copy H2D {med[0] / 1e3:8.1f} us, {med[1] * 100:5.1f}% of it during local kernels")
+        if med[2]:
+            lines.append(f"  send copy D2H {med[2] / 1e3:8.1f} us, {med[3] * 100:5.1f}% of it during local kernels")
+        lines.append(f"  local part {med[4] / 1e3:8.1f} us, whole call {med[5] / 1e3:8.1f} us")
+        if gaps:
+            lines.append(f"  first nonlocal kernel starts {min(gaps) / 1e3:.1f} us (min) after the halo copy ends")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+    print(json.dumps(result))
+
+
 def _counter_rows(d):
     import csv
 
@@ -844,6 +1018,8 @@ def main():
                     help="plan (JSON) for the headline product instead of the autotuner's")
     ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "OUT", "PLAN_JSON"))
     ap.add_argument("--summarize-stats", nargs=3, metavar=("STATS_CSV", "OUT", "COMMAND"))
+    ap.add_argument("--trace-pass", action="store_true")
+    ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "OUT", "COMMAND"))
     args = ap.parse_args()
 
     if args.summarize_pmc:
@@ -851,6 +1027,9 @@ def main():
         return 0
     if args.summarize_stats:
         summarize_stats(*args.summarize_stats)
+        return 0
+    if args.summarize_trace:
+        summarize_trace(*args.summarize_trace)
         return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X and has no "
@@ -868,6 +1047,9 @@ def main():
     spmv.load()
     if args.pmc_pass:
         pmc_pass(args.steps, args.plan)
+        return 0
+    if args.trace_pass:
+        trace_pass(args.steps)
         return 0
 
     t_start = time.time()

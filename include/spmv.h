@@ -91,7 +91,9 @@ typedef enum spmv_precision {
  *   col_idx         host int32[nnz], columns in [base, n_cols + base)
  *   val             host double[nnz]
  *   index_base      0 or 1 (Listing 1 is written 1-based)
- *   prec, flags     see above
+ *   prec            a spmv_precision_t value, passed as int32_t (any other
+ *                   value gives SPMV_ERR_INVALID_ARG)
+ *   flags           see above
  *   out             receives the new handle (set to NULL on failure)
  *
  * Unsorted columns, duplicate columns (summed), explicit zeros and empty rows
@@ -104,7 +106,7 @@ typedef enum spmv_precision {
 spmv_status_t spmv_create_crs(int64_t n_rows, int64_t n_cols, int64_t nnz,
                               const int32_t *row_ptr, const int32_t *col_idx,
                               const double *val, int32_t index_base,
-                              spmv_precision_t prec, uint32_t flags,
+                              int32_t prec, uint32_t flags,
                               spmv_handle_t *out);
 
 /* ---------------------------------------------------------------------------
@@ -192,6 +194,26 @@ spmv_status_t spmv_run_exchange(spmv_handle_t h, const void *B, void *C,
                                 const void *B_halo_host, void *send_host, void *stream);
 
 /* ---------------------------------------------------------------------------
+ * Phase timing of split handles: the one-GPU form of the paper's breakdown of
+ * a process's time into communication, local and nonlocal calculation
+ * (Sect. 3.3-3.5, Fig. 5).
+ *
+ * spmv_set_phase_timing(h, on): with on != 0, later spmv_run and
+ * spmv_run_exchange calls on h record timing events at the start of the call
+ * and around each phase, on the stream the phase runs on; on = 0 stops it.
+ * spmv_phase_times(h, t): waits for the events of the last call and writes
+ * eight times in milliseconds from that call's start:
+ *   t[0], t[1] halo copy start / end      t[2], t[3] local part start / end
+ *   t[4], t[5] nonlocal part start / end  t[6], t[7] send side start / end
+ * (send side = pack kernel and copy of the send buffer); phases that did not
+ * run give -1.  Errors: SPMV_ERR_UNSUPPORTED for non-split handles,
+ * SPMV_ERR_STATE if timing is off or no call has run since it was switched
+ * on, SPMV_ERR_INVALID_ARG for a NULL t.
+ * ------------------------------------------------------------------------- */
+spmv_status_t spmv_set_phase_timing(spmv_handle_t h, int32_t on);
+spmv_status_t spmv_phase_times(spmv_handle_t h, double *t);
+
+/* ---------------------------------------------------------------------------
  * a8: block of k right-hand sides, C[:, t] = C[:, t] + A*B[:, t], t < k,
  * with A streamed once per column tile.  B is row-major [n_cols x ldb], C is
  * row-major [n_rows x ldc] (element (r, t) at r*ld + t), 1 <= k <= 64,
@@ -249,7 +271,7 @@ const char *spmv_last_error(void);
 spmv_status_t spmv_create_batch(int32_t count, const int64_t *n_rows, const int64_t *n_cols,
                                 const int64_t *nnz, const int32_t *const *row_ptr,
                                 const int32_t *const *col_idx, const double *const *val,
-                                int32_t index_base, spmv_precision_t prec, uint32_t flags,
+                                int32_t index_base, int32_t prec, uint32_t flags,
                                 spmv_handle_t *out);
 
 /* ---------------------------------------------------------------------------

@@ -327,6 +327,10 @@ struct spmv_handle_s {
   int schedule = SPMV_SCHEDULE_OVERLAP;
   hipStream_t copy_stream = nullptr;
   hipEvent_t ev_start = nullptr, ev_copied = nullptr;
+  // split: timing events of the last call's phases (see spmv_set_phase_timing)
+  bool timing = false;
+  hipEvent_t tev[9] = {};
+  bool tran[4] = {};  // phases that ran in the last timed call
   // split: send side of the exchange
   DevBuf send_idx, send_buf;
   int64_t n_send = 0;
@@ -354,6 +358,8 @@ struct spmv_handle_s {
     if (copy_stream) (void)hipStreamSynchronize(copy_stream);
     if (send_stream) (void)hipStreamSynchronize(send_stream);
     if (ev_sent) (void)hipEventDestroy(ev_sent);
+    for (hipEvent_t &e : tev)
+      if (e) (void)hipEventDestroy(e);
     if (send_stream) (void)hipStreamDestroy(send_stream);
     if (gexec) (void)hipGraphExecDestroy(gexec);
     if (graph) (void)hipGraphDestroy(graph);
@@ -569,7 +575,9 @@ void validate_crs(int64_t n_rows, int64_t n_cols, int64_t nnz, const int32_t *rp
   }
 }
 
-int check_prec(spmv_precision_t p) {
+// The mode arrives as a plain int (an enum parameter would make an unknown
+// value undefined behaviour before it could be checked).
+int check_prec(int32_t p) {
   if (p != SPMV_PREC_F64 && p != SPMV_PREC_F32 && p != SPMV_PREC_BF16_F32ACC &&
       p != SPMV_PREC_F32_F64ACC)
     fail(SPMV_ERR_INVALID_ARG, "unknown precision mode");
@@ -654,7 +662,7 @@ int current_device() {
 extern "C" spmv_status_t spmv_create_crs(int64_t n_rows, int64_t n_cols, int64_t nnz,
                                          const int32_t *row_ptr, const int32_t *col_idx,
                                          const double *val, int32_t index_base,
-                                         spmv_precision_t prec, uint32_t flags,
+                                         int32_t prec, uint32_t flags,
                                          spmv_handle_t *out) {
   return guarded([&] {
     if (!out) fail(SPMV_ERR_INVALID_ARG, "out is null");
@@ -783,7 +791,7 @@ extern "C" spmv_status_t spmv_create_batch(int32_t count, const int64_t *n_rows,
                                            const int32_t *const *row_ptr,
                                            const int32_t *const *col_idx,
                                            const double *const *val, int32_t index_base,
-                                           spmv_precision_t prec, uint32_t flags,
+                                           int32_t prec, uint32_t flags,
                                            spmv_handle_t *out) {
   return guarded([&] {
     if (!out) fail(SPMV_ERR_INVALID_ARG, "out is null");
@@ -954,6 +962,21 @@ bool is_pinned_host(const void *p) {
 // Host memory of a copy that must overlap: pinned, unless the handle allows
 // pageable memory (a pageable copy is staged by the runtime and does not
 // proceed beside the kernels; nonblocking is not asynchronous, Sect. 3.1).
+// Phase events of split handles: tev[0] the call's start; then start and
+// end of the halo copy (1, 2), the local part (3, 4), the nonlocal part
+// (5, 6) and the send side (7, 8).
+enum { T_START = 0, T_COPY = 1, T_LOCAL = 3, T_NONLOCAL = 5, T_SEND = 7 };
+
+void mark(spmv_handle_s *h, int i, hipStream_t s) {
+  if (h->timing) hip_ok(hipEventRecord(h->tev[i], s), "timing event");
+}
+
+void begin_timed_call(spmv_handle_s *h, hipStream_t s) {
+  if (!h->timing) return;
+  for (bool &r : h->tran) r = false;
+  mark(h, T_START, s);
+}
+
 void require_pinned(const spmv_handle_s *h, const void *p, const char *what) {
   if (!(h->flags & SPMV_FLAG_ALLOW_PAGEABLE_HALO) && !is_pinned_host(p))
     fail(SPMV_ERR_INVALID_ARG,
@@ -1072,23 +1095,40 @@ extern "C" spmv_status_t spmv_run(spmv_handle_t h_, const void *B, void *C,
     void *recv = static_cast<char *>(const_cast<void *>(B)) + size_t(h->halo_begin) * vb;
     const bool copy = B_halo_host && n_halo > 0;
     if (copy) require_pinned(h, B_halo_host, "B_halo_host");
+    begin_timed_call(h, s);
     if (copy && h->schedule == SPMV_SCHEDULE_OVERLAP) {
       hip_ok(hipEventRecord(h->ev_start, s), "event record");
       hip_ok(hipStreamWaitEvent(h->copy_stream, h->ev_start, 0), "stream wait");
+      mark(h, T_COPY, h->copy_stream);
       hip_ok(hipMemcpyAsync(recv, B_halo_host, size_t(n_halo) * vb, hipMemcpyHostToDevice,
                             h->copy_stream),
              "halo copy");
+      mark(h, T_COPY + 1, h->copy_stream);
       hip_ok(hipEventRecord(h->ev_copied, h->copy_stream), "event record");
+      mark(h, T_LOCAL, s);
       run_part(h, h->main, B, C, s);
+      mark(h, T_LOCAL + 1, s);
       hip_ok(hipStreamWaitEvent(s, h->ev_copied, 0), "stream wait");
+      mark(h, T_NONLOCAL, s);
       run_part(h, h->nl, B, C, s);
+      mark(h, T_NONLOCAL + 1, s);
     } else {
-      if (copy)
+      if (copy) {
+        mark(h, T_COPY, s);
         hip_ok(hipMemcpyAsync(recv, B_halo_host, size_t(n_halo) * vb, hipMemcpyHostToDevice, s),
                "halo copy");
+        mark(h, T_COPY + 1, s);
+      }
+      mark(h, T_LOCAL, s);
       run_part(h, h->main, B, C, s);
+      mark(h, T_LOCAL + 1, s);
+      mark(h, T_NONLOCAL, s);
       run_part(h, h->nl, B, C, s);
+      mark(h, T_NONLOCAL + 1, s);
     }
+    h->tran[0] = copy;
+    h->tran[1] = h->tran[2] = true;
+    h->tran[3] = false;
   });
 }
 
@@ -1171,40 +1211,95 @@ extern "C" spmv_status_t spmv_run_exchange(spmv_handle_t h_, const void *B, void
     if (copy) require_pinned(h, B_halo_host, "B_halo_host");
     hipStream_t s = static_cast<hipStream_t>(stream);
     DeviceGuard dg(h->device);
+    begin_timed_call(h, s);
+    h->tran[0] = copy;
+    h->tran[1] = h->tran[2] = true;
+    h->tran[3] = ns > 0;
     if (h->schedule == SPMV_SCHEDULE_SERIAL) {
       if (ns > 0) {
+        mark(h, T_SEND, s);
         hip_ok(launch_pack(int(vb), B, h->send_idx.as<int32_t>(), ns, h->send_buf.p, s), "pack");
         hip_ok(hipMemcpyAsync(send_host, h->send_buf.p, size_t(ns) * vb, hipMemcpyDeviceToHost, s),
                "send copy");
+        mark(h, T_SEND + 1, s);
       }
-      if (copy)
+      if (copy) {
+        mark(h, T_COPY, s);
         hip_ok(hipMemcpyAsync(recv, B_halo_host, size_t(n_halo) * vb, hipMemcpyHostToDevice, s),
                "halo copy");
+        mark(h, T_COPY + 1, s);
+      }
+      mark(h, T_LOCAL, s);
       run_part(h, h->main, B, C, s);
+      mark(h, T_LOCAL + 1, s);
+      mark(h, T_NONLOCAL, s);
       run_part(h, h->nl, B, C, s);
+      mark(h, T_NONLOCAL + 1, s);
       return;
     }
     hip_ok(hipEventRecord(h->ev_start, s), "event record");
     if (ns > 0) {
       hip_ok(hipStreamWaitEvent(h->send_stream, h->ev_start, 0), "stream wait");
+      mark(h, T_SEND, h->send_stream);
       hip_ok(launch_pack(int(vb), B, h->send_idx.as<int32_t>(), ns, h->send_buf.p, h->send_stream),
              "pack");
       hip_ok(hipMemcpyAsync(send_host, h->send_buf.p, size_t(ns) * vb, hipMemcpyDeviceToHost,
                             h->send_stream),
              "send copy");
+      mark(h, T_SEND + 1, h->send_stream);
       hip_ok(hipEventRecord(h->ev_sent, h->send_stream), "event record");
     }
     if (copy) {
       hip_ok(hipStreamWaitEvent(h->copy_stream, h->ev_start, 0), "stream wait");
+      mark(h, T_COPY, h->copy_stream);
       hip_ok(hipMemcpyAsync(recv, B_halo_host, size_t(n_halo) * vb, hipMemcpyHostToDevice,
                             h->copy_stream),
              "halo copy");
+      mark(h, T_COPY + 1, h->copy_stream);
       hip_ok(hipEventRecord(h->ev_copied, h->copy_stream), "event record");
     }
+    mark(h, T_LOCAL, s);
     run_part(h, h->main, B, C, s);
+    mark(h, T_LOCAL + 1, s);
     if (copy) hip_ok(hipStreamWaitEvent(s, h->ev_copied, 0), "stream wait");
+    mark(h, T_NONLOCAL, s);
     run_part(h, h->nl, B, C, s);
+    mark(h, T_NONLOCAL + 1, s);
     if (ns > 0) hip_ok(hipStreamWaitEvent(s, h->ev_sent, 0), "stream wait");
+  });
+}
+
+// ==== phase timing of split handles ====================================================================
+
+extern "C" spmv_status_t spmv_set_phase_timing(spmv_handle_t h_, int32_t on) {
+  return guarded([&] {
+    spmv_handle_s *h = split_handle(h_, "spmv_set_phase_timing");
+    DeviceGuard dg(h->device);
+    if (on && !h->tev[0])
+      for (hipEvent_t &e : h->tev) hip_ok(hipEventCreate(&e), "timing event");
+    h->timing = on != 0;
+    for (bool &r : h->tran) r = false;
+  });
+}
+
+extern "C" spmv_status_t spmv_phase_times(spmv_handle_t h_, double *t) {
+  return guarded([&] {
+    spmv_handle_s *h = split_handle(h_, "spmv_phase_times");
+    if (!t) fail(SPMV_ERR_INVALID_ARG, "t is null");
+    if (!h->timing) fail(SPMV_ERR_STATE, "phase timing is off (spmv_set_phase_timing)");
+    if (!h->tran[1]) fail(SPMV_ERR_STATE, "no call has run since phase timing was switched on");
+    DeviceGuard dg(h->device);
+    for (int i = 0; i < 8; ++i) t[i] = -1.0;
+    for (int p = 0; p < 4; ++p) {
+      if (!h->tran[p]) continue;
+      for (int j = 0; j < 2; ++j) {
+        hipEvent_t e = h->tev[1 + 2 * p + j];
+        hip_ok(hipEventSynchronize(e), "timing event");
+        float ms = 0.f;
+        hip_ok(hipEventElapsedTime(&ms, h->tev[T_START], e), "timing event");
+        t[2 * p + j] = double(ms);
+      }
+    }
   });
 }
 

@@ -19,7 +19,9 @@ from typing import Optional, Sequence
 import numpy as np
 
 _PKG = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_PKG, "libspmv.so")
+# SPMV_LIBRARY selects another build of the library (for example one with
+# host sanitizers); by default the in-tree libspmv.so is loaded.
+LIB_PATH = os.environ.get("SPMV_LIBRARY") or os.path.join(_PKG, "libspmv.so")
 
 # status codes
 SPMV_OK = 0
@@ -72,7 +74,7 @@ EXPORTED = [
     "spmv_set_plan", "spmv_tune", "spmv_get_info", "spmv_export", "spmv_probe_copy",
     "spmv_probe_triad", "spmv_probe_read", "spmv_probe_spin", "spmv_set_schedule",
     "spmv_set_send_list", "spmv_send_list_symmetric", "spmv_run_exchange", "spmv_probe_atomic",
-    "spmv_kpm_moments",
+    "spmv_kpm_moments", "spmv_set_phase_timing", "spmv_phase_times",
 ]
 
 
@@ -137,6 +139,8 @@ def load():
         "spmv_run_exchange": [_vp, _vp, _vp, _vp, _vp, _vp],
         "spmv_probe_atomic": [_vp, _i64, _i32, _i32, _vp],
         "spmv_kpm_moments": [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp],
+        "spmv_set_phase_timing": [_vp, _i32],
+        "spmv_phase_times": [_vp, _vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -343,6 +347,20 @@ def spmv_run_exchange(h: Handle, B, C, B_halo_host=None, send_host=None, stream=
             raise ValueError(f"send_host must hold {n_send} elements")
         sp = ctypes.c_void_p(send_host.data_ptr()) if send_host.numel() else None
     _check(load().spmv_run_exchange(_ptr(h), bp, cp, hp, sp, _stream(stream)))
+
+
+PHASES = ("copy", "local", "nonlocal", "send")
+
+
+def spmv_set_phase_timing(h: Handle, on: bool = True) -> None:
+    _check(load().spmv_set_phase_timing(_ptr(h), int(bool(on))))
+
+
+def spmv_phase_times(h: Handle) -> dict:
+    """{phase: (start_ms, end_ms) or None} of the last timed call, from its start."""
+    t = (ctypes.c_double * 8)()
+    _check(load().spmv_phase_times(_ptr(h), t))
+    return {p: (None if t[2 * i] < 0 else (t[2 * i], t[2 * i + 1])) for i, p in enumerate(PHASES)}
 
 
 def spmv_run_block(h: Handle, B, C, stream=None) -> None:

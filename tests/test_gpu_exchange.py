@@ -200,3 +200,92 @@ def test_validation():
     finally:
         spmv.spmv_destroy(s)
         spmv.spmv_destroy(a)
+
+
+@pytest.mark.parametrize("P", [2, 3, 5])
+def test_p_shares_exchange_cycle(P):
+    """P nnz-balanced row shares of a symmetric matrix, each with its columns
+    renumbered (owned first, then its halo): every share's exchange cycle on
+    the GPU reproduces its rows of the full product bit for bit (integer
+    data), and each share sends exactly what the others receive from it."""
+    import test_partition as tp
+
+    A = tp.integer_symmetric(30_000, gen.rng_for(951, P))
+    x = gen.integer_vector(A.n_cols, gen.rng_for(951, 100 + P))
+    full = oracle.spmv(A.row_ptr, A.col_idx, A.val, x)
+    cuts = tp.shares(A.row_ptr, P)
+    received, sent = {}, {}
+    for p in range(P):
+        r0, r1 = int(cuts[p]), int(cuts[p + 1])
+        rp, col, val, h, halo = tp.share_matrix(A, r0, r1)
+        Bp = np.concatenate([x[r0:r1], x[halo]])
+        a = spmv.spmv_create_crs(rp, col, val, h + halo.size, flags=NOTUNE)
+        s = spmv.spmv_split_local_nonlocal(a, h)
+        try:
+            n = spmv.spmv_send_list_symmetric(s)
+            C, send, recv = _exchange(s, Bp, h, "f64", n)
+            assert np.array_equal(recv, x[halo])
+            assert np.array_equal(C, full[r0:r1])
+            sent[p] = spmv.spmv_export(s, spmv.SPMV_ARR_SEND_IDX) + r0
+            assert np.array_equal(send, x[sent[p]])
+            received[p] = halo
+        finally:
+            spmv.spmv_destroy(s)
+            spmv.spmv_destroy(a)
+    for q in range(P):
+        r0, r1 = int(cuts[q]), int(cuts[q + 1])
+        wanted = np.unique(np.concatenate([received[p][(received[p] >= r0) & (received[p] < r1)]
+                                           for p in range(P) if p != q] + [np.zeros(0, np.int64)]))
+        assert np.array_equal(sent[q], wanted)
+
+
+def test_phase_timing():
+    """Per-phase events: ordering under both schedules (the nonlocal part after
+    the halo copy, everything after the call's start), and the error cases."""
+    import torch
+
+    A, x = _irregular()
+    hb = gen.halo_begin(A.n_cols)
+    a, s = _handles(A, hb)
+    eps = 0.01  # ms of event-timestamp slack
+    try:
+        with pytest.raises(spmv.SpmvError) as ei:
+            spmv.spmv_phase_times(s)
+        assert ei.value.status == spmv.SPMV_ERR_STATE
+        with pytest.raises(spmv.SpmvError) as ei:
+            spmv.spmv_set_phase_timing(a, True)
+        assert ei.value.status == spmv.SPMV_ERR_UNSUPPORTED
+        spmv.spmv_set_phase_timing(s, True)
+        with pytest.raises(spmv.SpmvError) as ei:
+            spmv.spmv_phase_times(s)
+        assert ei.value.status == spmv.SPMV_ERR_STATE
+        n = spmv.spmv_send_list_symmetric(s)
+        for schedule in MODES:
+            spmv.spmv_set_schedule(s, schedule)
+            for exchange in (False, True):
+                if exchange:
+                    _exchange(s, x, hb, "f64", n)
+                else:
+                    B = to_dev(x, "f64")
+                    C = to_dev(np.zeros(A.n_rows), "f64")
+                    spmv.spmv_run(s, B, C, torch.from_numpy(np.ascontiguousarray(x[hb:])).pin_memory())
+                    torch.cuda.synchronize()
+                t = spmv.spmv_phase_times(s)
+                assert t["copy"] and t["local"] and t["nonlocal"]
+                assert (t["send"] is not None) == exchange
+                for ph in t.values():
+                    if ph:
+                        assert -eps <= ph[0] <= ph[1] + eps
+                assert t["copy"][1] <= t["nonlocal"][0] + eps
+                assert t["local"][1] <= t["nonlocal"][0] + eps
+                if schedule == spmv.SPMV_SCHEDULE_SERIAL:
+                    assert t["copy"][1] <= t["local"][0] + eps
+                    if exchange:
+                        assert t["send"][1] <= t["copy"][0] + eps
+        spmv.spmv_set_phase_timing(s, False)
+        with pytest.raises(spmv.SpmvError) as ei:
+            spmv.spmv_phase_times(s)
+        assert ei.value.status == spmv.SPMV_ERR_STATE
+    finally:
+        spmv.spmv_destroy(s)
+        spmv.spmv_destroy(a)

@@ -286,6 +286,42 @@ def test_split_run_matches_oracle(schedule):
     assert_close(got, oracle.spmv_split(parts, x, c0), den, FP64_TOL, "split vs split oracle")
 
 
+@pytest.mark.parametrize("plan", [None, dict(kernel=1, tile_items=8, panels=4),
+                                  dict(kernel=2, lanes=8), dict(kernel=1, tile_items=16, tiles_per_group=4)],
+                         ids=["default", "panels4", "vector8", "pipelined"])
+def test_local_part_never_reads_halo(plan):
+    """The receive area B[h:] holds NaN and no halo is copied: rows without a
+    halo entry are computed by the local part alone and must be finite and
+    equal to the oracle's local product; a single read of the receive area by
+    the local kernel would make some of them NaN."""
+    import torch
+
+    A, x = mats()["irregular"]
+    h_begin = gen.halo_begin(A.n_cols)
+    a, s = _split_handles(A, h_begin)
+    try:
+        if plan:
+            spmv.spmv_set_plan(s, spmv.SPMV_PART_MAIN, **plan)
+        Bh = x.copy()
+        Bh[h_begin:] = np.nan
+        B = to_dev(Bh, "f64")
+        C = to_dev(np.zeros(A.n_rows), "f64")
+        spmv.spmv_run(s, B, C)
+        torch.cuda.synchronize()
+        got = C.cpu().numpy()
+    finally:
+        spmv.spmv_destroy(s)
+        spmv.spmv_destroy(a)
+    parts = oracle.split(A.row_ptr, A.col_idx, A.val, h_begin)
+    only_local = np.ones(A.n_rows, bool)
+    only_local[parts["nl_rows"]] = False
+    assert np.isnan(got[parts["nl_rows"]]).all()
+    assert np.isfinite(got[only_local]).all()
+    ref = oracle.spmv(parts["loc_row_ptr"], parts["loc_col"], parts["loc_val"], x)
+    den = oracle.abs_spmv(parts["loc_row_ptr"], parts["loc_col"], parts["loc_val"], x)
+    assert_close(got[only_local], ref[only_local], den[only_local], FP64_TOL, "local rows")
+
+
 def test_split_local_part_panels():
     import torch
 
