@@ -302,6 +302,41 @@ def kpm_path(A, R: int = 8, M: int = 64, reps: int = 5):
     return out
 
 
+def lanczos_path(A, spmv_ms: float, m: int = 100, reps: int = 3):
+    """Lanczos (the eigensolver Sect. 1.3 names first) on the symmetric
+    irregular matrix: m steps enqueued at once, timed per call; the per-step
+    cost against one product; the extreme Ritz values of the m x m
+    tridiagonal matrix."""
+    import torch
+    from scipy.linalg import eigvalsh_tridiagonal
+
+    from paper_1106_5908_amd import spmv
+    from workloads import gen
+
+    h = make_handle(A, "f64")
+    q = torch.from_numpy(gen.uniform_vector(A.n_rows, gen.rng_for(43, 0))).to("cuda")
+    V1, V2 = torch.empty_like(q), torch.empty_like(q)
+    a, b = spmv.spmv_lanczos(h, q, m, V1, V2)
+    torch.cuda.synchronize()
+    t = time_launches(lambda: spmv.spmv_lanczos(h, q, m, V1, V2), reps, 1)
+    a2, b2 = spmv.spmv_lanczos(h, q, m, V1, V2)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(a, a2) and torch.equal(b, b2))
+    an, bn = a.cpu().numpy(), b.cpu().numpy()
+    ritz = eigvalsh_tridiagonal(an, bn[:-1])
+    spmv.spmv_destroy(h)
+    del q, V1, V2
+    torch.cuda.empty_cache()
+    step = t["p50_ms"] / m
+    out = {"m": m, "ms_per_call": t["p50_ms"], "ms_per_step": step, "spmv_ms": spmv_ms,
+           "frac_time_in_products": spmv_ms / step, "ritz_min": float(ritz[0]), "ritz_max": float(ritz[-1]),
+           "last_beta": float(bn[-1]), "repeatable": same,
+           "gflops_products": 2.0 * A.nnz * m / (t["p50_ms"] * 1e6)}
+    log(f"lanczos: {m} steps in {t['p50_ms']:.1f} ms ({step * 1e3:.0f} us per step against "
+        f"{spmv_ms * 1e3:.0f} us per product), Ritz range [{ritz[0]:.4f}, {ritz[-1]:.4f}]")
+    return out
+
+
 def atomic_probe(nnz27: int, n27: int, head_ms: float, iters: int = 100):
     """FP64 atomic-add throughput into a 32 MB vector, coalesced and
     scattered, and what it implies for the transposed half of a symmetric
@@ -1107,6 +1142,7 @@ def main():
         paths["overlap_probe"] = overlap_probe()
         paths["block_irregular8M"] = block_paths(A3, max(10, args.steps // 4), 3, r3["ms_per_step"])
         paths["kpm_irregular8M"] = kpm_path(A3)
+        paths["lanczos_irregular8M"] = lanczos_path(A3, r3["ms_per_step"])
         del A3, x3
         paths["batch_512_stencils"] = batch_paths(max(10, args.steps // 4), 3)
 

@@ -250,6 +250,32 @@ spmv_status_t spmv_run_block(spmv_handle_t h, int32_t k, const void *B, int64_t 
 spmv_status_t spmv_kpm_moments(spmv_handle_t h, int32_t R, int32_t M, const double *V0,
                                double *W1, double *W2, double *mu, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * Lanczos: the iterative eigensolver the paper names first among the
+ * algorithms whose time goes into spMVM (Sect. 1.3), in its plain three-term
+ * form without reorthogonalisation:
+ *   v_1 = q / |q|, beta_0 = 0, and for j = 1 .. m
+ *   w = H v_j - beta_{j-1} v_{j-1}, alpha_j = w.v_j, w = w - alpha_j v_j,
+ *   beta_j = |w|, v_{j+1} = w / beta_j (0 once beta_j = 0).
+ * alpha[j-1] = alpha_j and beta[j-1] = beta_j, both written to device memory;
+ * the tridiagonal matrix of the m steps has diagonal alpha[0 .. m-1] and
+ * off-diagonal beta[0 .. m-2], whose eigenvalues (computed by the caller)
+ * approximate the extreme eigenvalues of H.  One product (spmv_run's kernel
+ * and plan) per step; everything is enqueued on `stream`, and dot products
+ * and norms are reduced in a fixed order, so repeated runs agree bit for bit.
+ *
+ * h: plain SPMV_PREC_F64 handle of a square matrix (symmetric for the method
+ * to make sense).  1 <= m <= 2^20.  q: start vector, n_rows doubles on the
+ * device (read only); V1, V2: device work vectors of n_rows doubles,
+ * overwritten; alpha, beta: device arrays of m doubles.  The handle's small
+ * reduction buffer is shared with spmv_kpm_moments.
+ * Errors: SPMV_ERR_UNSUPPORTED for split, batch or non-F64 handles;
+ * SPMV_ERR_INVALID_ARG for a non-square matrix, m out of range, null or
+ * equal buffers.
+ * ------------------------------------------------------------------------- */
+spmv_status_t spmv_lanczos(spmv_handle_t h, int32_t m, const double *q, double *V1, double *V2,
+                           double *alpha, double *beta, void *stream);
+
 /* Releases a handle and its device memory after waiting for the handle's
  * internal copy stream.  spmv_destroy(NULL) is SPMV_OK; a destroyed or
  * foreign handle gives SPMV_ERR_STATE. */

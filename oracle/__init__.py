@@ -45,6 +45,7 @@ _SIGNATURES = {
     "oracle_split_fill": [_i64, _p, _p, _p, _i32, _i64, _p, _p, _p, _p, _p, _p, _p],
     "oracle_spmv_split": [_i64, _p, _p, _p, _i64, _p, _p, _p, _p, _p, _p],
     "oracle_kpm_moments": [_i64, _p, _p, _p, _i32, _i32, _i32, _p, _p],
+    "oracle_lanczos": [_i64, _p, _p, _p, _i32, _i32, _p, _p, _p],
     "oracle_pack": [_i64, _p, _p, _p],
     "oracle_send_list_symmetric": [_i64, _p, _p, _i32, _i64, _p, _p],
     "oracle_round_f32": [_i64, _p, _p],
@@ -75,6 +76,7 @@ class Oracle:
             fn.argtypes = args
             fn.restype = None
         lib.oracle_kpm_moments.restype = ctypes.c_int
+        lib.oracle_lanczos.restype = ctypes.c_int
         self._lib = lib
 
     def spmv(self, row_ptr, col_idx, val, B, C0=None, base: int = 0) -> np.ndarray:
@@ -184,6 +186,22 @@ class Oracle:
             raise MemoryError("oracle_kpm_moments")
         return mu
 
+    def lanczos(self, row_ptr, col_idx, val, q, m: int, base: int = 0):
+        """m plain Lanczos steps from q (Sect. 1.3 applications): returns
+        (alpha[m], beta[m])."""
+        row_ptr = _c(row_ptr, np.int32)
+        col_idx = _c(col_idx, np.int32)
+        val = _c(val, np.float64)
+        q = _c(q, np.float64)
+        n = row_ptr.size - 1
+        assert q.size == n
+        alpha = np.empty(m, np.float64)
+        beta = np.empty(m, np.float64)
+        if self._lib.oracle_lanczos(n, _ptr(row_ptr), _ptr(col_idx), _ptr(val), base, m, _ptr(q),
+                                    _ptr(alpha), _ptr(beta)) != 0:
+            raise MemoryError("oracle_lanczos")
+        return alpha, beta
+
     def pack(self, idx, B) -> np.ndarray:
         """Send buffer B[idx] (Sect. 3.3)."""
         idx = _c(idx, np.int32)
@@ -263,6 +281,10 @@ def spmv_split(*args, **kwargs):
 
 def kpm_moments(*args, **kwargs):
     return default().kpm_moments(*args, **kwargs)
+
+
+def lanczos(*args, **kwargs):
+    return default().lanczos(*args, **kwargs)
 
 
 def pack(*args, **kwargs):

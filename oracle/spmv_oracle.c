@@ -25,6 +25,7 @@
  *     into one contiguous buffer).
  *   - Chebyshev moments: the polynomial-expansion methods named in Sect. 1.3,
  *     from the three-term recursion of the Chebyshev polynomials.
+ *   - Lanczos: the eigensolver named in Sect. 1.3, plain three-term form.
  *
  * Index base: Listing 1 is written with 1-based (Fortran) indices.  Every
  * function takes `base` (0 or 1) and subtracts it from row_ptr and col_idx
@@ -242,6 +243,65 @@ int oracle_kpm_moments(int64_t n_rows, const int32_t *row_ptr, const int32_t *co
         }
     }
     free(prev); free(cur); free(hv);
+    return 0;
+}
+
+/* ---------------------------------------------------------------------------
+ * Lanczos (the iterative eigensolver the paper names first among the
+ * algorithms whose time goes into spMVM, Sect. 1.3), without
+ * reorthogonalisation: v_1 = q / |q|, beta_0 = 0, and for j = 1 .. m
+ *   w = H v_j - beta_{j-1} v_{j-1},  alpha_j = w . v_j,
+ *   w = w - alpha_j v_j,             beta_j = |w|,
+ *   v_{j+1} = w / beta_j  (0 if beta_j = 0: the Krylov space is invariant).
+ * alpha[j-1] = alpha_j and beta[j-1] = beta_j; the tridiagonal matrix of the
+ * first m steps has diagonal alpha[0..m-1] and off-diagonal beta[0..m-2].
+ * Products by the Listing 1 loop from a zero vector; dot products and norms
+ * summed in index order.  Returns 0, or -1 if work memory cannot be
+ * allocated.
+ * ------------------------------------------------------------------------- */
+int oracle_lanczos(int64_t n_rows, const int32_t *row_ptr, const int32_t *col_idx,
+                   const double *val, int32_t base, int32_t m, const double *q,
+                   double *alpha, double *beta)
+{
+    size_t n = (size_t)(n_rows > 0 ? n_rows : 1);
+    double *prev = calloc(n, sizeof(double));
+    double *cur = calloc(n, sizeof(double));
+    double *w = calloc(n, sizeof(double));
+    if (!prev || !cur || !w) {
+        free(prev); free(cur); free(w);
+        return -1;
+    }
+    double nq = 0.0;
+    for (int64_t i = 0; i < n_rows; ++i)
+        nq = nq + q[i] * q[i];
+    nq = sqrt(nq);
+    for (int64_t i = 0; i < n_rows; ++i)
+        cur[i] = nq > 0.0 ? q[i] / nq : 0.0;
+    double b_prev = 0.0;
+    for (int32_t j = 0; j < m; ++j) {
+        for (int64_t i = 0; i < n_rows; ++i)
+            w[i] = 0.0;
+        oracle_spmv(n_rows, row_ptr, col_idx, val, base, cur, w);
+        for (int64_t i = 0; i < n_rows; ++i)
+            w[i] = w[i] - b_prev * prev[i];
+        double a = 0.0;
+        for (int64_t i = 0; i < n_rows; ++i)
+            a = a + w[i] * cur[i];
+        for (int64_t i = 0; i < n_rows; ++i)
+            w[i] = w[i] - a * cur[i];
+        double b = 0.0;
+        for (int64_t i = 0; i < n_rows; ++i)
+            b = b + w[i] * w[i];
+        b = sqrt(b);
+        alpha[j] = a;
+        beta[j] = b;
+        for (int64_t i = 0; i < n_rows; ++i) {
+            prev[i] = cur[i];
+            cur[i] = b > 0.0 ? w[i] / b : 0.0;
+        }
+        b_prev = b;
+    }
+    free(prev); free(cur); free(w);
     return 0;
 }
 

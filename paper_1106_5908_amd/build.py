@@ -14,7 +14,7 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libspmv.so")
 BUILD = os.path.join(PKG, "_build")
-SOURCES = ["kernels.hip", "split.hip", "probes.hip", "exchange.hip", "kpm.hip", "api.cpp"]
+SOURCES = ["kernels.hip", "split.hip", "probes.hip", "exchange.hip", "kpm.hip", "lanczos.hip", "api.cpp"]
 ARCH = os.environ.get("SPMV_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

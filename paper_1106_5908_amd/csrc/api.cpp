@@ -1410,6 +1410,40 @@ extern "C" spmv_status_t spmv_kpm_moments(spmv_handle_t h_, int32_t R, int32_t M
   });
 }
 
+// ==== Lanczos =========================================================================================
+
+extern "C" spmv_status_t spmv_lanczos(spmv_handle_t h_, int32_t m, const double *q, double *V1,
+                                      double *V2, double *alpha, double *beta, void *stream) {
+  return guarded([&] {
+    spmv_handle_s *h = live(h_);
+    if (h->kind != SPMV_KIND_PLAIN) fail(SPMV_ERR_UNSUPPORTED, "spmv_lanczos serves plain handles only");
+    if (h->prec != P_F64) fail(SPMV_ERR_UNSUPPORTED, "spmv_lanczos needs an SPMV_PREC_F64 handle");
+    if (h->n_rows != h->n_cols) fail(SPMV_ERR_INVALID_ARG, "the matrix must be square");
+    if (m < 1 || m > (1 << 20)) fail(SPMV_ERR_INVALID_ARG, "m must be in [1, 2^20]");
+    if (!alpha || !beta) fail(SPMV_ERR_INVALID_ARG, "alpha or beta is null");
+    if (h->n_rows > 0 && (!q || !V1 || !V2)) fail(SPMV_ERR_INVALID_ARG, "q, V1 or V2 is null");
+    if (h->n_rows > 0 && (q == V1 || q == V2 || V1 == V2))
+      fail(SPMV_ERR_INVALID_ARG, "q, V1 and V2 must be distinct");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DeviceGuard dg(h->device);
+    const size_t need = size_t(2) * KPM_GRID * sizeof(double);
+    if (h->kpm_part.bytes < need) {
+      hip_ok(hipDeviceSynchronize(), "synchronize before growing the reduction scratch");
+      h->kpm_part.alloc(need, "reduction partial sums");
+    }
+    double *part = h->kpm_part.as<double>();
+    const int64_t n = h->n_rows;
+    hip_ok(launch_lz_start(q, V1, n, part, s), "Lanczos kernels");
+    hip_ok(launch_kpm_zero(V2, n, s), "zero fill");
+    double *V = V1, *W = V2;  // V = v_j, W = -beta_{j-1} v_{j-1}
+    for (int j = 0; j < m; ++j) {
+      run_part(h, h->main, V, W, s);  // W = H v_j - beta_{j-1} v_{j-1}
+      hip_ok(launch_lz_step(W, V, n, part, alpha + j, beta + j, s), "Lanczos kernels");
+      std::swap(V, W);
+    }
+  });
+}
+
 // ==== destroy / errors ==================================================================================
 
 extern "C" spmv_status_t spmv_destroy(spmv_handle_t h) {

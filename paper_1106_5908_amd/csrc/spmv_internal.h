@@ -136,6 +136,14 @@ hipError_t launch_kpm_first(const double *V0, const double *W1, double *W2, int6
 hipError_t launch_kpm_step(double *X, double *P, int64_t n_rows, int R, double *part, int step,
                            int M, double *mu, hipStream_t s);
 
+// ---- Lanczos (lanczos.hip) ---------------------------------------------------------
+// part holds KPM_GRID + 1 doubles.  start: V = q / |q|.  step: with W = H v_j -
+// beta_{j-1} v_{j-1} and V = v_j, writes *alpha, *beta, leaves v_{j+1} in W and
+// -beta_j v_j in V.
+hipError_t launch_lz_start(const double *q, double *V, int64_t n, double *part, hipStream_t s);
+hipError_t launch_lz_step(double *W, double *V, int64_t n, double *part, double *alpha,
+                          double *beta, hipStream_t s);
+
 // ---- probes (probes.hip) -------------------------------------------------------
 hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t s);
 hipError_t launch_triad(double *a, const double *b, const double *c, double sc, int64_t n,

@@ -74,7 +74,7 @@ EXPORTED = [
     "spmv_set_plan", "spmv_tune", "spmv_get_info", "spmv_export", "spmv_probe_copy",
     "spmv_probe_triad", "spmv_probe_read", "spmv_probe_spin", "spmv_set_schedule",
     "spmv_set_send_list", "spmv_send_list_symmetric", "spmv_run_exchange", "spmv_probe_atomic",
-    "spmv_kpm_moments", "spmv_set_phase_timing", "spmv_phase_times",
+    "spmv_kpm_moments", "spmv_set_phase_timing", "spmv_phase_times", "spmv_lanczos",
 ]
 
 
@@ -141,6 +141,7 @@ def load():
         "spmv_kpm_moments": [_vp, _i32, _i32, _vp, _vp, _vp, _vp, _vp],
         "spmv_set_phase_timing": [_vp, _i32],
         "spmv_phase_times": [_vp, _vp],
+        "spmv_lanczos": [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -396,6 +397,26 @@ def spmv_kpm_moments(h: Handle, V0, M: int, W1=None, W2=None, stream=None):
                                    _dev(W2, "float64", "W2"), _dev(mu, "float64", "mu"),
                                    _stream(stream)))
     return mu
+
+
+def spmv_lanczos(h: Handle, q, m: int, V1=None, V2=None, stream=None):
+    """spmv_lanczos: m plain Lanczos steps from q (a CUDA float64 vector of
+    n_rows); returns (alpha, beta) as CUDA tensors of m elements."""
+    import torch
+
+    if q.dim() != 1 or q.numel() != h.n_rows or not q.is_contiguous():
+        raise ValueError(f"q must be a contiguous vector of {h.n_rows} elements")
+    V1 = torch.empty_like(q) if V1 is None else V1
+    V2 = torch.empty_like(q) if V2 is None else V2
+    for name, V in (("V1", V1), ("V2", V2)):
+        if V.shape != q.shape or not V.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous vector shaped like q")
+    alpha = torch.empty(m, dtype=torch.float64, device=q.device)
+    beta = torch.empty(m, dtype=torch.float64, device=q.device)
+    _check(load().spmv_lanczos(_ptr(h), m, _dev(q, "float64", "q"), _dev(V1, "float64", "V1"),
+                               _dev(V2, "float64", "V2"), _dev(alpha, "float64", "alpha"),
+                               _dev(beta, "float64", "beta"), _stream(stream)))
+    return alpha, beta
 
 
 def spmv_destroy(h: Handle) -> None:

@@ -439,6 +439,61 @@ def check_kpm(O):
 
 
 # ----------------------------------------------------------------------------
+# Lanczos: a matrix already in Lanczos form, the Gram-polynomial recurrence,
+# and termination on an invariant subspace of the Dirichlet Laplacian
+# ----------------------------------------------------------------------------
+
+def _laplace_1d(n):
+    rp, ci, vv = [0], [], []
+    for i in range(n):
+        for j, v in ((i - 1, -1.0), (i, 2.0), (i + 1, -1.0)):
+            if 0 <= j < n:
+                ci.append(j)
+                vv.append(v)
+        rp.append(len(ci))
+    return np.array(rp, np.int32), np.array(ci, np.int32), np.array(vv)
+
+
+def check_lanczos(O):
+    # tridiag(-1, 2, -1) from e_1 is its own Lanczos matrix: alpha = 2, beta = 1
+    # (every operation exact), in both index bases
+    rp, ci, vv = _laplace_1d(50)
+    q = np.zeros(50)
+    q[0] = 3.0
+    for base in (0, 1):
+        a, b = O.lanczos(rp + base, ci + base, vv, q, 20, base=base)
+        assert a.tolist() == [2.0] * 20 and b.tolist() == [1.0] * 20
+    # diag(0, 1, ..., N-1) from the vector of ones: the recurrence of the
+    # discrete Chebyshev (Gram) polynomials, alpha_j = (N-1)/2 and
+    # beta_j^2 = j^2 (N^2 - j^2) / (4 (4 j^2 - 1))
+    N = 30
+    a, b = O.lanczos(np.arange(N + 1, dtype=np.int32), np.arange(N, dtype=np.int32),
+                     np.arange(N, dtype=np.float64), np.ones(N), N - 1)
+    j = np.arange(1, N)
+    assert np.allclose(a, (N - 1) / 2, rtol=0, atol=1e-12)
+    assert np.allclose(b, np.sqrt(j * j * (N * N - j * j) / (4.0 * (4 * j * j - 1))), rtol=0, atol=1e-12)
+    # q in the span of k sine modes of the 12 x 12 Dirichlet 5-point Laplacian:
+    # after k steps beta_k vanishes and T_k has exactly those k eigenvalues
+    n = 12
+    rp2, ci2 = _grid5_structure(n, n)
+    rows = np.repeat(np.arange(n * n), np.diff(rp2))
+    val = np.where(ci2 == rows, 4.0, -1.0)
+    idx = np.arange(1, n + 1)
+    S = np.sqrt(2.0 / (n + 1)) * np.sin(np.pi * np.outer(idx, idx) / (n + 1))
+    lam = 2.0 - 2.0 * np.cos(idx * np.pi / (n + 1))
+    modes = [(1, 1), (2, 5), (7, 3), (12, 12)]
+    q = np.zeros(n * n)
+    for t, (jx, ky) in enumerate(modes):
+        q += (t + 1.0) * np.outer(S[ky - 1], S[jx - 1]).reshape(-1)  # [y, x] layout
+    k = len(modes)
+    a, b = O.lanczos(rp2, ci2, val, q, k)
+    assert abs(b[k - 1]) <= 1e-12 * 8
+    T = np.diag(a) + np.diag(b[:k - 1], 1) + np.diag(b[:k - 1], -1)
+    want = sorted(lam[jx - 1] + lam[ky - 1] for jx, ky in modes)
+    assert np.allclose(np.linalg.eigvalsh(T), want, rtol=0, atol=1e-12)
+
+
+# ----------------------------------------------------------------------------
 # Rounding to the storage precisions: exhaustive enumeration of the targets
 # ----------------------------------------------------------------------------
 
@@ -541,7 +596,8 @@ def check_round_f32(O):
 
 
 ALL_CHECKS = [check_rowsums, check_quadratics, check_sine_modes, check_bruteforce, check_rows,
-              check_block, check_split, check_send, check_kpm, check_round_bf16, check_round_f32]
+              check_block, check_split, check_send, check_kpm, check_lanczos, check_round_bf16,
+              check_round_f32]
 
 
 def run_all(O) -> list:

@@ -125,3 +125,36 @@ def test_probe_argument_checks():
     assert lib.spmv_probe_spin(-1, None) == spmv.SPMV_ERR_INVALID_ARG
     assert lib.spmv_probe_copy(None, None, 5, None) == spmv.SPMV_ERR_INVALID_ARG
     assert lib.spmv_probe_triad(None, None, None, 1.0, -1, None) == spmv.SPMV_ERR_INVALID_ARG
+
+
+def test_errors_are_per_thread():
+    """Failing calls from many threads at once: each thread reads its own
+    message (spmv_last_error is thread-local) and gets its own status."""
+    import threading
+
+    lib = spmv.load()
+    cases = [(dict(rp=[1, 2, 3]), "row_ptr[0]"), (dict(ci=[0, 3, 1]), "col_idx[1]"),
+             (dict(base=2), "index_base"), (dict(prec=9), "precision"),
+             (dict(n_cols=-1), "negative"), (dict(rp=[0, 4, 3], ci=[0, 2, 1]), "decreases")]
+    results = {}
+    barrier = threading.Barrier(len(cases) * 4)
+
+    def worker(i, case, msg):
+        barrier.wait()
+        for _ in range(200):
+            rp, ci, v, n_cols = GOOD
+            st, out, err = _create(case.get("rp", rp), case.get("ci", ci), v, case.get("n_cols", n_cols),
+                                   base=case.get("base", 0), prec=case.get("prec", 0))
+            if st == spmv.SPMV_OK or msg not in err or out is not None:
+                results[i] = (st, err)
+                return
+        results[i] = None
+
+    threads = [threading.Thread(target=worker, args=(4 * j + r, c, m))
+               for j, (c, m) in enumerate(cases) for r in range(4)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert all(v is None for v in results.values()), results
+    assert lib is spmv.load()

@@ -11,7 +11,10 @@ import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 BUILD = os.path.join(ROOT, "paper_1106_5908_amd", "_build")
-OBJS = ["kernels.o", "split.o", "probes.o", "exchange.o", "kpm.o"]
+def _device_objects():
+    from paper_1106_5908_amd import build as b
+
+    return [os.path.splitext(src)[0] + ".o" for src in b.SOURCES if src.endswith(".hip")]
 
 
 def _lib(name):
@@ -23,7 +26,7 @@ def _lib(name):
 @pytest.mark.skipif(shutil.which("g++") is None or _lib("libasan.so") is None
                     or not os.path.isdir("/opt/rocm/include"), reason="toolchain missing")
 def test_host_runtime_under_sanitizers(tmp_path):
-    objs = [os.path.join(BUILD, o) for o in OBJS]
+    objs = [os.path.join(BUILD, o) for o in _device_objects()]
     if not all(os.path.exists(o) for o in objs):
         pytest.skip("device objects not built (run the package build first)")
     api_o = str(tmp_path / "api_san.o")

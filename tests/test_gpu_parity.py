@@ -165,6 +165,46 @@ def test_determinism():
     assert np.array_equal(a, b)
 
 
+def test_handles_on_threads_and_streams():
+    """Two handles driven from two host threads, each on a stream of its own
+    (default priority), 20 products each: both results equal the same
+    products run from one thread."""
+    import threading
+
+    import torch
+
+    work = {"27pt": mats()["27pt"], "irregular": mats()["irregular"]}
+    ref = {k: gpu_spmv(A, x, runs=20) for k, (A, x) in work.items()}
+    out, errs = {}, []
+
+    def run(key):
+        try:
+            A, x = work[key]
+            st = torch.cuda.Stream()
+            h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, flags=NOTUNE)
+            try:
+                with torch.cuda.stream(st):
+                    B = to_dev(x, "f64")
+                    C = to_dev(np.zeros(A.n_rows), "f64")
+                    for _ in range(20):
+                        spmv.spmv_run(h, B, C, stream=st)
+                st.synchronize()
+                out[key] = C.cpu().numpy()
+            finally:
+                spmv.spmv_destroy(h)
+        except Exception as e:  # reported below
+            errs.append(repr(e))
+
+    threads = [threading.Thread(target=run, args=(k,)) for k in work]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join()
+    assert not errs, errs
+    for k in work:
+        assert np.array_equal(out[k], ref[k]), k
+
+
 def test_accumulates_into_c():
     A, x = mats()["27pt"]
     xi = np.round(x * 8)

@@ -73,6 +73,11 @@ MUTANTS = {
     "kpm_first_step_doubled": [("oracle_kpm_moments", "(m == 0) ? hv[i]", "(m == 0) ? 2.0 * hv[i]")],
     "kpm_dot_with_prev": [("oracle_kpm_moments", "d = d + V0[i * R + r] * cur[i];",
                            "d = d + V0[i * R + r] * prev[i];")],
+    "lanczos_no_prev": [("oracle_lanczos", "w[i] = w[i] - b_prev * prev[i];", "w[i] = w[i];")],
+    "lanczos_alpha_sign": [("oracle_lanczos", "w[i] = w[i] - a * cur[i];", "w[i] = w[i] + a * cur[i];")],
+    "lanczos_beta_not_sqrt": [("oracle_lanczos", "b = sqrt(b);", "b = b;")],
+    "lanczos_unnormalised_start": [("oracle_lanczos", "cur[i] = nq > 0.0 ? q[i] / nq : 0.0;",
+                                    "cur[i] = q[i];")],
     "bf16_ties_away": [("oracle_round_bf16", "nearbyint(q)", "round(q)")],
     "bf16_precision": [("oracle_round_bf16", "E - 7;", "E - 8;")],
     "bf16_subnormal_threshold": [("oracle_round_bf16", "(E < -126)", "(E < -127)")],
