@@ -785,23 +785,39 @@ def cpu_omp(A, x, ref, den, reps: int = 10, triad_n: int = 1 << 26):
 # rocprofv3 counter passes
 # ----------------------------------------------------------------------------
 
-def pmc_pass(steps: int, plan_json: str | None):
-    """Headline kernel `steps` times with the given plan (no tuning, so the
-    profile holds only these dispatches), then a copy of 2^27 doubles (the
-    calibration kernel of known size), each bracketed by synchronisation."""
+PMC_WORKLOADS = {
+    # name: (matrix, k, description)
+    "27pt160": ("c2", 1, "27-point 160^3 FP64"),
+    "irregular8M": ("c3", 1, "irregular 8M FP64"),
+    "irregular8M-k4": ("c3", 4, "irregular 8M FP64, block of k = 4"),
+}
+
+
+def pmc_pass(steps: int, plan_json: str | None, workload: str = "27pt160"):
+    """The product of one workload `steps` times with the given plan (no
+    tuning, so the profile holds only these dispatches), then a copy of 2^27
+    doubles (the calibration kernel of known size), each bracketed by
+    synchronisation."""
     import torch
 
     from paper_1106_5908_amd import spmv
     from workloads import gen
 
-    A, x = gen.workload_c2()
+    mat, k, _ = PMC_WORKLOADS[workload]
+    A, x = gen.workload_c2() if mat == "c2" else gen.workload_c3()
     h = make_handle(A, "f64", tune=False)
     if plan_json:
         spmv.spmv_set_plan(h, **json.loads(plan_json))
-    B = dev_vec(x, "f64")
-    C = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+    if k == 1:
+        B = dev_vec(x, "f64")
+        C = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+        call = lambda: spmv.spmv_run(h, B, C)  # noqa: E731
+    else:
+        B = torch.from_numpy(np.repeat(x[:, None], k, axis=1)).to("cuda")
+        C = torch.zeros((A.n_rows, k), dtype=torch.float64, device="cuda")
+        call = lambda: spmv.spmv_run_block(h, B, C)  # noqa: E731
     for _ in range(steps):
-        spmv.spmv_run(h, B, C)
+        call()
     torch.cuda.synchronize()
     n = 1 << 27
     a = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -966,17 +982,21 @@ def _counter_rows(d):
     return rows
 
 
-def summarize_pmc(fetch_dir, write_dir, out_path, plan_json):
-    """Per-dispatch FETCH_SIZE / WRITE_SIZE (KiB) of the spMV kernel, scaled
-    by the same counters' reading for the copy kernel of known size."""
+def summarize_pmc(fetch_dir, write_dir, out_path, plan_json, workload="27pt160", steps="10"):
+    """FETCH_SIZE / WRITE_SIZE (KiB) of the product, summed over its kernel
+    dispatches (several with diagonal panels) and divided by the number of
+    products, scaled by the same counters' reading for the copy kernel of
+    known size."""
+    steps = int(steps)
+
     def per_kernel(rows, counter):
         acc = {}
         for r in rows:
             if r.get("Counter_Name") != counter:
                 continue
             name = r["Kernel_Name"]
-            key = "spmv" if "spmv::" in name and ("k_stream" in name or "k_vector" in name) else (
-                "copy" if "k_copy" in name else None)
+            spmv_kernel = "spmv::" in name and any(k in name for k in ("k_stream", "k_vector", "k_block"))
+            key = "spmv" if spmv_kernel else ("copy" if "k_copy" in name else None)
             if key is None:
                 continue
             acc.setdefault((key, r["Dispatch_Id"]), 0.0)
@@ -984,7 +1004,8 @@ def summarize_pmc(fetch_dir, write_dir, out_path, plan_json):
         out = {}
         for (key, _), v in acc.items():
             out.setdefault(key, []).append(v)
-        return {k: float(np.median(v)) for k, v in out.items()}
+        return {"copy": float(np.median(out["copy"])), "spmv": float(np.sum(out["spmv"])) / steps,
+                "spmv_dispatches": len(out["spmv"])}
 
     fetch = per_kernel(_counter_rows(fetch_dir), "FETCH_SIZE")
     write = per_kernel(_counter_rows(write_dir), "WRITE_SIZE")
@@ -993,20 +1014,30 @@ def summarize_pmc(fetch_dir, write_dir, out_path, plan_json):
     w_fac = copy_bytes / (write["copy"] * 1024.0)
     fetch_b = fetch["spmv"] * 1024.0 * f_fac
     write_b = write["spmv"] * 1024.0 * w_fac
+    mat, k, desc = PMC_WORKLOADS[workload]
+    if mat == "c2":
+        n, nnz = 4096000, 109215352
+    else:
+        from workloads import gen
+
+        A, _ = gen.workload_c3()
+        n, nnz = A.n_rows, A.nnz
+    wl = "" if workload == "27pt160" else f" --pmc-workload {workload}"
     res = {
         "kernel_sha": kernel_hash(), "plan": json.loads(plan_json),
-        "workload": "27-point 160^3 FP64",
-        "fetch_kib_per_dispatch": fetch["spmv"], "write_kib_per_dispatch": write["spmv"],
+        "workload": desc,
+        "fetch_kib_per_product": fetch["spmv"], "write_kib_per_product": write["spmv"],
+        "dispatches_per_product": fetch["spmv_dispatches"] / steps,
         "copy_fetch_kib": fetch["copy"], "copy_write_kib": write["copy"],
         "fetch_scale": f_fac, "write_scale": w_fac,
         "traffic_bytes": fetch_b + write_b,
-        "algorithmic_bytes": algorithmic_bytes(4096000, 4096000, 109215352, "f64"),
+        "algorithmic_bytes": algorithmic_bytes(n, n, nnz, "f64", k),
         "commands": [
             "rocprofv3 --pmc FETCH_SIZE -d <fetch_dir> -o p --output-format csv -- "
-            "python3 bench.py --pmc-pass --steps 10 --plan '<plan>'",
+            f"python3 bench.py --pmc-pass --steps {steps} --plan '<plan>'{wl}",
             "rocprofv3 --pmc WRITE_SIZE -d <write_dir> -o p --output-format csv -- "
-            "python3 bench.py --pmc-pass --steps 10 --plan '<plan>'",
-            "python3 bench.py --summarize-pmc <fetch_dir> <write_dir> <this file> '<plan>'",
+            f"python3 bench.py --pmc-pass --steps {steps} --plan '<plan>'{wl}",
+            f"python3 bench.py --summarize-pmc <fetch_dir> <write_dir> <this file> '<plan>' {workload} {steps}",
         ],
         "scale_note": "counter KiB per dispatch x 1024 x (known bytes of the 2^27-double copy "
                       "/ the same counter's reading for that copy)",
@@ -1051,7 +1082,9 @@ def main():
     ap.add_argument("--pmc-pass", action="store_true")
     ap.add_argument("--plan", default=None,
                     help="plan (JSON) for the headline product instead of the autotuner's")
-    ap.add_argument("--summarize-pmc", nargs=4, metavar=("FETCH_DIR", "WRITE_DIR", "OUT", "PLAN_JSON"))
+    ap.add_argument("--summarize-pmc", nargs="+",
+                    metavar="FETCH_DIR WRITE_DIR OUT PLAN_JSON [WORKLOAD STEPS]")
+    ap.add_argument("--pmc-workload", default="27pt160", choices=sorted(PMC_WORKLOADS))
     ap.add_argument("--summarize-stats", nargs=3, metavar=("STATS_CSV", "OUT", "COMMAND"))
     ap.add_argument("--trace-pass", action="store_true")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "OUT", "COMMAND"))
@@ -1081,7 +1114,7 @@ def main():
         return 2
     spmv.load()
     if args.pmc_pass:
-        pmc_pass(args.steps, args.plan)
+        pmc_pass(args.steps, args.plan, args.pmc_workload)
         return 0
     if args.trace_pass:
         trace_pass(args.steps)
