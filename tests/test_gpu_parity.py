@@ -205,6 +205,44 @@ def test_handles_on_threads_and_streams():
         assert np.array_equal(out[k], ref[k]), k
 
 
+@pytest.mark.parametrize("kind", ["plain", "split"])
+def test_caller_graph_capture(kind):
+    """A caller captures spmv_run in its own HIP graph (after one eager call,
+    which builds the handle's tile tables) and replays it: every replay,
+    with eager work and synchronisation in between, equals the same number of
+    eager calls bit for bit."""
+    import torch
+
+    A, x = mats()["irregular"]
+    hb = gen.halo_begin(A.n_cols)
+    a = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, flags=NOTUNE)
+    h = spmv.spmv_split_local_nonlocal(a, hb) if kind == "split" else a
+    try:
+        B = to_dev(x, "f64")
+        halo = torch.from_numpy(np.ascontiguousarray(x[hb:])).pin_memory() if kind == "split" else None
+        E = to_dev(np.zeros(A.n_rows), "f64")
+        spmv.spmv_run(h, B, E, halo)  # eager warm-up
+        torch.cuda.synchronize()
+        C = torch.zeros_like(E)
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            spmv.spmv_run(h, B, C, halo)
+        for r in range(1, 6):
+            g.replay()
+            torch.cuda.synchronize()
+            junk = torch.ones(1 << 20, device="cuda").cumsum(0)  # unrelated eager work
+            torch.cuda.synchronize()
+            del junk
+            if r > 1:
+                spmv.spmv_run(h, B, E, halo)
+                torch.cuda.synchronize()
+            assert torch.equal(C, E), f"replay {r}"
+    finally:
+        if h is not a:
+            spmv.spmv_destroy(h)
+        spmv.spmv_destroy(a)
+
+
 def test_accumulates_into_c():
     A, x = mats()["27pt"]
     xi = np.round(x * 8)
