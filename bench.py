@@ -1047,6 +1047,42 @@ def summarize_pmc(fetch_dir, write_dir, out_path, plan_json, workload="27pt160",
     print(json.dumps(res))
 
 
+def summarize_counters(out_path, command, *dirs):
+    """Per-dispatch medians of every counter in one or more rocprofv3 --pmc
+    runs of --pmc-pass, for the product's kernels and for the copy kernel,
+    with the derived per-CU figures: busy cycles of the L1 address unit
+    (TA_TA_BUSY_sum / 256 CUs) against the kernel's cycles
+    (GRBM_GUI_ACTIVE / 8 XCDs), and L1 accesses per dispatch."""
+    acc = {}
+    for run, d in enumerate(dirs):  # dispatch numbers restart in every run
+        for r in _counter_rows(d):
+            name = r["Kernel_Name"]
+            spmv_kernel = "spmv::" in name and any(k in name for k in ("k_stream", "k_vector", "k_block"))
+            key = "spmv" if spmv_kernel else ("copy" if "k_copy" in name else None)
+            if key is None:
+                continue
+            d_acc = acc.setdefault((key, r["Counter_Name"]), {})
+            d_acc[(run, r["Dispatch_Id"])] = d_acc.get((run, r["Dispatch_Id"]), 0.0) + float(r["Counter_Value"])
+    med = {}
+    for (key, c), v in acc.items():
+        med.setdefault(key, {})[c] = float(np.median(list(v.values())))
+    lines = ["# rocprofv3 counters per dispatch (medians): the spMV kernel against the copy kernel",
+             f"# command: {command}",
+             f"# {'counter':40s} {'spmv':>16s} {'copy':>16s}"]
+    for c in sorted(set(med.get("spmv", {})) | set(med.get("copy", {}))):
+        lines.append(f"  {c:40s} {med.get('spmv', {}).get(c, float('nan')):16.1f} "
+                     f"{med.get('copy', {}).get(c, float('nan')):16.1f}")
+    for key in ("spmv", "copy"):
+        m = med.get(key, {})
+        if "TA_TA_BUSY_sum" in m and "GRBM_GUI_ACTIVE" in m:
+            cyc = m["GRBM_GUI_ACTIVE"] / 8.0
+            lines.append(f"# {key}: L1 address unit busy {m['TA_TA_BUSY_sum'] / 256.0 / cyc * 100:.0f}% of "
+                         f"{cyc:.0f} cycles per CU")
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print("\n".join(lines))
+
+
 def summarize_stats(stats_csv, out_path, command, kernel_filter=""):
     """Short text summary of a rocprofv3 --stats kernel table."""
     import csv
@@ -1087,6 +1123,7 @@ def main():
     ap.add_argument("--pmc-workload", default="27pt160", choices=sorted(PMC_WORKLOADS))
     ap.add_argument("--summarize-stats", nargs=3, metavar=("STATS_CSV", "OUT", "COMMAND"))
     ap.add_argument("--trace-pass", action="store_true")
+    ap.add_argument("--summarize-counters", nargs="+", metavar="OUT COMMAND DIR")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "OUT", "COMMAND"))
     args = ap.parse_args()
 
@@ -1098,6 +1135,9 @@ def main():
         return 0
     if args.summarize_trace:
         summarize_trace(*args.summarize_trace)
+        return 0
+    if args.summarize_counters:
+        summarize_counters(*args.summarize_counters)
         return 0
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) != 1:
         print("bench.py measures one GPU only: the path runs on a single MI355X and has no "
