@@ -110,12 +110,22 @@ _i32 = ctypes.c_int32
 
 
 def load():
-    """Load libspmv.so (raises ImportError if it has not been built)."""
+    """Load libspmv.so (raises ImportError if it has not been built).
+
+    PyTorch is imported first when it is installed: the library then binds
+    to the HIP runtime torch carries (both name the same shared object), so
+    the process has one runtime and torch's streams and buffers are the
+    library's.  Loaded the other way round, torch cannot bring up its own
+    copy of the runtime afterwards."""
     global _lib
     if _lib is not None:
         return _lib
     if not os.path.exists(LIB_PATH):
         raise ImportError(f"{LIB_PATH} is not built; run python -m paper_1106_5908_amd.build")
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     sig = {
         "spmv_create_crs": [_i64, _i64, _i64, _vp, _vp, _vp, _i32, _i32, ctypes.c_uint32, _vp],
