@@ -161,13 +161,22 @@ def log(msg: str):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
+SETUP_TIMES = {}
+
+
 def make_handle(A, prec="f64", tune=True):
+    """Handle with the plan the autotuner picks (the cache is bypassed, so
+    every run tunes); the ingest and tuning times of the last call are kept
+    in SETUP_TIMES."""
     from paper_1106_5908_amd import spmv
 
+    t0 = time.perf_counter()
     h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, prec=prec,
                              flags=spmv.SPMV_FLAG_NO_TUNE_CACHE)
+    t1 = time.perf_counter()
     if tune:
         spmv.spmv_tune(h, 1)
+    SETUP_TIMES.update(create_ms=(t1 - t0) * 1e3, tune_ms=(time.perf_counter() - t1) * 1e3 if tune else 0.0)
     return h
 
 
@@ -209,6 +218,7 @@ def run_spmv_path(A, x, prec, steps, warmup, label, ref=None, den=None, tune=Tru
     from paper_1106_5908_amd import spmv
 
     h = make_handle(A, prec, tune and plan is None)
+    setup = dict(SETUP_TIMES)
     if plan is not None:
         spmv.spmv_set_plan(h, **plan)
     B = dev_vec(x, prec)
@@ -229,7 +239,7 @@ def run_spmv_path(A, x, prec, steps, warmup, label, ref=None, den=None, tune=Tru
         "path": label, "prec": prec, "gflops": flops / (t["ms_per_step"] * 1e6),
         "model_GBs": mb / (t["ms_per_step"] * 1e6), "model_bytes": mb, **t, **err,
         "err_bound": bound(prec, n), "within_bound": err["max_normalized_err"] <= bound(prec, n),
-        "plan": plan,
+        "plan": plan, "ingest_ms": setup["create_ms"], "tune_ms": setup["tune_ms"],
     }
     log(f"{label} {prec}: {out['gflops']:.0f} GFlop/s, {out['model_GBs']:.0f} GB/s model, "
         f"err {err['max_normalized_err']:.2e}")
