@@ -32,7 +32,9 @@
  *   - Asynchronous device faults surface at the caller's next
  *     synchronisation, not as a status from the call that enqueued them.
  *   - Different handles may be used concurrently from different threads; one
- *     handle must be used by one thread at a time.
+ *     handle must be used by one thread at a time.  Calls on one handle must
+ *     also be ordered on the device (one stream, or streams ordered by
+ *     events): a handle's internal buffers and streams serve every call.
  */
 #ifndef LIBSPMV_SPMV_H
 #define LIBSPMV_SPMV_H
@@ -161,7 +163,9 @@ spmv_status_t spmv_run(spmv_handle_t h, const void *B, void *C,
  * spmv_set_send_list (split handles only): send_idx[0 .. n_send) are
  * positions in B of locally owned elements, each in [0, h) with h the
  * handle's halo_begin_col, in send order; repeats are allowed.  The list is
- * copied to device memory owned by the handle; n_send = 0 clears it.
+ * copied to device memory owned by the handle; n_send = 0 clears it.  The
+ * call first waits for all work on the device, since an exchange still in
+ * flight may read the list it replaces.
  * Errors: SPMV_ERR_UNSUPPORTED for plain and batch handles;
  * SPMV_ERR_INVALID_ARG for n_send < 0, a NULL list with n_send > 0, or an
  * index outside [0, h) (the message names the first).
@@ -268,7 +272,8 @@ spmv_status_t spmv_kpm_moments(spmv_handle_t h, int32_t R, int32_t M, const doub
  * to make sense).  1 <= m <= 2^20.  q: start vector, n_rows doubles on the
  * device (read only); V1, V2: device work vectors of n_rows doubles,
  * overwritten; alpha, beta: device arrays of m doubles.  The handle's small
- * reduction buffer is shared with spmv_kpm_moments.
+ * reduction buffer is shared with spmv_kpm_moments (allocated on first use,
+ * after a device synchronisation).
  * Errors: SPMV_ERR_UNSUPPORTED for split, batch or non-F64 handles;
  * SPMV_ERR_INVALID_ARG for a non-square matrix, m out of range, null or
  * equal buffers.
