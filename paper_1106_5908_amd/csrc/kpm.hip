@@ -79,22 +79,38 @@ __global__ __launch_bounds__(WG) void k_kpm_step(double *__restrict__ X, double 
   wg_column_sums(a, b, R, s_a, s_b, part_a, part_b);
 }
 
-// Sums the per-workgroup partials of each column in workgroup order and
-// writes the moments: first step (first != 0): mu[0] = <v0|v0>,
-// mu[1] = <v1|v0>; step n: mu[2n] = 2 <v_n|v_n> - mu[0],
-// mu[2n+1] = 2 <v_{n+1}|v_n> - mu[1]; moments at or past M are not written.
-// One workgroup; thread r < R handles column r.
-__global__ __launch_bounds__(64) void k_kpm_finish(const double *__restrict__ part_a,
+// Sums the per-workgroup partials of each column and writes the moments:
+// first step (first != 0): mu[0] = <v0|v0>, mu[1] = <v1|v0>; step n:
+// mu[2n] = 2 <v_n|v_n> - mu[0], mu[2n+1] = 2 <v_{n+1}|v_n> - mu[1]; moments
+// at or past M are not written.  One workgroup: thread t sums column t % R
+// over the partials t / R, t / R + WG / R, ... (each pass of the workgroup
+// reads WG consecutive doubles), then a fixed tree over the WG / R groups.
+__global__ __launch_bounds__(WG) void k_kpm_finish(const double *__restrict__ part_a,
                                                    const double *__restrict__ part_b, int n_parts,
                                                    int R, int first, int step, int M,
                                                    double *__restrict__ mu) {
-  const int r = threadIdx.x;
-  if (r >= R) return;
+  __shared__ double s_a[WG], s_b[WG];
+  const int tid = threadIdx.x;
+  const int groups = WG / R;
   double a = 0.0, b = 0.0;
-  for (int w = 0; w < n_parts; ++w) {
-    a += part_a[(int64_t)w * R + r];
-    b += part_b[(int64_t)w * R + r];
+  for (int w = tid / R; w < n_parts; w += groups) {
+    a += part_a[(int64_t)w * R + tid % R];
+    b += part_b[(int64_t)w * R + tid % R];
   }
+  s_a[tid] = a;
+  s_b[tid] = b;
+  __syncthreads();
+  for (int off = WG / 2; off >= R; off >>= 1) {
+    if (tid < off) {
+      s_a[tid] += s_a[tid + off];
+      s_b[tid] += s_b[tid + off];
+    }
+    __syncthreads();
+  }
+  if (tid >= R) return;
+  const int r = tid;
+  a = s_a[r];
+  b = s_b[r];
   if (first) {
     mu[r] = a;
     if (M > 1) mu[(int64_t)R + r] = b;
@@ -129,7 +145,7 @@ hipError_t launch_kpm_first(const double *V0, const double *W1, double *W2, int6
   const unsigned g = grid_for(n);
   hipLaunchKernelGGL(k_kpm_first, dim3(g), dim3(WG), 0, s, V0, W1, W2, n, R, part,
                      part + (int64_t)KPM_GRID * R);
-  hipLaunchKernelGGL(k_kpm_finish, dim3(1), dim3(64), 0, s, part, part + (int64_t)KPM_GRID * R,
+  hipLaunchKernelGGL(k_kpm_finish, dim3(1), dim3(WG), 0, s, part, part + (int64_t)KPM_GRID * R,
                      (int)g, R, 1, 0, M, mu);
   return hipGetLastError();
 }
@@ -140,7 +156,7 @@ hipError_t launch_kpm_step(double *X, double *P, int64_t n_rows, int R, double *
   const unsigned g = grid_for(n);
   hipLaunchKernelGGL(k_kpm_step, dim3(g), dim3(WG), 0, s, X, P, n, R, part,
                      part + (int64_t)KPM_GRID * R);
-  hipLaunchKernelGGL(k_kpm_finish, dim3(1), dim3(64), 0, s, part, part + (int64_t)KPM_GRID * R,
+  hipLaunchKernelGGL(k_kpm_finish, dim3(1), dim3(WG), 0, s, part, part + (int64_t)KPM_GRID * R,
                      (int)g, R, 0, step, M, mu);
   return hipGetLastError();
 }
