@@ -21,6 +21,7 @@
 #include <mutex>
 #include <sstream>
 #include <string>
+#include <system_error>
 #include <thread>
 #include <vector>
 
@@ -130,10 +131,16 @@ void parallel_for(int64_t n, F &&f) {
     return;
   }
   std::vector<std::thread> th;
+  th.reserve(T);
   const int64_t chunk = (n + T - 1) / T;
   for (unsigned t = 0; t < T; ++t) {
     const int64_t b = int64_t(t) * chunk, e = std::min(n, b + chunk);
-    if (b < e) th.emplace_back([&f, b, e] { f(b, e); });
+    if (b >= e) continue;
+    try {
+      th.emplace_back([&f, b, e] { f(b, e); });
+    } catch (const std::system_error &) {
+      f(b, e);  // no thread to be had: this chunk runs here, the started ones are joined below
+    }
   }
   for (auto &x : th) x.join();
 }
