@@ -236,13 +236,17 @@ spmv_status_t spmv_run_block(spmv_handle_t h, int32_t k, const void *B, int64_t 
  * with the Chebyshev recursion v_{n+1} = 2 H v_n - v_{n-1} (v_1 = H v0) and
  * the product relations mu_{2n} = 2 v_n.v_n - mu_0 and
  * mu_{2n+1} = 2 v_{n+1}.v_n - mu_1, so M moments cost ceil(M/2) block
- * products (spmv_run_block with k = R).
+ * products (the kernel of spmv_run_block with k = R).  The loop carries
+ * z_n = c_n v_n with c_n = 1, 1, -1, -1, 1, 1, ...; each step is then one
+ * product accumulating in place, z_{n+1} = z_{n-1} + (+-2 H) z_n, with the
+ * values scaled by +-2 as they are staged (exact), and one read-only pass for
+ * the two dot products.
  *
  * h: plain SPMV_PREC_F64 handle of a square matrix.  R: a power of two in
  * [1, 64].  1 <= M <= 2^20.  V0, W1, W2: device blocks of n_rows x R
  * doubles, row-major (element (i, r) at i*R + r); V0 is read only, W1 and W2
  * are work space overwritten by the call (on return they hold the last two
- * vectors of the recursion, scaled).  mu: device array of M*R doubles.
+ * vectors of the recursion, each possibly negated).  mu: device array of M*R doubles.
  * Everything is enqueued on `stream`; the dot products are reduced in a fixed
  * order, so repeated calls give identical moments.  The handle keeps a small
  * device buffer of partial sums (grown on the first call with a larger R,

@@ -1320,25 +1320,28 @@ int default_kt(int k) {
   return 16;
 }
 
-// Block product over a part, or over its diagonal panels in turn when
-// `panels` > 1 (the panels are shared with the single-vector plan).
+// Block product C = C + scale*A*B over a part, or over its diagonal panels
+// in turn when `panels` > 1 (the panels are shared with the single-vector
+// plan).  `scale` is 1 or a power of two, applied exactly to every value.
 void run_block_part(spmv_handle_s *h, Part &p, int kt, int nt, int remap, int panels, int k,
-                    const void *B, int64_t ldb, void *C, int64_t ldc, hipStream_t s) {
+                    const void *B, int64_t ldb, void *C, int64_t ldc, hipStream_t s,
+                    double scale = 1.0) {
   if (p.n_rows == 0 || p.nnz == 0) return;
   if (panels > 1) {
     for (auto &q : build_panels(h, p, panels))
-      run_block_part(h, *q, kt, nt, remap, 1, k, B, ldb, C, ldc, s);
+      run_block_part(h, *q, kt, nt, remap, 1, k, B, ldb, C, ldc, s, scale);
     return;
   }
   auto t = p.tiles_for(4);
   hip_ok(launch_spmv_block(h->prec, p.dev(), t.first, t.second, 4, nt, remap, kt, k, B, ldb, C,
-                           ldc, s),
+                           ldc, scale, s),
          "block kernel launch");
 }
 
-// C = C + A*B for k columns of a plain handle (arguments already checked).
+// C = C + scale*A*B for k columns of a plain handle (arguments already
+// checked; scale as in run_block_part).
 void block_product(spmv_handle_s *h, int k, const void *B, int64_t ldb, void *C, int64_t ldc,
-                   hipStream_t s) {
+                   hipStream_t s, double scale = 1.0) {
     Part &p = h->main;
     // per-k choices made by spmv_tune for this handle, else the cache, else defaults
     int kt = p.plan.block_kt, nt = p.plan.nontemporal, panels = p.plan.panels;
@@ -1359,7 +1362,7 @@ void block_product(spmv_handle_s *h, int k, const void *B, int64_t ldb, void *C,
         h->block_plans[k] = c;
       }
     }
-    run_block_part(h, p, kt, nt, p.plan.xcd_remap, panels, k, B, ldb, C, ldc, s);
+    run_block_part(h, p, kt, nt, p.plan.xcd_remap, panels, k, B, ldb, C, ldc, s, scale);
 }
 
 }  // namespace
@@ -1405,12 +1408,16 @@ extern "C" spmv_status_t spmv_kpm_moments(spmv_handle_t h_, int32_t R, int32_t M
     }
     double *part = h->kpm_part.as<double>();
     const int64_t n = h->n_rows;
+    // The recursion v_{n+1} = 2 H v_n - v_{n-1} runs on z_n = c_n v_n with
+    // c = 1, 1, -1, -1, 1, 1, ...: then z_{n+1} = z_{n-1} + 2 (c_{n+1}/c_n) H z_n,
+    // one product accumulating in place onto the older vector with the exact
+    // scale +2 (n even) or -2 (n odd), and no pass to negate or halve it.
     hip_ok(launch_kpm_zero(W1, n * R, s), "zero fill");
-    block_product(h, R, V0, R, W1, R, s);  // W1 = H v0 = v1
-    hip_ok(launch_kpm_first(V0, W1, W2, n, R, part, M, mu, s), "moment kernels");
-    double *X = W1, *P = W2;  // X = v_n, P = -v_{n-1} / 2
+    block_product(h, R, V0, R, W1, R, s);  // W1 = H v0 = v1 = z1
+    hip_ok(launch_kpm_first(V0, W1, W2, n, R, part, M, mu, s), "moment kernels");  // W2 = z0
+    double *X = W1, *P = W2;  // X = z_n, P = z_{n-1}
     for (int step = 1; 2 * step < M; ++step) {
-      block_product(h, R, X, R, P, R, s);  // P = H v_n - v_{n-1} / 2
+      block_product(h, R, X, R, P, R, s, step % 2 == 0 ? 2.0 : -2.0);  // P = z_{n+1}
       hip_ok(launch_kpm_step(X, P, n, R, part, step, M, mu, s), "moment kernels");
       std::swap(X, P);
     }

@@ -442,6 +442,9 @@ __global__ __launch_bounds__(WG) void k_vector(CsrDev A, int64_t rows_per_wg, in
 // ---------------------------------------------------------------------------
 // Block kernel: columns [t0, t0 + KT) of k right-hand sides.  Each row is
 // handled by G = KT / VW lanes; lane l owns columns t0 + l*VW .. + VW - 1.
+// Every stored value is multiplied by `scale` as it is staged: 1 for
+// C = C + A*B; a power of two (exact) for the recursions that need a
+// multiple of A, e.g. -2 for the Chebyshev three-term recursion.
 // ---------------------------------------------------------------------------
 template <class X, int VW> struct VecT;
 template <> struct VecT<double, 1> { using T = double; };
@@ -466,7 +469,8 @@ __device__ __forceinline__ void load_vec(const X *p, X (&out)[VW]) {
 template <int P, int E, int KT, int VW, bool NT>
 __global__ __launch_bounds__(WG) void k_block(CsrDev A, const TileRP *__restrict__ tiles,
                                               int64_t n_tiles, int remap, int k, int t0,
-                                              const void *Bv, int64_t ldb, void *Cv, int64_t ldc) {
+                                              const void *Bv, int64_t ldb, void *Cv, int64_t ldc,
+                                              typename Ty<P>::X scale) {
   using V = typename Ty<P>::V;
   using X = typename Ty<P>::X;
   constexpr int TILE = WG * E;
@@ -497,7 +501,7 @@ __global__ __launch_bounds__(WG) void k_block(CsrDev A, const TileRP *__restrict
     if (active) {
       for (int j = p0 + g; j < p1; j += NG) {
         const int c = ld<int32_t, NT>(A.col + j);
-        const X a = widen<X>(ld<V, NT>(val + j));
+        const X a = widen<X>(ld<V, NT>(val + j)) * scale;
         X bv[VW];
         load_vec<X, VW>(B + (int64_t)c * ldb + cb, bv);
 #pragma unroll
@@ -533,7 +537,7 @@ __global__ __launch_bounds__(WG) void k_block(CsrDev A, const TileRP *__restrict
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       s_col[e * WG + tid] = cc[e];
-      s_val[e * WG + tid] = widen<X>(vv[e]);
+      s_val[e * WG + tid] = widen<X>(vv[e]) * scale;
     }
   }
   __syncthreads();
@@ -723,24 +727,27 @@ hipError_t dispatch_spmv(const CsrDev &A, const PlanDev &pl, const TileRP *tiles
 template <int P, int KT, int VW>
 hipError_t run_block_kt(const CsrDev &A, const TileRP *tiles, int64_t n_tiles, int nt, int remap,
                         int k, int t0, const void *B, int64_t ldb, void *C, int64_t ldc,
-                        hipStream_t s) {
+                        double scale, hipStream_t s) {
+  using X = typename Ty<P>::X;
+  const X sc = static_cast<X>(scale);
   if (nt)
     hipLaunchKernelGGL((k_block<P, 4, KT, VW, true>), dim3((unsigned)n_tiles), dim3(WG), 0, s, A,
-                       tiles, n_tiles, remap, k, t0, B, ldb, C, ldc);
+                       tiles, n_tiles, remap, k, t0, B, ldb, C, ldc, sc);
   else
     hipLaunchKernelGGL((k_block<P, 4, KT, VW, false>), dim3((unsigned)n_tiles), dim3(WG), 0, s, A,
-                       tiles, n_tiles, remap, k, t0, B, ldb, C, ldc);
+                       tiles, n_tiles, remap, k, t0, B, ldb, C, ldc, sc);
   return hipGetLastError();
 }
 
 template <int P, int VW>
 hipError_t run_block_vw(const CsrDev &A, const TileRP *tiles, int64_t n_tiles, int nt, int remap,
                         int kt, int k, int t0, const void *B, int64_t ldb, void *C, int64_t ldc,
-                        hipStream_t s) {
+                        double scale, hipStream_t s) {
   switch (kt) {
-    case 4: return run_block_kt<P, 4, VW>(A, tiles, n_tiles, nt, remap, k, t0, B, ldb, C, ldc, s);
-    case 8: return run_block_kt<P, 8, VW>(A, tiles, n_tiles, nt, remap, k, t0, B, ldb, C, ldc, s);
-    case 16: return run_block_kt<P, 16, VW>(A, tiles, n_tiles, nt, remap, k, t0, B, ldb, C, ldc, s);
+    case 4: return run_block_kt<P, 4, VW>(A, tiles, n_tiles, nt, remap, k, t0, B, ldb, C, ldc, scale, s);
+    case 8: return run_block_kt<P, 8, VW>(A, tiles, n_tiles, nt, remap, k, t0, B, ldb, C, ldc, scale, s);
+    case 16:
+      return run_block_kt<P, 16, VW>(A, tiles, n_tiles, nt, remap, k, t0, B, ldb, C, ldc, scale, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -748,7 +755,7 @@ hipError_t run_block_vw(const CsrDev &A, const TileRP *tiles, int64_t n_tiles, i
 template <int P>
 hipError_t dispatch_block(const CsrDev &A, const TileRP *tiles, int64_t n_tiles, int nt, int remap,
                           int kt, int k, const void *B, int64_t ldb, void *C, int64_t ldc,
-                          hipStream_t s) {
+                          double scale, hipStream_t s) {
   using X = typename Ty<P>::X;
   constexpr int VWIDE = sizeof(X) == 8 ? 2 : 4;
   // Wide column loads need every lane's first column aligned to VWIDE.
@@ -758,9 +765,9 @@ hipError_t dispatch_block(const CsrDev &A, const TileRP *tiles, int64_t n_tiles,
                     (reinterpret_cast<uintptr_t>(C) % (sizeof(X) * VWIDE) == 0);
   for (int t0 = 0; t0 < k; t0 += kt) {
     hipError_t e = wide ? run_block_vw<P, VWIDE>(A, tiles, n_tiles, nt, remap, kt, k, t0, B, ldb, C,
-                                                 ldc, s)
+                                                 ldc, scale, s)
                         : run_block_vw<P, 1>(A, tiles, n_tiles, nt, remap, kt, k, t0, B, ldb, C,
-                                             ldc, s);
+                                             ldc, scale, s);
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
@@ -825,11 +832,12 @@ hipError_t launch_spmv(int prec, const CsrDev &A, const PlanDev &plan, const Til
 
 hipError_t launch_spmv_block(int prec, const CsrDev &A, const TileRP *tiles, int64_t n_tiles,
                              int tile_items, int nontemporal, int xcd_remap, int kt, int k,
-                             const void *B, int64_t ldb, void *C, int64_t ldc, hipStream_t s) {
+                             const void *B, int64_t ldb, void *C, int64_t ldc, double scale,
+                             hipStream_t s) {
   if (tile_items != 4) return hipErrorInvalidValue;
   if (n_tiles <= 0) return hipSuccess;
   SPMV_PREC_SWITCH(prec, (dispatch_block<PP>(A, tiles, n_tiles, nontemporal, xcd_remap, kt, k, B,
-                                              ldb, C, ldc, s)))
+                                              ldb, C, ldc, scale, s)))
 }
 
 hipError_t launch_batch_reset(int32_t *counter, hipStream_t s) {

@@ -4,6 +4,12 @@
 // spMV, Sect. 1.3).  The product itself is the block kernel; these kernels
 // do the O(N) work between products.
 //
+// The loop keeps z_n = c_n v_n with c_n = 1, 1, -1, -1, 1, 1, ... (period
+// four), for which the three-term recursion becomes one in-place product
+// z_{n+1} = z_{n-1} + 2 (c_{n+1}/c_n) H z_n.  Then |z_n|^2 = |v_n|^2 and
+// <v_{n+1}|v_n> = (c_{n+1}/c_n) <z_{n+1}|z_n>, with c_{n+1}/c_n = +1 for n
+// even and -1 for n odd.
+//
 // Vectors are blocks of R columns stored row-major (element (i, r) at
 // i*R + r), R a power of two <= 64, as the block product reads and writes
 // them.  Every dot product is reduced in a fixed order (per-thread partial
@@ -39,9 +45,9 @@ __device__ __forceinline__ void wg_column_sums(double a, double b, int R, double
   }
 }
 
-// First step: with W1 = H v0 (v0 = V0), partial sums of <v0|v0> and
-// <W1|v0> per column, and W2 = -v0 / 2 (the scaled previous vector the
-// next product accumulates onto).
+// First step: with W1 = H v0 = z1 (v0 = V0), partial sums of <v0|v0> and
+// <W1|v0> per column, and W2 = v0 = z0, the vector the next product
+// accumulates onto (V0 itself stays untouched).
 __global__ __launch_bounds__(WG) void k_kpm_first(const double *__restrict__ V0,
                                                   const double *__restrict__ W1,
                                                   double *__restrict__ W2, int64_t n, int R,
@@ -54,35 +60,33 @@ __global__ __launch_bounds__(WG) void k_kpm_first(const double *__restrict__ V0,
     const double v = V0[e];
     a += v * v;
     b += W1[e] * v;
-    W2[e] = -0.5 * v;
+    W2[e] = v;
   }
   wg_column_sums(a, b, R, s_a, s_b, part_a, part_b);
 }
 
-// Step n >= 1: X = v_n, P = H v_n - v_{n-1} / 2.  Sets P = 2 P = v_{n+1}
-// (exact scaling), takes partial sums of <v_n|v_n> and <v_{n+1}|v_n>, and
-// sets X = -v_n / 2 for the following product.
-__global__ __launch_bounds__(WG) void k_kpm_step(double *__restrict__ X, double *__restrict__ P,
-                                                 int64_t n, int R, double *__restrict__ part_a,
+// Step n >= 1: X = z_n, P = z_{n+1}.  Partial sums of <z_n|z_n> and
+// <z_{n+1}|z_n>; nothing is written back.
+__global__ __launch_bounds__(WG) void k_kpm_step(const double *__restrict__ X,
+                                                 const double *__restrict__ P, int64_t n, int R,
+                                                 double *__restrict__ part_a,
                                                  double *__restrict__ part_b) {
   __shared__ double s_a[WG], s_b[WG];
   const int64_t stride = (int64_t)gridDim.x * WG;
   double a = 0.0, b = 0.0;
   for (int64_t e = (int64_t)blockIdx.x * WG + threadIdx.x; e < n; e += stride) {
     const double x = X[e];
-    const double p = 2.0 * P[e];
     a += x * x;
-    b += p * x;
-    P[e] = p;
-    X[e] = -0.5 * x;
+    b += P[e] * x;
   }
   wg_column_sums(a, b, R, s_a, s_b, part_a, part_b);
 }
 
 // Sums the per-workgroup partials of each column and writes the moments:
 // first step (first != 0): mu[0] = <v0|v0>, mu[1] = <v1|v0>; step n:
-// mu[2n] = 2 <v_n|v_n> - mu[0], mu[2n+1] = 2 <v_{n+1}|v_n> - mu[1]; moments
-// at or past M are not written.  One workgroup: thread t sums column t % R
+// mu[2n] = 2 <v_n|v_n> - mu[0], mu[2n+1] = 2 <v_{n+1}|v_n> - mu[1], the dot
+// products taken from those of z (see above); moments at or past M are not
+// written.  One workgroup: thread t sums column t % R
 // over the partials t / R, t / R + WG / R, ... (each pass of the workgroup
 // reads WG consecutive doubles), then a fixed tree over the WG / R groups.
 __global__ __launch_bounds__(WG) void k_kpm_finish(const double *__restrict__ part_a,
@@ -117,7 +121,8 @@ __global__ __launch_bounds__(WG) void k_kpm_finish(const double *__restrict__ pa
   } else {
     const int m0 = 2 * step, m1 = 2 * step + 1;
     if (m0 < M) mu[(int64_t)m0 * R + r] = 2.0 * a - mu[r];
-    if (m1 < M) mu[(int64_t)m1 * R + r] = 2.0 * b - mu[(int64_t)R + r];
+    const double sgn = (step % 2 == 0) ? 1.0 : -1.0;  // c_{n+1} / c_n
+    if (m1 < M) mu[(int64_t)m1 * R + r] = 2.0 * (sgn * b) - mu[(int64_t)R + r];
   }
 }
 
@@ -150,8 +155,8 @@ hipError_t launch_kpm_first(const double *V0, const double *W1, double *W2, int6
   return hipGetLastError();
 }
 
-hipError_t launch_kpm_step(double *X, double *P, int64_t n_rows, int R, double *part, int step,
-                           int M, double *mu, hipStream_t s) {
+hipError_t launch_kpm_step(const double *X, const double *P, int64_t n_rows, int R, double *part,
+                           int step, int M, double *mu, hipStream_t s) {
   const int64_t n = n_rows * R;
   const unsigned g = grid_for(n);
   hipLaunchKernelGGL(k_kpm_step, dim3(g), dim3(WG), 0, s, X, P, n, R, part,

@@ -62,9 +62,12 @@ struct BatchTile {
 hipError_t launch_spmv(int prec, const CsrDev &A, const PlanDev &plan, const TileRP *tiles,
                        int64_t n_tiles, const void *x, void *y, hipStream_t s);
 
+// Block product C = C + scale*A*B; `scale` is 1, or a power of two so that the
+// scaled values are exact.
 hipError_t launch_spmv_block(int prec, const CsrDev &A, const TileRP *tiles, int64_t n_tiles,
                              int tile_items, int nontemporal, int xcd_remap, int kt, int k,
-                             const void *B, int64_t ldb, void *C, int64_t ldc, hipStream_t s);
+                             const void *B, int64_t ldb, void *C, int64_t ldc, double scale,
+                             hipStream_t s);
 
 // counters: one int32 per XCD (8)
 hipError_t launch_batch_reset(int32_t *counters, hipStream_t s);
@@ -128,12 +131,14 @@ hipError_t launch_pack(int word_bytes, const void *B, const int32_t *idx, int64_
                        hipStream_t s);
 
 // ---- Chebyshev moments (kpm.hip) -----------------------------------------------
-// Blocks of R columns, row-major; part holds 2 * KPM_GRID * R doubles.
+// Blocks of R columns, row-major; part holds 2 * KPM_GRID * R doubles.  first:
+// W1 = H v0 = z1 given, copies V0 into W2 and writes mu[0], mu[1].  step n: X = z_n,
+// P = z_{n+1} given (z_n = c_n v_n, c = 1, 1, -1, -1, ...), writes mu[2n], mu[2n+1].
 constexpr int KPM_GRID = 1024;
 hipError_t launch_kpm_zero(double *p, int64_t n, hipStream_t s);
 hipError_t launch_kpm_first(const double *V0, const double *W1, double *W2, int64_t n_rows, int R,
                             double *part, int M, double *mu, hipStream_t s);
-hipError_t launch_kpm_step(double *X, double *P, int64_t n_rows, int R, double *part, int step,
+hipError_t launch_kpm_step(const double *X, const double *P, int64_t n_rows, int R, double *part, int step,
                            int M, double *mu, hipStream_t s);
 
 // ---- Lanczos (lanczos.hip) ---------------------------------------------------------
