@@ -80,6 +80,8 @@ def test_irregular_moments_and_determinism():
         assert np.array_equal(m1.view(np.uint64), m2.view(np.uint64))
         spmv.spmv_tune(h, R)  # a tuned block plan gives the same moments to the bound
         m3 = spmv.spmv_kpm_moments(h, V, M).cpu().numpy()
+        # V0 is read only: the recursion works in W1 and W2
+        assert np.array_equal(V.cpu().numpy().view(np.uint64), V0.view(np.uint64))
     finally:
         spmv.spmv_destroy(h)
     check(A, val, V0, m1, M)
