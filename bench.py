@@ -43,7 +43,7 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 PROFILES = os.path.join(ROOT, "profiles")
-TRAFFIC_FILE = os.path.join(PROFILES, "traffic_csr_stream_27pt160_f64.txt")
+TRAFFIC_GLOB = os.path.join(PROFILES, "traffic_*_27pt160_f64.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1106_5908_amd", "csrc", "kernels.hip")
 
 VAL_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f32f64": 4}
@@ -141,16 +141,18 @@ def kernel_hash() -> str:
 
 
 def read_traffic(plan: dict):
-    """HBM bytes per launch from the committed counter summary, if it was
-    taken with the current kernel source and plan; else None."""
-    try:
-        with open(TRAFFIC_FILE) as f:
-            t = json.load(f)
-    except (OSError, ValueError):
-        return None
-    if t.get("kernel_sha") != kernel_hash() or t.get("plan") != plan:
-        return None
-    return t.get("traffic_bytes")
+    """HBM bytes per launch from the committed counter summary of the
+    27-point workload taken with the current kernel source and this plan;
+    None if there is none."""
+    for path in sorted(glob.glob(TRAFFIC_GLOB)):
+        try:
+            with open(path) as f:
+                t = json.load(f)
+        except (OSError, ValueError):
+            continue
+        if t.get("kernel_sha") == kernel_hash() and t.get("plan") == plan:
+            return t.get("traffic_bytes")
+    return None
 
 
 # ----------------------------------------------------------------------------
@@ -940,7 +942,8 @@ def summarize_trace(trace_dir, out_path, command):
         rows = []
         for c in calls:
             ks = [e for e in c if e[0] == "k"]
-            nl = [e for e in ks if "k_stream" in e[1] and _template_args(e[1])[-1:] == ["true"]]
+            nl = [e for e in ks if ("k_stream" in e[1] or "k_staged" in e[1])
+                  and _template_args(e[1])[-1:] == ["true"]]
             first_nl = min((e[2] for e in nl), default=None)
             loc = [e for e in ks if first_nl is None or e[2] < first_nl]
             loc = [e for e in loc if "k_pack" not in e[1]]
@@ -1005,7 +1008,8 @@ def summarize_pmc(fetch_dir, write_dir, out_path, plan_json, workload="27pt160",
             if r.get("Counter_Name") != counter:
                 continue
             name = r["Kernel_Name"]
-            spmv_kernel = "spmv::" in name and any(k in name for k in ("k_stream", "k_vector", "k_block"))
+            spmv_kernel = "spmv::" in name and any(
+                k in name for k in ("k_stream", "k_staged", "k_vector", "k_block"))
             key = "spmv" if spmv_kernel else ("copy" if "k_copy" in name else None)
             if key is None:
                 continue
@@ -1067,7 +1071,8 @@ def summarize_counters(out_path, command, *dirs):
     for run, d in enumerate(dirs):  # dispatch numbers restart in every run
         for r in _counter_rows(d):
             name = r["Kernel_Name"]
-            spmv_kernel = "spmv::" in name and any(k in name for k in ("k_stream", "k_vector", "k_block"))
+            spmv_kernel = "spmv::" in name and any(
+                k in name for k in ("k_stream", "k_staged", "k_vector", "k_block"))
             key = "spmv" if spmv_kernel else ("copy" if "k_copy" in name else None)
             if key is None:
                 continue

@@ -324,7 +324,16 @@ spmv_status_t spmv_create_batch(int32_t count, const int64_t *n_rows, const int6
  *                row and reduce it with cross-lane shuffles (not for batches).
  *                SPMV_KERNEL_TILE_GRID: batch handles only; one workgroup per
  *                tile of the whole batch in a single launch.
- *   tile_items   4, 8 or 16 (stream kernel)
+ *                SPMV_KERNEL_STAGED: the stream kernel's tiles, with the
+ *                columns each tile reads merged into at most four runs
+ *                (gaps of up to 16 columns filled) that the workgroup loads
+ *                into LDS (up to 12 KB of B) before its val and col_idx, so
+ *                the entries read B from LDS; a tile whose columns do not
+ *                fit is run as in the stream kernel.  Stencil-like
+ *                matrices, whose tiles read a few contiguous column ranges,
+ *                gain; the run table (48 bytes per tile) is built on the host
+ *                from a copy of col_idx read back once.  Not for batches.
+ *   tile_items   4, 8 or 16 (stream kernel); 8 or 16 (staged kernel)
  *   lanes        2, 4, 8, 16, 32 or 64 (vector kernel)
  *   nontemporal  1: val and col_idx are loaded with the streaming hint so
  *                they do not displace B from the caches
@@ -345,6 +354,7 @@ spmv_status_t spmv_create_batch(int32_t count, const int64_t *n_rows, const int6
 #define SPMV_KERNEL_STREAM 1
 #define SPMV_KERNEL_VECTOR 2
 #define SPMV_KERNEL_TILE_GRID 3
+#define SPMV_KERNEL_STAGED 4
 #define SPMV_PART_MAIN 0
 #define SPMV_PART_NONLOCAL 1
 
@@ -386,6 +396,8 @@ typedef struct spmv_info {
     double row_len_mean, row_len_cv;
     int64_t row_len_max;
     int64_t n_send;        /* split: entries of the send list; else 0 */
+    int64_t n_staged_tiles; /* staged plan of the main part: tiles that read B
+                               from LDS (the rest gather); else 0 */
 } spmv_info_t;
 
 spmv_status_t spmv_get_info(spmv_handle_t h, spmv_info_t *info);
@@ -395,7 +407,13 @@ spmv_status_t spmv_get_info(spmv_handle_t h, spmv_info_t *info);
  *   SPMV_ARR_ROW_PTR, _COL, _VAL: the matrix (split: the local part), 0-based,
  *     val in storage precision (f64, f32 or bfloat16 codes as uint16);
  *   SPMV_ARR_NL_ROWS, _NL_PTR, _NL_COL, _NL_VAL: the nonlocal part;
- *   SPMV_ARR_SEND_IDX: the send list (int32). */
+ *   SPMV_ARR_SEND_IDX: the send list (int32);
+ *   SPMV_ARR_TILES: the main part's tiles for its plan's tile_items,
+ *     n_tiles + 1 pairs (first row, first entry) of int32;
+ *   SPMV_ARR_RUNS: its run table when the plan is SPMV_KERNEL_STAGED without
+ *     panels: 12 int32 per tile, nr, L, s_0..s_3, d_0..d_3, 0, 0 -- nr runs of
+ *     columns [s_r, s_r + len_r) (nr = 0: the tile gathers from B), run r in
+ *     LDS slots s_r + d_r .. s_r + d_r + len_r - 1, L slots in all. */
 #define SPMV_ARR_ROW_PTR 0
 #define SPMV_ARR_COL 1
 #define SPMV_ARR_VAL 2
@@ -404,6 +422,8 @@ spmv_status_t spmv_get_info(spmv_handle_t h, spmv_info_t *info);
 #define SPMV_ARR_NL_COL 5
 #define SPMV_ARR_NL_VAL 6
 #define SPMV_ARR_SEND_IDX 7
+#define SPMV_ARR_TILES 8
+#define SPMV_ARR_RUNS 9
 
 spmv_status_t spmv_export(spmv_handle_t h, int32_t which, void *dst, int64_t bytes,
                           int64_t *size_bytes);

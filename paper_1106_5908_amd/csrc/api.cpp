@@ -122,11 +122,13 @@ struct DeviceGuard {
 
 // ---- host parallel loops -------------------------------------------------------
 
+// f(b, e) over chunks of [0, n) on up to 16 threads; one thread below
+// `serial_below` items.
 template <class F>
-void parallel_for(int64_t n, F &&f) {
+void parallel_for(int64_t n, F &&f, int64_t serial_below = int64_t(1) << 18) {
   unsigned T = std::thread::hardware_concurrency();
   T = std::max(1u, std::min(T, 16u));
-  if (n < (int64_t(1) << 18) || T == 1) {
+  if (n < serial_below || T == 1) {
     f(int64_t(0), n);
     return;
   }
@@ -230,6 +232,63 @@ std::vector<int32_t> make_tiles(const int32_t *rp, int64_t n, int64_t tile_items
   return t;
 }
 
+// Run table of the staged kernel (layout in spmv_internal.h): each tile's
+// distinct columns, ascending, merged into runs across gaps of at most
+// kRunGap columns (the gap columns are loaded too).  A tile gets nr = 0, and
+// is run as in the stream kernel, when it has no entries, more than
+// `max_entries` (a single long row), more than RUN_MAX runs or more than
+// `budget` columns to stage.
+constexpr int64_t kRunGap = 16;
+
+std::vector<int32_t> make_runs(const int32_t *rp, const int32_t *col,
+                               const std::vector<int32_t> &tiles, int64_t max_entries,
+                               int64_t budget) {
+  const int64_t n_tiles = int64_t(tiles.size()) - 1;
+  std::vector<int32_t> out(size_t(std::max<int64_t>(n_tiles, 0)) * RUN_WORDS, 0);
+  parallel_for(
+      n_tiles,
+      [&](int64_t b, int64_t e) {
+        std::vector<int32_t> cs;
+        for (int64_t t = b; t < e; ++t) {
+          const int64_t p0 = rp[tiles[size_t(t)]], p1 = rp[tiles[size_t(t + 1)]];
+          if (p1 - p0 < 1 || p1 - p0 > max_entries) continue;
+          cs.assign(col + p0, col + p1);
+          std::sort(cs.begin(), cs.end());
+          int64_t start[RUN_MAX], end[RUN_MAX];  // [start, end)
+          int nr = 0;
+          bool ok = true;
+          for (const int32_t c : cs) {
+            if (nr > 0 && c < end[nr - 1]) continue;  // repeated column
+            if (nr > 0 && c - end[nr - 1] <= kRunGap) {
+              end[nr - 1] = int64_t(c) + 1;
+              continue;
+            }
+            if (nr == RUN_MAX) {
+              ok = false;
+              break;
+            }
+            start[nr] = c;
+            end[nr] = int64_t(c) + 1;
+            ++nr;
+          }
+          int64_t L = 0;
+          for (int r = 0; r < nr; ++r) L += end[r] - start[r];
+          if (!ok || L > budget) continue;
+          int32_t *q = out.data() + size_t(t) * RUN_WORDS;
+          q[0] = nr;
+          q[1] = int32_t(L);
+          int64_t o = 0;
+          for (int r = 0; r < nr; ++r) {
+            q[2 + r] = int32_t(start[r]);
+            q[6 + r] = int32_t(o - start[r]);
+            o += end[r] - start[r];
+          }
+        }
+      },
+      64);
+  return out;
+}
+
 // ---- plans -------------------------------------------------------------------------
 
 spmv_plan_t default_plan() {
@@ -247,10 +306,13 @@ spmv_plan_t default_plan() {
 
 void check_plan(const spmv_plan_t &p) {
   if (p.kernel != SPMV_KERNEL_STREAM && p.kernel != SPMV_KERNEL_VECTOR &&
-      p.kernel != SPMV_KERNEL_TILE_GRID)
-    fail(SPMV_ERR_INVALID_ARG, "plan.kernel must be SPMV_KERNEL_STREAM, _VECTOR or _TILE_GRID");
+      p.kernel != SPMV_KERNEL_TILE_GRID && p.kernel != SPMV_KERNEL_STAGED)
+    fail(SPMV_ERR_INVALID_ARG,
+         "plan.kernel must be SPMV_KERNEL_STREAM, _VECTOR, _TILE_GRID or _STAGED");
   if (p.tile_items != 4 && p.tile_items != 8 && p.tile_items != 16)
     fail(SPMV_ERR_INVALID_ARG, "plan.tile_items must be 4, 8 or 16");
+  if (p.kernel == SPMV_KERNEL_STAGED && p.tile_items == 4)
+    fail(SPMV_ERR_INVALID_ARG, "the staged kernel takes tile_items 8 or 16");
   if (p.lanes < 2 || p.lanes > 64 || (p.lanes & (p.lanes - 1)))
     fail(SPMV_ERR_INVALID_ARG, "plan.lanes must be a power of two in [2, 64]");
   if (p.block_kt != 0 && p.block_kt != 4 && p.block_kt != 8 && p.block_kt != 16)
@@ -293,6 +355,7 @@ struct Part {
   std::map<int, std::vector<std::unique_ptr<Part>>> panel_sets;
   int64_t d_min = 0, d_max = 0;
   std::map<int, std::pair<DevBuf, int64_t>> tiles;  // tile_items -> (tile starts, count)
+  std::map<int, std::pair<DevBuf, int64_t>> runs;   // tile_items -> (run table, staged tiles)
 
   CsrDev dev() const {
     CsrDev d;
@@ -314,6 +377,26 @@ struct Part {
       it = tiles.emplace(items, std::make_pair(std::move(d), int64_t(t.size()) - 1)).first;
     }
     return {it->second.first.as<const TileRP>(), it->second.second};
+  }
+  // Run table of the staged kernel for tiles of `items` (built on first use
+  // from a copy of col_idx read back from the device; synchronous).
+  const int32_t *runs_for(int items, int x_bytes) {
+    auto it = runs.find(items);
+    if (it == runs.end()) {
+      const std::vector<int32_t> t = make_tiles(h_row_ptr.data(), n_rows, int64_t(kWG) * items);
+      std::vector<int32_t> hc(static_cast<size_t>(nnz));
+      if (nnz > 0)
+        hip_ok(hipMemcpy(hc.data(), col.p, size_t(nnz) * 4, hipMemcpyDeviceToHost), "col readback");
+      const std::vector<int32_t> table = make_runs(h_row_ptr.data(), hc.data(), t,
+                                                   int64_t(kWG) * items - 4,
+                                                   RUN_STAGE_BYTES / x_bytes);
+      int64_t staged = 0;
+      for (size_t i = 0; i < table.size(); i += RUN_WORDS) staged += table[i] > 0 ? 1 : 0;
+      DevBuf d;
+      upload(d, table.data(), table.size() * 4, "run table");
+      it = runs.emplace(items, std::make_pair(std::move(d), staged)).first;
+    }
+    return it->second.first.as<const int32_t>();
   }
 };
 
@@ -641,6 +724,7 @@ void encode(int64_t n_rows, int64_t nnz, const int32_t *rp, const int32_t *col, 
 }
 
 std::vector<std::unique_ptr<Part>> &build_panels(spmv_handle_s *h, Part &p, int K);
+void prepare_part(spmv_handle_s *h, Part &p);
 
 void choose_plan(spmv_handle_s *h, Part &p, const char *part_name) {
   p.plan = default_plan();
@@ -649,7 +733,10 @@ void choose_plan(spmv_handle_s *h, Part &p, const char *part_name) {
     if (cache_lookup(tune_key(h->device, h->prec, 1, part_name, p.n_rows, p.stats), &c)) p.plan = c;
   }
   if (p.plan.panels > 1 && (p.row_ids.p || h->kind == SPMV_KIND_BATCH)) p.plan.panels = 1;
+  if (h->kind == SPMV_KIND_BATCH && p.plan.kernel == SPMV_KERNEL_STAGED)
+    p.plan.kernel = SPMV_KERNEL_STREAM;
   if (p.plan.panels > 1) build_panels(h, p, p.plan.panels);
+  if (h->kind != SPMV_KIND_BATCH) prepare_part(h, p);
   if (std::getenv("SPMV_LOG"))
     std::fprintf(stderr, "libspmv: %s part n=%lld nnz=%lld mean=%.2f max=%lld cv=%.2f -> kernel=%d "
                          "tile_items=%d lanes=%d nt=%d remap=%d\n",
@@ -696,7 +783,6 @@ extern "C" spmv_status_t spmv_create_crs(int64_t n_rows, int64_t n_cols, int64_t
     m.h_row_ptr = std::move(enc.rp);
     m.stats = row_stats(m.h_row_ptr.data(), n_rows);
     choose_plan(h.get(), m, "main");
-    (void)m.tiles_for(m.plan.tile_items);
     register_handle(h.get());
     *out = h.release();
   });
@@ -779,8 +865,6 @@ extern "C" spmv_status_t spmv_split_local_nonlocal(spmv_handle_t a_, int64_t hal
     N.stats = row_stats(N.h_row_ptr.data(), R);
     choose_plan(h.get(), L, "local");
     choose_plan(h.get(), N, "nonlocal");
-    (void)L.tiles_for(L.plan.tile_items);
-    (void)N.tiles_for(N.plan.tile_items);
     hip_ok(hipStreamCreateWithFlags(&h->copy_stream, hipStreamNonBlocking), "copy stream");
     hip_ok(hipEventCreateWithFlags(&h->ev_start, hipEventDisableTiming), "event");
     hip_ok(hipEventCreateWithFlags(&h->ev_copied, hipEventDisableTiming), "event");
@@ -1057,8 +1141,28 @@ void prune_panels(Part &p, const std::vector<int> &keep) {
   }
 }
 
+// Tiles (and, for the staged kernel, run tables) of the part's plan, and of
+// its panels when the plan uses them: built here so that spmv_run only
+// enqueues work.
+void prepare_part(spmv_handle_s *h, Part &p) {
+  const int items = p.plan.tile_items;
+  const bool staged = p.plan.kernel == SPMV_KERNEL_STAGED;
+  const int xb = vec_bytes(h->prec);
+  if (p.plan.panels > 1) {
+    for (auto &q : build_panels(h, p, p.plan.panels)) {
+      (void)q->tiles_for(items);
+      if (staged) (void)q->runs_for(items, xb);
+    }
+    return;
+  }
+  (void)p.tiles_for(items);
+  if (staged) (void)p.runs_for(items, xb);
+}
+
 void run_part(spmv_handle_s *h, Part &p, const void *B, void *C, hipStream_t s) {
   if (p.n_rows == 0 || p.nnz == 0) return;
+  const bool staged = p.plan.kernel == SPMV_KERNEL_STAGED;
+  const int xb = vec_bytes(h->prec);
   if (p.plan.panels > 1) {
     auto &set = build_panels(h, p, p.plan.panels);
     spmv_plan_t sub = p.plan;
@@ -1067,13 +1171,15 @@ void run_part(spmv_handle_s *h, Part &p, const void *B, void *C, hipStream_t s) 
     for (auto &q : set) {
       if (q->nnz == 0) continue;
       auto t = q->tiles_for(sub.tile_items);
-      hip_ok(launch_spmv(h->prec, q->dev(), pl, t.first, t.second, B, C, s), "kernel launch");
+      const int32_t *r = staged ? q->runs_for(sub.tile_items, xb) : nullptr;
+      hip_ok(launch_spmv(h->prec, q->dev(), pl, t.first, r, t.second, B, C, s), "kernel launch");
     }
     return;
   }
   const PlanDev pl = to_dev(p.plan);
   auto t = p.tiles_for(p.plan.tile_items);
-  hip_ok(launch_spmv(h->prec, p.dev(), pl, t.first, t.second, B, C, s), "kernel launch");
+  const int32_t *r = staged ? p.runs_for(p.plan.tile_items, xb) : nullptr;
+  hip_ok(launch_spmv(h->prec, p.dev(), pl, t.first, r, t.second, B, C, s), "kernel launch");
 }
 
 }  // namespace
@@ -1538,6 +1644,14 @@ std::vector<spmv_plan_t> candidates() {
     p.lanes = l;
     c.push_back(p);
   }
+  for (int e : {8, 16})
+    for (int rm : {1, 0}) {
+      spmv_plan_t p = default_plan();
+      p.kernel = SPMV_KERNEL_STAGED;
+      p.tile_items = e;
+      p.xcd_remap = rm;
+      c.push_back(p);
+    }
   return c;
 }
 
@@ -1576,6 +1690,7 @@ void tune_part(spmv_handle_s *h, Part &p, const char *name, void *x, void *y, hi
   std::vector<float> times;
   for (const spmv_plan_t &c : cands) {
     p.plan = c;
+    prepare_part(h, p);
     times.push_back(tm.median_ms([&] { run_part(h, p, x, y, s); }, s));
     best = std::min(best, times.back());
   }
@@ -1589,8 +1704,7 @@ void tune_part(spmv_handle_s *h, Part &p, const char *name, void *x, void *y, hi
     }
   best_p.block_kt = 0;
   p.plan = best_p;
-  (void)p.tiles_for(p.plan.tile_items);
-  if (p.plan.panels > 1) build_panels(h, p, p.plan.panels);
+  prepare_part(h, p);
   // free the device copies of panel sets no chosen plan uses
   std::vector<int> keep{p.plan.panels};
   for (auto &bp : h->block_plans) keep.push_back(bp.second.panels);
@@ -1619,7 +1733,8 @@ extern "C" spmv_status_t spmv_set_plan(spmv_handle_t h_, int32_t part, const spm
     spmv_handle_s *h = live(h_);
     if (!plan) fail(SPMV_ERR_INVALID_ARG, "plan is null");
     check_plan(*plan);
-    if (h->kind == SPMV_KIND_BATCH && plan->kernel == SPMV_KERNEL_VECTOR)
+    if (h->kind == SPMV_KIND_BATCH &&
+        (plan->kernel == SPMV_KERNEL_VECTOR || plan->kernel == SPMV_KERNEL_STAGED))
       fail(SPMV_ERR_UNSUPPORTED, "batch handles run the stream or tile-grid kernel");
     if (h->kind != SPMV_KIND_BATCH && plan->kernel == SPMV_KERNEL_TILE_GRID)
       fail(SPMV_ERR_UNSUPPORTED, "the tile-grid kernel serves batch handles only");
@@ -1630,11 +1745,7 @@ extern "C" spmv_status_t spmv_set_plan(spmv_handle_t h_, int32_t part, const spm
       fail(SPMV_ERR_UNSUPPORTED, "diagonal panels need a part that covers all rows");
     DeviceGuard dg(h->device);
     p.plan = *plan;
-    if (h->kind != SPMV_KIND_BATCH) {
-      (void)p.tiles_for(p.plan.tile_items);
-      if (p.plan.panels > 1)
-        for (auto &q : build_panels(h, p, p.plan.panels)) (void)q->tiles_for(p.plan.tile_items);
-    }
+    if (h->kind != SPMV_KIND_BATCH) prepare_part(h, p);
   });
 }
 
@@ -1746,6 +1857,20 @@ extern "C" spmv_status_t spmv_get_info(spmv_handle_t h_, spmv_info_t *info) {
     info->row_len_cv = h->main.stats.cv;
     info->row_len_max = h->main.stats.max;
     info->n_send = h->n_send;
+    if (h->kind != SPMV_KIND_BATCH && h->main.plan.kernel == SPMV_KERNEL_STAGED) {
+      const int items = h->main.plan.tile_items;
+      auto count = [items](const Part &q) {
+        auto r = q.runs.find(items);
+        return r == q.runs.end() ? int64_t(0) : r->second.second;
+      };
+      if (h->main.plan.panels > 1) {
+        auto ps = h->main.panel_sets.find(h->main.plan.panels);
+        if (ps != h->main.panel_sets.end())
+          for (auto &q : ps->second) info->n_staged_tiles += count(*q);
+      } else {
+        info->n_staged_tiles = count(h->main);
+      }
+    }
   });
 }
 
@@ -1766,6 +1891,24 @@ extern "C" spmv_status_t spmv_export(spmv_handle_t h_, int32_t which, void *dst,
       case SPMV_ARR_NL_COL: if (split) { src = &h->nl.col; n = h->nl.nnz * 4; } break;
       case SPMV_ARR_NL_VAL: if (split) { src = &h->nl.val; n = h->nl.nnz * vb; } break;
       case SPMV_ARR_SEND_IDX: if (split) { src = &h->send_idx; n = h->n_send * 4; } break;
+      case SPMV_ARR_TILES:
+      case SPMV_ARR_RUNS: {
+        if (h->kind == SPMV_KIND_BATCH) break;
+        const int items = h->main.plan.tile_items;
+        auto t = h->main.tiles.find(items);
+        if (t == h->main.tiles.end()) break;
+        const int64_t nt = t->second.second;
+        if (which == SPMV_ARR_TILES) {
+          src = &t->second.first;
+          n = (nt + 1) * int64_t(sizeof(TileRP));
+        } else {
+          auto r = h->main.runs.find(items);
+          if (r == h->main.runs.end()) break;
+          src = &r->second.first;
+          n = nt * RUN_WORDS * 4;
+        }
+        break;
+      }
       default: break;
     }
     if (!src) fail(SPMV_ERR_INVALID_ARG, "no such array in this handle");

@@ -26,6 +26,8 @@
 // rows without entries leave C untouched.
 #include <hip/hip_runtime.h>
 
+#include <climits>
+
 #include "spmv_internal.h"
 
 namespace spmv {
@@ -405,6 +407,91 @@ __global__ __launch_bounds__(WG) void k_stream(CsrDev A, const TileRP *__restric
 }
 
 // ---------------------------------------------------------------------------
+// Staged stream kernel.  A tile of a stencil-like matrix reads B from a few
+// contiguous column ranges (one per plane of neighbours).  The planner
+// merges each tile's columns into at most RUN_MAX ascending runs and records
+// them in a run table (see spmv_internal.h); the workgroup loads the runs
+// into LDS with coalesced loads issued before the tile's col_idx / val, and
+// each entry then reads its B value from LDS at col + d_r (r: the last run
+// starting at or below col).  The gathers thus leave the chain that follows
+// the col_idx loads.  A tile whose table row says nr = 0 is run as in the
+// stream kernel.  The arithmetic is the stream kernel's: the same products
+// summed in the same order.
+// ---------------------------------------------------------------------------
+template <int P, int E, bool NT, bool IND>
+__global__ __launch_bounds__(WG) void k_staged(CsrDev A, const TileRP *__restrict__ tiles,
+                                               const int32_t *__restrict__ runs, int64_t n_tiles,
+                                               int remap, const void *xv, void *yv) {
+  using V = typename Ty<P>::V;
+  using X = typename Ty<P>::X;
+  constexpr int G = group_of<V>();
+  constexpr int NB = RUN_STAGE_BYTES / (WG * (int)sizeof(X));
+  __shared__ X s_prod[WG * E + WG * NB];
+  X *s_b = s_prod + WG * E;
+  const V *__restrict__ val = static_cast<const V *>(A.val);
+  const X *__restrict__ x = static_cast<const X *>(xv);
+  X *__restrict__ y = static_cast<X *>(yv);
+  const int64_t t = xcd_tile(blockIdx.x, n_tiles, remap);
+  const int32_t *__restrict__ rt = runs + t * RUN_WORDS;
+  const int nr = rt[0];
+  const TileRP m0 = tiles[t], m1 = tiles[t + 1];
+  if (nr == 0) {
+    tile_grouped<P, E, NT, IND>(A.row_ptr, A.col, val, A.row_ids, m0, m1, 0, x, y, s_prod);
+    return;
+  }
+  // nr in [1, RUN_MAX]; L in [1, WG * NB]; 1 <= nnz <= WG * E - 4 (planner)
+  const int L = rt[1];
+  const int d0 = rt[6], d1 = rt[7], d2 = rt[8], d3 = rt[9];
+  const int s1 = nr > 1 ? rt[3] : INT_MAX, s2 = nr > 2 ? rt[4] : INT_MAX,
+            s3 = nr > 3 ? rt[5] : INT_MAX;
+  const int o1 = nr > 1 ? s1 + d1 : INT_MAX, o2 = nr > 2 ? s2 + d2 : INT_MAX,
+            o3 = nr > 3 ? s3 + d3 : INT_MAX;
+  const int tid = (int)threadIdx.x;
+  // LDS slot i holds B[i - d_r], r the last run whose slots start at or
+  // below i; slots past L load slot L - 1 again and are not stored.
+  X bst[NB];
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    const int slot = min(i * WG + tid, L - 1);
+    int d = d0;
+    if (slot >= o1) d = d1;
+    if (slot >= o2) d = d2;
+    if (slot >= o3) d = d3;
+    bst[i] = x[slot - d];
+  }
+  const int nnz = m1.p - m0.p;
+  const int nrows = m1.r - m0.r;
+  const int off = m0.p % G;
+  const int base = m0.p - off;
+  int c[E];
+  V v[E];
+  load_cv_groups<E, NT>(A.col, val, base, nnz, off, c, v);
+  const RowSlot<X> slot = row_slot<X, IND>(A.row_ptr, A.row_ids, m0.r, nrows, base, y);
+#pragma unroll
+  for (int i = 0; i < NB; ++i)
+    if (i * WG + tid < L) s_b[i * WG + tid] = bst[i];
+  lds_barrier();
+  X xg[E];
+#pragma unroll
+  for (int e = 0; e < E; ++e) {
+    const int cc = c[e];
+    int d = d0;
+    if (cc >= s1) d = d1;
+    if (cc >= s2) d = d2;
+    if (cc >= s3) d = d3;
+    xg[e] = s_b[cc + d];
+  }
+#pragma unroll
+  for (int e = 0; e < E / G; ++e) {
+    const int g = e * WG + tid;
+#pragma unroll
+    for (int j = 0; j < G; ++j) s_prod[G * g + j] = widen<X>(v[G * e + j]) * xg[G * e + j];
+  }
+  lds_barrier();
+  tile_reduce<X, IND>(A.row_ptr, A.row_ids, m0.r, nrows, base, slot, y, s_prod);
+}
+
+// ---------------------------------------------------------------------------
 // Vector kernel: L lanes per row, rows_per_wg consecutive rows per workgroup.
 // ---------------------------------------------------------------------------
 template <int P, int L, bool NT>
@@ -702,9 +789,41 @@ hipError_t run_vector(const CsrDev &A, const PlanDev &pl, const void *x, void *y
   return hipGetLastError();
 }
 
+template <int P, int E>
+hipError_t run_staged(const CsrDev &A, const PlanDev &pl, const TileRP *tiles,
+                      const int32_t *runs, int64_t n_tiles, const void *x, void *y,
+                      hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  if (!runs) return hipErrorInvalidValue;
+  if (A.row_ids) {
+    if (pl.nontemporal)
+      hipLaunchKernelGGL((k_staged<P, E, true, true>), dim3((unsigned)n_tiles), dim3(WG), 0, s, A,
+                         tiles, runs, n_tiles, pl.xcd_remap, x, y);
+    else
+      hipLaunchKernelGGL((k_staged<P, E, false, true>), dim3((unsigned)n_tiles), dim3(WG), 0, s, A,
+                         tiles, runs, n_tiles, pl.xcd_remap, x, y);
+  } else {
+    if (pl.nontemporal)
+      hipLaunchKernelGGL((k_staged<P, E, true, false>), dim3((unsigned)n_tiles), dim3(WG), 0, s, A,
+                         tiles, runs, n_tiles, pl.xcd_remap, x, y);
+    else
+      hipLaunchKernelGGL((k_staged<P, E, false, false>), dim3((unsigned)n_tiles), dim3(WG), 0, s,
+                         A, tiles, runs, n_tiles, pl.xcd_remap, x, y);
+  }
+  return hipGetLastError();
+}
+
 template <int P>
-hipError_t dispatch_spmv(const CsrDev &A, const PlanDev &pl, const TileRP *tiles, int64_t n_tiles,
-                         const void *x, void *y, hipStream_t s) {
+hipError_t dispatch_spmv(const CsrDev &A, const PlanDev &pl, const TileRP *tiles,
+                         const int32_t *runs, int64_t n_tiles, const void *x, void *y,
+                         hipStream_t s) {
+  if (pl.kernel == 4) {
+    switch (pl.tile_items) {
+      case 8: return run_staged<P, 8>(A, pl, tiles, runs, n_tiles, x, y, s);
+      case 16: return run_staged<P, 16>(A, pl, tiles, runs, n_tiles, x, y, s);
+      default: return hipErrorInvalidValue;
+    }
+  }
   if (pl.kernel == 2) {
     switch (pl.lanes) {
       case 2: return run_vector<P, 2>(A, pl, x, y, s);
@@ -826,8 +945,9 @@ int persistent_grid_for(int device) {
   }
 
 hipError_t launch_spmv(int prec, const CsrDev &A, const PlanDev &plan, const TileRP *tiles,
-                       int64_t n_tiles, const void *x, void *y, hipStream_t s) {
-  SPMV_PREC_SWITCH(prec, (dispatch_spmv<PP>(A, plan, tiles, n_tiles, x, y, s)))
+                       const int32_t *runs, int64_t n_tiles, const void *x, void *y,
+                       hipStream_t s) {
+  SPMV_PREC_SWITCH(prec, (dispatch_spmv<PP>(A, plan, tiles, runs, n_tiles, x, y, s)))
 }
 
 hipError_t launch_spmv_block(int prec, const CsrDev &A, const TileRP *tiles, int64_t n_tiles,

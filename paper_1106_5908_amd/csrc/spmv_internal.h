@@ -25,13 +25,23 @@ struct CsrDev {
 };
 
 struct PlanDev {
-  int kernel;       // 1 stream, 2 vector
+  int kernel;       // 1 stream, 2 vector, 4 staged stream
   int tile_items;   // stream: products per thread (tile = 256 * tile_items)
   int lanes;        // vector: lanes per row
   int nontemporal;  // streaming hint on val / col
   int xcd_remap;    // place consecutive tiles on one XCD
   int tiles_per_group;  // stream: consecutive tiles per workgroup (software pipelined)
 };
+
+// Run table of the staged kernel: RUN_WORDS int32 per tile,
+//   nr, L, s_0 .. s_3, d_0 .. d_3, 0, 0
+// nr runs (1..RUN_MAX) of columns [s_r, s_r + len_r), ascending and
+// disjoint, that cover every column the tile's entries read; run r fills
+// LDS slots [s_r + d_r, s_r + d_r + len_r), L slots in all, at most
+// RUN_STAGE_BYTES of B.  nr = 0: the tile is run as in the stream kernel.
+constexpr int RUN_WORDS = 12;
+constexpr int RUN_MAX = 4;
+constexpr int RUN_STAGE_BYTES = 12288;
 
 // Start of a tile: first row and first stored entry (row_ptr[r]).  A part
 // with T tiles has T + 1 of these; the last one is (n_rows, nnz).
@@ -59,8 +69,10 @@ struct BatchTile {
 // ---- launchers (kernels.hip) -------------------------------------------------
 // All return hipSuccess or the launch error.  `tiles` (stream and block
 // kernels) holds the n_tiles + 1 tile starts of `A`.
+// `runs`: the run table of the tiles (staged kernel only, else unused).
 hipError_t launch_spmv(int prec, const CsrDev &A, const PlanDev &plan, const TileRP *tiles,
-                       int64_t n_tiles, const void *x, void *y, hipStream_t s);
+                       const int32_t *runs, int64_t n_tiles, const void *x, void *y,
+                       hipStream_t s);
 
 // Block product C = C + scale*A*B; `scale` is 1, or a power of two so that the
 // scaled values are exact.

@@ -46,6 +46,7 @@ SPMV_FLAG_NO_TUNE_CACHE = 0x2
 SPMV_KERNEL_STREAM = 1
 SPMV_KERNEL_VECTOR = 2
 SPMV_KERNEL_TILE_GRID = 3
+SPMV_KERNEL_STAGED = 4
 SPMV_PART_MAIN = 0
 SPMV_PART_NONLOCAL = 1
 
@@ -61,6 +62,8 @@ SPMV_ARR_NL_PTR = 4
 SPMV_ARR_NL_COL = 5
 SPMV_ARR_NL_VAL = 6
 SPMV_ARR_SEND_IDX = 7
+SPMV_ARR_TILES = 8
+SPMV_ARR_RUNS = 9
 
 SPMV_SCHEDULE_OVERLAP = 0
 SPMV_SCHEDULE_SERIAL = 1
@@ -100,6 +103,7 @@ class spmv_info_t(ctypes.Structure):
         ("batch_count", ctypes.c_int32), ("n_tiles", ctypes.c_int64),
         ("row_len_mean", ctypes.c_double), ("row_len_cv", ctypes.c_double),
         ("row_len_max", ctypes.c_int64), ("n_send", ctypes.c_int64),
+        ("n_staged_tiles", ctypes.c_int64),
     ]
 
 
@@ -461,7 +465,8 @@ def spmv_get_info(h: Handle) -> dict:
 
 
 _EXPORT_DTYPE = {SPMV_ARR_ROW_PTR: np.int32, SPMV_ARR_COL: np.int32, SPMV_ARR_NL_ROWS: np.int32,
-                 SPMV_ARR_NL_PTR: np.int32, SPMV_ARR_NL_COL: np.int32, SPMV_ARR_SEND_IDX: np.int32}
+                 SPMV_ARR_NL_PTR: np.int32, SPMV_ARR_NL_COL: np.int32, SPMV_ARR_SEND_IDX: np.int32,
+                 SPMV_ARR_TILES: np.int32, SPMV_ARR_RUNS: np.int32}
 
 
 def spmv_export(h: Handle, which: int) -> np.ndarray:
@@ -472,6 +477,10 @@ def spmv_export(h: Handle, which: int) -> np.ndarray:
     dt = _EXPORT_DTYPE.get(which, VAL_DTYPE[h.prec])
     out = np.empty(size.value // np.dtype(dt).itemsize, dtype=dt)
     _check(lib.spmv_export(_ptr(h), which, _hp(out), size.value, ctypes.byref(size)))
+    if which == SPMV_ARR_TILES:
+        return out.reshape(-1, 2)  # (first row, first entry) per tile start
+    if which == SPMV_ARR_RUNS:
+        return out.reshape(-1, 12)
     return out
 
 

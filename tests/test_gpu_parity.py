@@ -41,7 +41,8 @@ PLANS = ([dict(kernel=1, tile_items=e, nontemporal=nt, xcd_remap=rm)
          [dict(kernel=1, tile_items=e, panels=k, xcd_remap=rm)
           for e in (4, 8) for k in (2, 4, 8) for rm in (0, 1)] +
          [dict(kernel=1, tile_items=8, panels=4, tiles_per_group=4)] +
-         [dict(kernel=2, lanes=l) for l in (2, 4, 8, 16, 32, 64)])
+         [dict(kernel=2, lanes=l) for l in (2, 4, 8, 16, 32, 64)] +
+         [dict(kernel=4, tile_items=e, nontemporal=nt) for e in (8, 16) for nt in (0, 1)])
 
 
 def _pid(p):
@@ -93,7 +94,8 @@ def _long_row_matrix(long_len, n_short=300, n_cols=20000, seed=3):
                          [dict(kernel=1, tile_items=e, tiles_per_group=t) for e in (4, 8)
                           for t in (3, 16)] +
                          [dict(kernel=1, tile_items=8, panels=k) for k in (2, 8)] +
-                         [dict(kernel=2, lanes=64)], ids=_pid)
+                         [dict(kernel=2, lanes=64)] +
+                         [dict(kernel=4, tile_items=e) for e in (8, 16)], ids=_pid)
 def test_long_rows(long_len, plan):
     A = _long_row_matrix(long_len)
     x = gen.uniform_vector(A.n_cols, gen.rng_for(10, 5))
@@ -365,8 +367,9 @@ def test_split_run_matches_oracle(schedule):
 
 
 @pytest.mark.parametrize("plan", [None, dict(kernel=1, tile_items=8, panels=4),
-                                  dict(kernel=2, lanes=8), dict(kernel=1, tile_items=16, tiles_per_group=4)],
-                         ids=["default", "panels4", "vector8", "pipelined"])
+                                  dict(kernel=2, lanes=8), dict(kernel=1, tile_items=16, tiles_per_group=4),
+                                  dict(kernel=4, tile_items=8)],
+                         ids=["default", "panels4", "vector8", "pipelined", "staged8"])
 def test_local_part_never_reads_halo(plan):
     """The receive area B[h:] holds NaN and no halo is copied: rows without a
     halo entry are computed by the local part alone and must be finite and
@@ -761,7 +764,8 @@ def test_set_plan_validation():
     A, _ = mats()["irregular"]
     h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, flags=NOTUNE)
     try:
-        for bad in (dict(kernel=4), dict(kernel=3), dict(tile_items=5), dict(lanes=3), dict(block_kt=2),
+        for bad in (dict(kernel=5), dict(kernel=0), dict(kernel=3), dict(kernel=4, tile_items=4),
+                    dict(tile_items=5), dict(lanes=3), dict(block_kt=2),
                     dict(tiles_per_group=0), dict(tiles_per_group=65), dict(panels=3)):
             with pytest.raises(spmv.SpmvError):
                 spmv.spmv_set_plan(h, **bad)

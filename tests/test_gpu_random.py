@@ -26,6 +26,8 @@ PLANS = st.one_of(
     st.builds(lambda e, k: dict(kernel=1, tile_items=e, panels=k),
               st.sampled_from([4, 8]), st.sampled_from([2, 4, 8])),
     st.builds(lambda l: dict(kernel=2, lanes=l), st.sampled_from([2, 4, 8, 16, 32, 64])),
+    st.builds(lambda e, nt: dict(kernel=4, tile_items=e, nontemporal=nt),
+              st.sampled_from([8, 16]), st.integers(0, 1)),
 )
 
 
