@@ -1677,12 +1677,48 @@ std::vector<spmv_plan_t> panel_candidates() {
   return c;
 }
 
+// Whether the staged kernel can stage most tiles of `items` entries per
+// lane: the run rule applied to up to 64 tiles spread over the part, whose
+// columns alone are read back.  Saves building whole run tables (a copy of
+// col_idx and a sort per tile) for matrices whose tiles would all gather.
+bool staged_promising(const spmv_handle_s *h, const Part &p, int items) {
+  const std::vector<int32_t> t = make_tiles(p.h_row_ptr.data(), p.n_rows, int64_t(kWG) * items);
+  const int64_t n_tiles = int64_t(t.size()) - 1;
+  if (n_tiles <= 0) return false;
+  const int64_t n_sample = std::min<int64_t>(64, n_tiles);
+  std::vector<int32_t> rp_s{0}, tiles_s{0}, col_s;
+  for (int64_t i = 0; i < n_sample; ++i) {
+    const int64_t k = i * n_tiles / n_sample;
+    const int64_t p0 = p.h_row_ptr[size_t(t[size_t(k)])], p1 = p.h_row_ptr[size_t(t[size_t(k + 1)])];
+    const size_t at = col_s.size();
+    col_s.resize(at + size_t(p1 - p0));
+    if (p1 > p0)
+      hip_ok(hipMemcpy(col_s.data() + at, p.col.as<int32_t>() + p0, size_t(p1 - p0) * 4,
+                       hipMemcpyDeviceToHost),
+             "col readback");
+    rp_s.push_back(int32_t(col_s.size()));  // one pseudo-row per sampled tile
+    tiles_s.push_back(int32_t(i + 1));
+  }
+  const std::vector<int32_t> table =
+      make_runs(rp_s.data(), col_s.data(), tiles_s, int64_t(kWG) * items - 4,
+                RUN_STAGE_BYTES / vec_bytes(h->prec));
+  int64_t fit = 0;
+  for (size_t i = 0; i < table.size(); i += RUN_WORDS) fit += table[i] > 0 ? 1 : 0;
+  return 2 * fit > n_sample;
+}
+
 void tune_part(spmv_handle_s *h, Part &p, const char *name, void *x, void *y, hipStream_t s,
                Timer &tm) {
   if (p.n_rows == 0 || p.nnz == 0) return;
   float best = 1e30f;
   spmv_plan_t best_p = p.plan;
-  std::vector<spmv_plan_t> cands = candidates();
+  std::vector<spmv_plan_t> cands;
+  {
+    const bool promising[2] = {staged_promising(h, p, 8), staged_promising(h, p, 16)};
+    for (const spmv_plan_t &c : candidates())
+      if (c.kernel != SPMV_KERNEL_STAGED || promising[c.tile_items == 16 ? 1 : 0])
+        cands.push_back(c);
+  }
   if (!p.row_ids.p) {
     const std::vector<spmv_plan_t> pc = panel_candidates();
     cands.insert(cands.end(), pc.begin(), pc.end());
