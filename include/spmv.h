@@ -332,7 +332,8 @@ spmv_status_t spmv_create_batch(int32_t count, const int64_t *n_rows, const int6
  *                fit is run as in the stream kernel.  Stencil-like
  *                matrices, whose tiles read a few contiguous column ranges,
  *                gain; the run table (48 bytes per tile) is built on the host
- *                from a copy of col_idx read back once.  Not for batches.
+ *                from a copy of col_idx read back once.  For batch handles:
+ *                one workgroup per batch tile, as SPMV_KERNEL_TILE_GRID.
  *   tile_items   4, 8 or 16 (stream kernel); 8 or 16 (staged kernel)
  *   lanes        2, 4, 8, 16, 32 or 64 (vector kernel)
  *   nontemporal  1: val and col_idx are loaded with the streaming hint so

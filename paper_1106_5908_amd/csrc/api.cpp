@@ -240,6 +240,39 @@ std::vector<int32_t> make_tiles(const int32_t *rp, int64_t n, int64_t tile_items
 // `budget` columns to stage.
 constexpr int64_t kRunGap = 16;
 
+// One row of the run table for the n columns of one tile (q: RUN_WORDS
+// int32, zeroed by the caller); `cs` is scratch.
+void run_row(const int32_t *cols, int64_t n, int64_t max_entries, int64_t budget,
+             std::vector<int32_t> &cs, int32_t *q) {
+  if (n < 1 || n > max_entries) return;
+  cs.assign(cols, cols + n);
+  std::sort(cs.begin(), cs.end());
+  int64_t start[RUN_MAX], end[RUN_MAX];  // [start, end)
+  int nr = 0;
+  for (const int32_t c : cs) {
+    if (nr > 0 && c < end[nr - 1]) continue;  // repeated column
+    if (nr > 0 && c - end[nr - 1] <= kRunGap) {
+      end[nr - 1] = int64_t(c) + 1;
+      continue;
+    }
+    if (nr == RUN_MAX) return;  // more runs than the kernel takes
+    start[nr] = c;
+    end[nr] = int64_t(c) + 1;
+    ++nr;
+  }
+  int64_t L = 0;
+  for (int r = 0; r < nr; ++r) L += end[r] - start[r];
+  if (L > budget) return;
+  q[0] = nr;
+  q[1] = int32_t(L);
+  int64_t o = 0;
+  for (int r = 0; r < nr; ++r) {
+    q[2 + r] = int32_t(start[r]);
+    q[6 + r] = int32_t(o - start[r]);
+    o += end[r] - start[r];
+  }
+}
+
 std::vector<int32_t> make_runs(const int32_t *rp, const int32_t *col,
                                const std::vector<int32_t> &tiles, int64_t max_entries,
                                int64_t budget) {
@@ -251,38 +284,7 @@ std::vector<int32_t> make_runs(const int32_t *rp, const int32_t *col,
         std::vector<int32_t> cs;
         for (int64_t t = b; t < e; ++t) {
           const int64_t p0 = rp[tiles[size_t(t)]], p1 = rp[tiles[size_t(t + 1)]];
-          if (p1 - p0 < 1 || p1 - p0 > max_entries) continue;
-          cs.assign(col + p0, col + p1);
-          std::sort(cs.begin(), cs.end());
-          int64_t start[RUN_MAX], end[RUN_MAX];  // [start, end)
-          int nr = 0;
-          bool ok = true;
-          for (const int32_t c : cs) {
-            if (nr > 0 && c < end[nr - 1]) continue;  // repeated column
-            if (nr > 0 && c - end[nr - 1] <= kRunGap) {
-              end[nr - 1] = int64_t(c) + 1;
-              continue;
-            }
-            if (nr == RUN_MAX) {
-              ok = false;
-              break;
-            }
-            start[nr] = c;
-            end[nr] = int64_t(c) + 1;
-            ++nr;
-          }
-          int64_t L = 0;
-          for (int r = 0; r < nr; ++r) L += end[r] - start[r];
-          if (!ok || L > budget) continue;
-          int32_t *q = out.data() + size_t(t) * RUN_WORDS;
-          q[0] = nr;
-          q[1] = int32_t(L);
-          int64_t o = 0;
-          for (int r = 0; r < nr; ++r) {
-            q[2 + r] = int32_t(start[r]);
-            q[6 + r] = int32_t(o - start[r]);
-            o += end[r] - start[r];
-          }
+          run_row(col + p0, p1 - p0, max_entries, budget, cs, out.data() + size_t(t) * RUN_WORDS);
         }
       },
       64);
@@ -433,6 +435,9 @@ struct spmv_handle_s {
   int64_t b_ntiles = 0;
   int b_tiles_items = 0;
   int b_grid = 0;
+  DevBuf b_runs;           // run table of the batch tiles (staged kernel)
+  int b_runs_items = 0;
+  int64_t b_staged = 0;
   hipStream_t cap_stream = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t gexec = nullptr;
@@ -733,8 +738,6 @@ void choose_plan(spmv_handle_s *h, Part &p, const char *part_name) {
     if (cache_lookup(tune_key(h->device, h->prec, 1, part_name, p.n_rows, p.stats), &c)) p.plan = c;
   }
   if (p.plan.panels > 1 && (p.row_ids.p || h->kind == SPMV_KIND_BATCH)) p.plan.panels = 1;
-  if (h->kind == SPMV_KIND_BATCH && p.plan.kernel == SPMV_KERNEL_STAGED)
-    p.plan.kernel = SPMV_KERNEL_STREAM;
   if (p.plan.panels > 1) build_panels(h, p, p.plan.panels);
   if (h->kind != SPMV_KIND_BATCH) prepare_part(h, p);
   if (std::getenv("SPMV_LOG"))
@@ -967,9 +970,14 @@ extern "C" spmv_status_t spmv_create_batch(int32_t count, const int64_t *n_rows,
 namespace {
 
 // Tile queue of a batch for the current tile size.
+void batch_runs(spmv_handle_s *h);
+
 void batch_prepare(spmv_handle_s *h) {
   const int items = h->main.plan.tile_items;
-  if (h->b_tiles_items == items && h->b_tiles.p) return;
+  if (h->b_tiles_items == items && h->b_tiles.p) {
+    if (h->main.plan.kernel == SPMV_KERNEL_STAGED && h->b_runs_items != items) batch_runs(h);
+    return;
+  }
   std::vector<BatchTile> tl;
   for (int32_t m = 0; m < h->count; ++m) {
     const BatchDesc &d = h->h_desc[size_t(m)];
@@ -984,9 +992,47 @@ void batch_prepare(spmv_handle_s *h) {
   h->b_tiles_items = items;
   h->b_grid = batch_persistent_grid(h->prec, items, h->device);
   h->h_btiles = std::move(tl);
+  if (h->main.plan.kernel == SPMV_KERNEL_STAGED) batch_runs(h);
+}
+
+// Run table of the batch tiles for the staged kernel, from a copy of the
+// pooled (member-local) col_idx read back once.
+void batch_runs(spmv_handle_s *h) {
+  const int items = h->b_tiles_items;
+  const Part &M = h->main;
+  std::vector<int32_t> hc(static_cast<size_t>(M.nnz));
+  if (M.nnz > 0)
+    hip_ok(hipMemcpy(hc.data(), M.col.p, size_t(M.nnz) * 4, hipMemcpyDeviceToHost), "col readback");
+  const int64_t nt = int64_t(h->h_btiles.size());
+  std::vector<int32_t> table(size_t(nt) * RUN_WORDS, 0);
+  const int64_t budget = RUN_STAGE_BYTES / vec_bytes(h->prec);
+  parallel_for(
+      nt,
+      [&](int64_t b, int64_t e) {
+        std::vector<int32_t> cs;
+        for (int64_t t = b; t < e; ++t) {
+          const BatchTile &T = h->h_btiles[size_t(t)];
+          const BatchDesc &D = h->h_desc[size_t(T.member)];
+          const int64_t p0 = M.h_row_ptr[size_t(D.rp_off + T.r0)];
+          const int64_t p1 = M.h_row_ptr[size_t(D.rp_off + T.r1)];
+          run_row(hc.data() + D.nz_off + p0, p1 - p0, int64_t(kWG) * items - 4, budget, cs,
+                  table.data() + size_t(t) * RUN_WORDS);
+        }
+      },
+      64);
+  int64_t staged = 0;
+  for (size_t i = 0; i < table.size(); i += RUN_WORDS) staged += table[i] > 0 ? 1 : 0;
+  upload(h->b_runs, table.data(), table.size() * 4, "batch run table");
+  h->b_runs_items = items;
+  h->b_staged = staged;
 }
 
 hipError_t batch_launch_direct(spmv_handle_s *h, const void *B, void *C, hipStream_t s) {
+  if (h->main.plan.kernel == SPMV_KERNEL_STAGED)
+    return launch_batch_staged(h->prec, h->main.row_ptr.as<int32_t>(), h->main.col.as<int32_t>(),
+                               h->main.val.p, h->b_desc.as<BatchDesc>(), h->b_tiles.as<BatchTile>(),
+                               h->b_runs.as<int32_t>(), h->b_ntiles, h->b_tiles_items,
+                               h->main.plan.nontemporal, B, C, s);
   if (h->main.plan.kernel == SPMV_KERNEL_TILE_GRID)
     return launch_batch_flat(h->prec, h->main.row_ptr.as<int32_t>(), h->main.col.as<int32_t>(),
                              h->main.val.p, h->b_desc.as<BatchDesc>(), h->b_tiles.as<BatchTile>(),
@@ -1769,9 +1815,8 @@ extern "C" spmv_status_t spmv_set_plan(spmv_handle_t h_, int32_t part, const spm
     spmv_handle_s *h = live(h_);
     if (!plan) fail(SPMV_ERR_INVALID_ARG, "plan is null");
     check_plan(*plan);
-    if (h->kind == SPMV_KIND_BATCH &&
-        (plan->kernel == SPMV_KERNEL_VECTOR || plan->kernel == SPMV_KERNEL_STAGED))
-      fail(SPMV_ERR_UNSUPPORTED, "batch handles run the stream or tile-grid kernel");
+    if (h->kind == SPMV_KIND_BATCH && plan->kernel == SPMV_KERNEL_VECTOR)
+      fail(SPMV_ERR_UNSUPPORTED, "batch handles run the stream, tile-grid or staged kernel");
     if (h->kind != SPMV_KIND_BATCH && plan->kernel == SPMV_KERNEL_TILE_GRID)
       fail(SPMV_ERR_UNSUPPORTED, "the tile-grid kernel serves batch handles only");
     if (h->kind == SPMV_KIND_BATCH && plan->panels != 1)
@@ -1781,7 +1826,10 @@ extern "C" spmv_status_t spmv_set_plan(spmv_handle_t h_, int32_t part, const spm
       fail(SPMV_ERR_UNSUPPORTED, "diagonal panels need a part that covers all rows");
     DeviceGuard dg(h->device);
     p.plan = *plan;
-    if (h->kind != SPMV_KIND_BATCH) prepare_part(h, p);
+    if (h->kind != SPMV_KIND_BATCH)
+      prepare_part(h, p);
+    else
+      batch_prepare(h);
   });
 }
 
@@ -1806,13 +1854,15 @@ extern "C" spmv_status_t spmv_tune(spmv_handle_t h_, int32_t k, void *stream) {
       spmv_plan_t best_p = keep;
       const int saved_sched = h->schedule;
       h->schedule = SPMV_SCHEDULE_BATCH_DIRECT;
-      for (int kern : {SPMV_KERNEL_STREAM, SPMV_KERNEL_TILE_GRID})
+      for (int kern : {SPMV_KERNEL_STREAM, SPMV_KERNEL_TILE_GRID, SPMV_KERNEL_STAGED})
       for (int e : {4, 8, 16})
         for (int nt : {1, 0}) {
+          if (kern == SPMV_KERNEL_STAGED && e == 4) continue;
           p.plan = keep;
           p.plan.kernel = kern;
           p.plan.tile_items = e;
           p.plan.nontemporal = nt;
+          batch_prepare(h);  // tiles and run tables before the timing
           const float ms = tm.median_ms([&] { batch_run(h, x.p, y.p, s); }, s);
           if (ms < best) {
             best = ms;
@@ -1893,6 +1943,8 @@ extern "C" spmv_status_t spmv_get_info(spmv_handle_t h_, spmv_info_t *info) {
     info->row_len_cv = h->main.stats.cv;
     info->row_len_max = h->main.stats.max;
     info->n_send = h->n_send;
+    if (h->kind == SPMV_KIND_BATCH && h->main.plan.kernel == SPMV_KERNEL_STAGED)
+      info->n_staged_tiles = h->b_staged;
     if (h->kind != SPMV_KIND_BATCH && h->main.plan.kernel == SPMV_KERNEL_STAGED) {
       const int items = h->main.plan.tile_items;
       auto count = [items](const Part &q) {

@@ -418,25 +418,28 @@ __global__ __launch_bounds__(WG) void k_stream(CsrDev A, const TileRP *__restric
 // stream kernel.  The arithmetic is the stream kernel's: the same products
 // summed in the same order.
 // ---------------------------------------------------------------------------
+// LDS elements of B a staged tile may hold.
+template <class X> constexpr int stage_slots() { return RUN_STAGE_BYTES / (int)sizeof(X); }
+
+// One tile of the staged kernel; `rt` is its run-table row and s_prod holds
+// WG * E + stage_slots<X>() elements.  `bias` as in tile_grouped.
 template <int P, int E, bool NT, bool IND>
-__global__ __launch_bounds__(WG) void k_staged(CsrDev A, const TileRP *__restrict__ tiles,
-                                               const int32_t *__restrict__ runs, int64_t n_tiles,
-                                               int remap, const void *xv, void *yv) {
+__device__ __forceinline__ void staged_tile(const int32_t *__restrict__ rp,
+                                            const int32_t *__restrict__ col,
+                                            const typename Ty<P>::V *__restrict__ val,
+                                            const int32_t *__restrict__ row_ids, TileRP m0,
+                                            TileRP m1, int bias, const int32_t *__restrict__ rt,
+                                            const typename Ty<P>::X *__restrict__ x,
+                                            typename Ty<P>::X *__restrict__ y,
+                                            typename Ty<P>::X *s_prod) {
   using V = typename Ty<P>::V;
   using X = typename Ty<P>::X;
   constexpr int G = group_of<V>();
-  constexpr int NB = RUN_STAGE_BYTES / (WG * (int)sizeof(X));
-  __shared__ X s_prod[WG * E + WG * NB];
+  constexpr int NB = stage_slots<X>() / WG;
   X *s_b = s_prod + WG * E;
-  const V *__restrict__ val = static_cast<const V *>(A.val);
-  const X *__restrict__ x = static_cast<const X *>(xv);
-  X *__restrict__ y = static_cast<X *>(yv);
-  const int64_t t = xcd_tile(blockIdx.x, n_tiles, remap);
-  const int32_t *__restrict__ rt = runs + t * RUN_WORDS;
   const int nr = rt[0];
-  const TileRP m0 = tiles[t], m1 = tiles[t + 1];
   if (nr == 0) {
-    tile_grouped<P, E, NT, IND>(A.row_ptr, A.col, val, A.row_ids, m0, m1, 0, x, y, s_prod);
+    tile_grouped<P, E, NT, IND>(rp, col, val, row_ids, m0, m1, bias, x, y, s_prod);
     return;
   }
   // nr in [1, RUN_MAX]; L in [1, WG * NB]; 1 <= nnz <= WG * E - 4 (planner)
@@ -461,12 +464,12 @@ __global__ __launch_bounds__(WG) void k_staged(CsrDev A, const TileRP *__restric
   }
   const int nnz = m1.p - m0.p;
   const int nrows = m1.r - m0.r;
-  const int off = m0.p % G;
+  const int off = (m0.p + bias) % G;
   const int base = m0.p - off;
   int c[E];
   V v[E];
-  load_cv_groups<E, NT>(A.col, val, base, nnz, off, c, v);
-  const RowSlot<X> slot = row_slot<X, IND>(A.row_ptr, A.row_ids, m0.r, nrows, base, y);
+  load_cv_groups<E, NT>(col, val, base, nnz, off, c, v);
+  const RowSlot<X> slot = row_slot<X, IND>(rp, row_ids, m0.r, nrows, base, y);
 #pragma unroll
   for (int i = 0; i < NB; ++i)
     if (i * WG + tid < L) s_b[i * WG + tid] = bst[i];
@@ -488,7 +491,20 @@ __global__ __launch_bounds__(WG) void k_staged(CsrDev A, const TileRP *__restric
     for (int j = 0; j < G; ++j) s_prod[G * g + j] = widen<X>(v[G * e + j]) * xg[G * e + j];
   }
   lds_barrier();
-  tile_reduce<X, IND>(A.row_ptr, A.row_ids, m0.r, nrows, base, slot, y, s_prod);
+  tile_reduce<X, IND>(rp, row_ids, m0.r, nrows, base, slot, y, s_prod);
+}
+
+template <int P, int E, bool NT, bool IND>
+__global__ __launch_bounds__(WG) void k_staged(CsrDev A, const TileRP *__restrict__ tiles,
+                                               const int32_t *__restrict__ runs, int64_t n_tiles,
+                                               int remap, const void *xv, void *yv) {
+  using V = typename Ty<P>::V;
+  using X = typename Ty<P>::X;
+  __shared__ X s_prod[WG * E + stage_slots<X>()];
+  const int64_t t = xcd_tile(blockIdx.x, n_tiles, remap);
+  staged_tile<P, E, NT, IND>(A.row_ptr, A.col, static_cast<const V *>(A.val), A.row_ids, tiles[t],
+                             tiles[t + 1], 0, runs + t * RUN_WORDS, static_cast<const X *>(xv),
+                             static_cast<X *>(yv), s_prod);
 }
 
 // ---------------------------------------------------------------------------
@@ -744,6 +760,29 @@ __global__ __launch_bounds__(WG) void k_batch_flat(const int32_t *__restrict__ r
   batch_tile<P, E, NT>(rp, col, val, desc, T, xv, yv, s_prod);
 }
 
+// Batch tiles with the staged kernel's tile: one workgroup per tile, the run
+// table row of tile t at runs + t * RUN_WORDS (member-local columns).
+template <int P, int E, bool NT>
+__global__ __launch_bounds__(WG) void k_batch_staged(const int32_t *__restrict__ rp,
+                                                     const int32_t *__restrict__ col,
+                                                     const void *val, const BatchDesc *desc,
+                                                     const BatchTile *tiles,
+                                                     const int32_t *__restrict__ runs,
+                                                     int64_t n_tiles, const void *xv, void *yv) {
+  using V = typename Ty<P>::V;
+  using X = typename Ty<P>::X;
+  __shared__ X s_prod[WG * E + stage_slots<X>()];
+  const int64_t t = xcd_tile(blockIdx.x, n_tiles, 1);
+  const BatchTile T = tiles[t];
+  const BatchDesc D = desc[T.member];
+  const int32_t *mrp = rp + D.rp_off;
+  const TileRP m0{T.r0, mrp[T.r0]}, m1{T.r1, mrp[T.r1]};
+  staged_tile<P, E, NT, false>(mrp, col + D.nz_off, static_cast<const V *>(val) + D.nz_off, nullptr,
+                               m0, m1, (int)(D.nz_off % group_of<V>()), runs + t * RUN_WORDS,
+                               static_cast<const X *>(xv) + D.x_off,
+                               static_cast<X *>(yv) + D.y_off, s_prod);
+}
+
 // ---------------------------------------------------------------------------
 // Dispatch helpers
 // ---------------------------------------------------------------------------
@@ -996,6 +1035,41 @@ static hipError_t flat_e(const int32_t *rp, const int32_t *col, const void *val,
     case 16: return run_flat<P, 16>(rp, col, val, desc, tiles, n_tiles, nt, x, y, s);
     default: return hipErrorInvalidValue;
   }
+}
+
+template <int P, int E>
+hipError_t run_batch_staged(const int32_t *rp, const int32_t *col, const void *val,
+                            const BatchDesc *desc, const BatchTile *tiles, const int32_t *runs,
+                            int64_t n_tiles, int nt, const void *x, void *y, hipStream_t s) {
+  if (n_tiles <= 0) return hipSuccess;
+  if (!runs) return hipErrorInvalidValue;
+  if (nt)
+    hipLaunchKernelGGL((k_batch_staged<P, E, true>), dim3((unsigned)n_tiles), dim3(WG), 0, s, rp,
+                       col, val, desc, tiles, runs, n_tiles, x, y);
+  else
+    hipLaunchKernelGGL((k_batch_staged<P, E, false>), dim3((unsigned)n_tiles), dim3(WG), 0, s, rp,
+                       col, val, desc, tiles, runs, n_tiles, x, y);
+  return hipGetLastError();
+}
+
+template <int P>
+static hipError_t batch_staged_e(const int32_t *rp, const int32_t *col, const void *val,
+                                 const BatchDesc *desc, const BatchTile *tiles,
+                                 const int32_t *runs, int64_t n_tiles, int tile_items, int nt,
+                                 const void *x, void *y, hipStream_t s) {
+  switch (tile_items) {
+    case 8: return run_batch_staged<P, 8>(rp, col, val, desc, tiles, runs, n_tiles, nt, x, y, s);
+    case 16: return run_batch_staged<P, 16>(rp, col, val, desc, tiles, runs, n_tiles, nt, x, y, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+hipError_t launch_batch_staged(int prec, const int32_t *rp, const int32_t *col, const void *val,
+                               const BatchDesc *desc, const BatchTile *tiles, const int32_t *runs,
+                               int64_t n_tiles, int tile_items, int nontemporal, const void *x,
+                               void *y, hipStream_t s) {
+  SPMV_PREC_SWITCH(prec, (batch_staged_e<PP>(rp, col, val, desc, tiles, runs, n_tiles, tile_items,
+                                             nontemporal, x, y, s)))
 }
 
 hipError_t launch_batch_flat(int prec, const int32_t *rp, const int32_t *col, const void *val,

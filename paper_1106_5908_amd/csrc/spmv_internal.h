@@ -93,6 +93,13 @@ hipError_t launch_batch_flat(int prec, const int32_t *rp, const int32_t *col, co
                              const BatchDesc *desc, const BatchTile *tiles, int64_t n_tiles,
                              int tile_items, int nontemporal, const void *x, void *y, hipStream_t s);
 
+// The staged kernel over batch tiles (tile_items 8 or 16): one workgroup per
+// tile, `runs` the run table of the n_tiles batch tiles (member-local columns).
+hipError_t launch_batch_staged(int prec, const int32_t *rp, const int32_t *col, const void *val,
+                               const BatchDesc *desc, const BatchTile *tiles, const int32_t *runs,
+                               int64_t n_tiles, int tile_items, int nontemporal, const void *x,
+                               void *y, hipStream_t s);
+
 int batch_persistent_grid(int prec, int tile_items, int device);
 
 // ---- split bookkeeping (split.hip) -------------------------------------------

@@ -633,10 +633,12 @@ def _batch(count=40, nmax=30000, seed_extra=1):
     return gen.workload_c5_batch(count=count, nmin=1000, nmax=nmax, seed_extra=seed_extra)
 
 
-@pytest.mark.parametrize("kernel", [spmv.SPMV_KERNEL_STREAM, spmv.SPMV_KERNEL_TILE_GRID])
+@pytest.mark.parametrize("kernel,tile_items",
+                         [(k, e) for k in (spmv.SPMV_KERNEL_STREAM, spmv.SPMV_KERNEL_TILE_GRID)
+                          for e in (4, 8, 16)] +
+                         [(spmv.SPMV_KERNEL_STAGED, e) for e in (8, 16)])
 @pytest.mark.parametrize("schedule", [spmv.SPMV_SCHEDULE_BATCH_GRAPH, spmv.SPMV_SCHEDULE_BATCH_DIRECT,
                                       spmv.SPMV_SCHEDULE_BATCH_FLAT])
-@pytest.mark.parametrize("tile_items", [4, 8, 16])
 def test_batch_matches_members(schedule, tile_items, kernel):
     import torch
 
@@ -662,7 +664,8 @@ def test_batch_matches_members(schedule, tile_items, kernel):
         off += A.n_rows
 
 
-@pytest.mark.parametrize("kernel", [spmv.SPMV_KERNEL_STREAM, spmv.SPMV_KERNEL_TILE_GRID])
+@pytest.mark.parametrize("kernel", [spmv.SPMV_KERNEL_STREAM, spmv.SPMV_KERNEL_TILE_GRID,
+                                    spmv.SPMV_KERNEL_STAGED])
 def test_batch_graph_replays_and_recapture(kernel):
     import torch
 

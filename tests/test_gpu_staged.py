@@ -7,7 +7,8 @@ contiguous, within the budget; a tile left to gather must really not fit),
 then the products are compared with the oracle on stencils, where most tiles
 are staged, and on matrices where tiles fall back, in every precision, for
 split handles (local part next to a NaN receive area, nonlocal part) and with
-diagonal panels.  Integer data must match bit for bit."""
+diagonal panels, and over the tiles of a batch.  Integer data must match
+bit for bit."""
 from __future__ import annotations
 
 import numpy as np
@@ -297,9 +298,41 @@ def test_validation():
     b = spmv.spmv_create_batch([(A.row_ptr, A.col_idx, A.val, A.n_cols)] * 2)
     try:
         with pytest.raises(spmv.SpmvError) as ei:
-            spmv.spmv_set_plan(b, **staged(16))
-        assert ei.value.status == spmv.SPMV_ERR_UNSUPPORTED
+            spmv.spmv_set_plan(b, **staged(4))
+        assert ei.value.status == spmv.SPMV_ERR_INVALID_ARG
         with pytest.raises(spmv.SpmvError):
             spmv.spmv_export(b, spmv.SPMV_ARR_RUNS)
     finally:
         spmv.spmv_destroy(b)
+
+
+@pytest.mark.parametrize("e", [8, 16])
+def test_batch_members(e):
+    """A batch of stencils of many sizes plus a random member: most batch
+    tiles are staged, and every member's rows match the oracle."""
+    import torch
+
+    rng = gen.rng_for(47, e)
+    mem = [gen.laplace_5pt_2d(int(n)) for n in (17, 64, 150, 301)]
+    mem += [gen.laplace_7pt_3d(int(n)) for n in (9, 20, 33)]
+    mem += [gen.stencil_27pt_3d(12), gen.random_crs(900, 1300, rng, max_len=9)]
+    xs = [gen.uniform_vector(A.n_cols, rng) for A in mem]
+    c0 = gen.uniform_vector(sum(A.n_rows for A in mem), rng)
+    h = spmv.spmv_create_batch([(A.row_ptr, A.col_idx, A.val, A.n_cols) for A in mem], flags=NOTUNE)
+    try:
+        spmv.spmv_set_plan(h, **staged(e))
+        info = spmv.spmv_get_info(h)
+        assert info["n_staged_tiles"] > 0.5 * info["n_tiles"], info
+        B = to_dev(np.concatenate(xs), "f64")
+        C = to_dev(c0, "f64")
+        spmv.spmv_run(h, B, C)
+        torch.cuda.synchronize()
+        got = C.cpu().numpy()
+    finally:
+        spmv.spmv_destroy(h)
+    off = 0
+    for A, x in zip(mem, xs):
+        sl = slice(off, off + A.n_rows)
+        ref, den = oracle_ref(A, x, c0[sl])
+        assert_close(got[sl], ref, den, FP64_TOL, f"member at {off}")
+        off += A.n_rows
