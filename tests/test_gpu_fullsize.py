@@ -56,6 +56,32 @@ def test_27pt160_fp64(c2):
     assert_close(got, ref, den, FP64_TOL, f"27-point 160^3 FP64, plan {plan}")
 
 
+@pytest.mark.parametrize("plan", [dict(kernel=spmv.SPMV_KERNEL_STAGED, tile_items=16),
+                                  dict(kernel=spmv.SPMV_KERNEL_STREAM, tile_items=16)],
+                         ids=["staged16", "stream16"])
+def test_27pt160_fp64_fixed_plans(c2, plan):
+    """The two kernels the tuner chooses between on this matrix, each at the
+    full size whatever the tuner picks; the staged one must stage nearly
+    every tile."""
+    import torch
+
+    A, x, ref, den = c2
+    h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, flags=NOTUNE)
+    try:
+        spmv.spmv_set_plan(h, **plan)
+        info = spmv.spmv_get_info(h)
+        if plan["kernel"] == spmv.SPMV_KERNEL_STAGED:
+            assert info["n_staged_tiles"] > 0.99 * info["n_tiles"], info
+        B = to_dev(x, "f64")
+        C = torch.zeros(A.n_rows, dtype=B.dtype, device="cuda")
+        spmv.spmv_run(h, B, C)
+        torch.cuda.synchronize()
+        got = C.cpu().numpy()
+    finally:
+        spmv.spmv_destroy(h)
+    assert_close(got, ref, den, FP64_TOL, f"27-point 160^3 FP64, plan {plan}")
+
+
 def test_27pt160_integer_bit_exact():
     A = gen.stencil_27pt_3d(160)
     x = gen.integer_vector(A.n_cols, gen.rng_for(2, 9), vmax=8)
