@@ -7,6 +7,8 @@ data must match bit for bit; random data to the FP64 bound or the
 reduced-precision bounds."""
 from __future__ import annotations
 
+import os
+
 import numpy as np
 import pytest
 from hypothesis import HealthCheck, given, settings
@@ -17,6 +19,10 @@ from gpu_util import FP64_TOL, assert_close, gpu_spmv, prec_bounds, rounded_inpu
 from workloads import gen
 
 pytestmark = pytest.mark.gpu
+
+# examples per test (SPMV_RANDOM_EXAMPLES scales a longer search)
+N_FP64 = int(os.environ.get("SPMV_RANDOM_EXAMPLES", "60"))
+N_REDUCED = max(1, N_FP64 // 2)
 
 PLANS = st.one_of(
     st.builds(lambda e, nt, rm, tpw: dict(kernel=1, tile_items=e, nontemporal=nt, xcd_remap=rm,
@@ -64,7 +70,7 @@ def matrices(draw):
     return gen.CRS(n_rows, n_cols, rp, cols, vals), x, c0, integer
 
 
-@settings(max_examples=60, deadline=None, suppress_health_check=list(HealthCheck))
+@settings(max_examples=N_FP64, deadline=None, suppress_health_check=list(HealthCheck))
 @given(m=matrices(), plan=PLANS, base=st.integers(0, 1))
 def test_random_fp64(m, plan, base):
     A, x, c0, integer = m
@@ -78,7 +84,7 @@ def test_random_fp64(m, plan, base):
         assert_close(got, ref, den, FP64_TOL, str(plan))
 
 
-@settings(max_examples=30, deadline=None, suppress_health_check=list(HealthCheck))
+@settings(max_examples=N_REDUCED, deadline=None, suppress_health_check=list(HealthCheck))
 @given(m=matrices(), plan=PLANS, prec=st.sampled_from(["f32", "bf16", "f32f64"]))
 def test_random_reduced_precision(m, plan, prec):
     A, x, c0, integer = m
