@@ -382,6 +382,48 @@ def atomic_probe(nnz27: int, n27: int, head_ms: float, iters: int = 100):
     return out
 
 
+def symmetric_path(steps: int, warmup: int):
+    """Symmetric storage (Sect. 1.3.1) on the unperturbed 27-point 160^3
+    stencil (26 / -1, exactly symmetric): the upper triangle with the
+    transposed half scattered by atomic adds, against full storage of the
+    same matrix, each with its tuned plan.  Integer B, so both results are
+    exact and must agree bit for bit."""
+    import torch
+
+    from paper_1106_5908_amd import spmv
+    from workloads import gen
+
+    A = gen.stencil_27pt_3d(160)
+    U = gen.upper_triangle(A)
+    x = gen.integer_vector(A.n_cols, gen.rng_for(2, 11), vmax=8)
+    B = torch.from_numpy(x).to("cuda")
+    hf = make_handle(A)
+    hs = spmv.spmv_create_sym_crs(U.row_ptr, U.col_idx, U.val, flags=spmv.SPMV_FLAG_NO_TUNE_CACHE)
+    spmv.spmv_tune(hs)
+    out = {"n_rows": A.n_rows, "nnz_full": A.nnz, "nnz_upper": U.nnz,
+           "plan_full": spmv.spmv_get_plan(hf), "plan_symmetric": spmv.spmv_get_plan(hs)}
+    res = []
+    for h in (hf, hs):
+        C = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+        spmv.spmv_run(h, B, C)
+        torch.cuda.synchronize()
+        res.append(C.cpu().numpy())
+        t = time_launches(lambda: spmv.spmv_run(h, B, C), steps, warmup)
+        out["full_ms" if h is hf else "symmetric_ms"] = t["p50_ms"]
+    out["results_bit_exact"] = bool(np.array_equal(res[0], res[1]))
+    out["matrix_bytes_full"] = A.nnz * 12 + 4 * (A.n_rows + 1)
+    out["matrix_bytes_symmetric"] = U.nnz * 12 + 4 * (A.n_rows + 1)
+    out["symmetric_over_full_time"] = out["symmetric_ms"] / out["full_ms"]
+    spmv.spmv_destroy(hs)
+    spmv.spmv_destroy(hf)
+    del A, U, B
+    torch.cuda.empty_cache()
+    log(f"symmetric storage: {out['symmetric_ms'] * 1e3:.0f} us against {out['full_ms'] * 1e3:.0f} us "
+        f"for full storage ({out['nnz_upper']} of {out['nnz_full']} entries stored; results equal: "
+        f"{out['results_bit_exact']})")
+    return out
+
+
 def split_paths(A, x, steps, warmup):
     """The three schedules of Fig. 5 on one GPU: (a) blocking halo copy then
     the unsplit kernel, (b) split kernels with the copy serialised on the
@@ -1200,6 +1242,7 @@ def main():
     if args.only == "all":
         paths["headline_cold"] = cold_headline(A2, x2, head["plan"])
         paths["atomic_probe"] = atomic_probe(A2.nnz, A2.n_rows, head["ms_per_step"])
+        paths["symmetric_27pt160"] = symmetric_path(max(10, args.steps // 4), 3)
         prec_rows = []
         for prec in ("f32", "bf16", "f32f64"):
             r, _, _ = run_spmv_path(A2, x2, prec, args.steps, args.warmup, "27pt160", ref2, den2)

@@ -310,6 +310,31 @@ spmv_status_t spmv_create_batch(int32_t count, const int64_t *n_rows, const int6
                                 spmv_handle_t *out);
 
 /* ---------------------------------------------------------------------------
+ * Symmetric storage: the upper triangle only, the variant Sect. 1.3.1
+ * describes for symmetric matrices and sets aside, because the transposed
+ * half of the product writes into entries of C that other rows (other
+ * threads) also write.
+ *
+ * row_ptr / col_idx / val: the upper triangle U of a symmetric n x n matrix
+ * A in CRS, as for spmv_create_crs (index_base, duplicates and empty rows as
+ * there), with every column at or right of its row (col >= row).  spmv_run on
+ * the handle computes C = C + A*B with A = U + U^T - diag(U): each stored
+ * entry a_ij adds a_ij * B[j] to C[i] and, for j != i, a_ij * B[i] to C[j].
+ * The additions into C are device-scope atomic adds, so their order, and the
+ * rounding of C, may differ from call to call; B and C are as for plain
+ * handles.  Plans: SPMV_KERNEL_VECTOR only (`lanes` lanes per row, the
+ * streaming hint, the XCD remap); spmv_tune searches them.  Other entry
+ * points (split, block, batch, moments, Lanczos) return
+ * SPMV_ERR_UNSUPPORTED for symmetric handles.
+ * Errors: as spmv_create_crs; SPMV_ERR_INVALID_MATRIX for an entry left of
+ * the diagonal; SPMV_ERR_UNSUPPORTED for a precision other than
+ * SPMV_PREC_F64.
+ * ------------------------------------------------------------------------- */
+spmv_status_t spmv_create_sym_crs(int64_t n, int64_t nnz, const int32_t *row_ptr,
+                                  const int32_t *col_idx, const double *val, int32_t index_base,
+                                  int32_t prec, uint32_t flags, spmv_handle_t *out);
+
+/* ---------------------------------------------------------------------------
  * a10: kernel plans and the autotuner.
  *
  * A plan says how rows are mapped to the GPU for one part of a handle
@@ -385,6 +410,7 @@ spmv_status_t spmv_tune(spmv_handle_t h, int32_t k, void *stream);
 #define SPMV_KIND_PLAIN 0
 #define SPMV_KIND_SPLIT 1
 #define SPMV_KIND_BATCH 2
+#define SPMV_KIND_SYMMETRIC 3
 
 typedef struct spmv_info {
     int32_t kind;          /* SPMV_KIND_* */

@@ -733,6 +733,17 @@ void prepare_part(spmv_handle_s *h, Part &p);
 
 void choose_plan(spmv_handle_s *h, Part &p, const char *part_name) {
   p.plan = default_plan();
+  if (h->kind == SPMV_KIND_SYMMETRIC) {  // the symmetric kernel: lanes per row only
+    p.plan.kernel = SPMV_KERNEL_VECTOR;
+    p.plan.lanes = 16;
+    if (!(h->flags & SPMV_FLAG_NO_TUNE_CACHE)) {
+      spmv_plan_t c;
+      if (cache_lookup(tune_key(h->device, h->prec, 1, "symmetric", p.n_rows, p.stats), &c) &&
+          c.kernel == SPMV_KERNEL_VECTOR && c.panels == 1)
+        p.plan = c;
+    }
+    return;
+  }
   if (!(h->flags & SPMV_FLAG_NO_TUNE_CACHE)) {
     spmv_plan_t c;
     if (cache_lookup(tune_key(h->device, h->prec, 1, part_name, p.n_rows, p.stats), &c)) p.plan = c;
@@ -756,6 +767,38 @@ int current_device() {
 
 }  // namespace
 
+namespace {
+
+// Plain or symmetric handle from host CRS arrays (validated by the caller).
+spmv_handle_s *create_handle(int kind, int64_t n_rows, int64_t n_cols, int64_t nnz,
+                             const int32_t *row_ptr, const int32_t *col_idx, const double *val,
+                             int32_t index_base, int p, uint32_t flags) {
+  Encoded enc;
+  encode(n_rows, nnz, row_ptr, col_idx, val, index_base, p, enc);
+  std::unique_ptr<spmv_handle_s> h(new spmv_handle_s());
+  h->device = current_device();
+  h->prec = p;
+  h->flags = flags;
+  h->kind = kind;
+  h->n_rows = n_rows;
+  h->n_cols = n_cols;
+  h->nnz = nnz;
+  h->halo_begin = n_cols;
+  Part &m = h->main;
+  m.n_rows = n_rows;
+  m.nnz = nnz;
+  upload(m.row_ptr, enc.rp.data(), enc.rp.size() * 4, "row_ptr");
+  upload(m.col, enc.col_ptr, size_t(nnz) * 4, "col_idx");
+  upload(m.val, enc.val_ptr, size_t(nnz) * val_bytes(p), "val");
+  m.h_row_ptr = std::move(enc.rp);
+  m.stats = row_stats(m.h_row_ptr.data(), n_rows);
+  choose_plan(h.get(), m, kind == SPMV_KIND_SYMMETRIC ? "symmetric" : "main");
+  register_handle(h.get());
+  return h.release();
+}
+
+}  // namespace
+
 extern "C" spmv_status_t spmv_create_crs(int64_t n_rows, int64_t n_cols, int64_t nnz,
                                          const int32_t *row_ptr, const int32_t *col_idx,
                                          const double *val, int32_t index_base,
@@ -766,28 +809,34 @@ extern "C" spmv_status_t spmv_create_crs(int64_t n_rows, int64_t n_cols, int64_t
     *out = nullptr;
     const int p = check_prec(prec);
     validate_crs(n_rows, n_cols, nnz, row_ptr, col_idx, val, index_base, "");
-    Encoded enc;
-    encode(n_rows, nnz, row_ptr, col_idx, val, index_base, p, enc);
-    std::unique_ptr<spmv_handle_s> h(new spmv_handle_s());
-    h->device = current_device();
-    h->prec = p;
-    h->flags = flags;
-    h->kind = SPMV_KIND_PLAIN;
-    h->n_rows = n_rows;
-    h->n_cols = n_cols;
-    h->nnz = nnz;
-    h->halo_begin = n_cols;
-    Part &m = h->main;
-    m.n_rows = n_rows;
-    m.nnz = nnz;
-    upload(m.row_ptr, enc.rp.data(), enc.rp.size() * 4, "row_ptr");
-    upload(m.col, enc.col_ptr, size_t(nnz) * 4, "col_idx");
-    upload(m.val, enc.val_ptr, size_t(nnz) * val_bytes(p), "val");
-    m.h_row_ptr = std::move(enc.rp);
-    m.stats = row_stats(m.h_row_ptr.data(), n_rows);
-    choose_plan(h.get(), m, "main");
-    register_handle(h.get());
-    *out = h.release();
+    *out = create_handle(SPMV_KIND_PLAIN, n_rows, n_cols, nnz, row_ptr, col_idx, val, index_base,
+                         p, flags);
+  });
+}
+
+// ==== symmetric storage (Sect. 1.3.1) ==========================================================
+
+extern "C" spmv_status_t spmv_create_sym_crs(int64_t n, int64_t nnz, const int32_t *row_ptr,
+                                             const int32_t *col_idx, const double *val,
+                                             int32_t index_base, int32_t prec, uint32_t flags,
+                                             spmv_handle_t *out) {
+  return guarded([&] {
+    if (!out) fail(SPMV_ERR_INVALID_ARG, "out is null");
+    *out = nullptr;
+    const int p = check_prec(prec);
+    if (p != P_F64) fail(SPMV_ERR_UNSUPPORTED, "symmetric storage is served in SPMV_PREC_F64 only");
+    validate_crs(n, n, nnz, row_ptr, col_idx, val, index_base, "");
+    for (int64_t i = 0; i < n; ++i)
+      for (int64_t j = int64_t(row_ptr[i]) - index_base; j < int64_t(row_ptr[i + 1]) - index_base;
+           ++j)
+        if (int64_t(col_idx[j]) - index_base < i)
+          fail(SPMV_ERR_INVALID_MATRIX, "col_idx[" + std::to_string(j) + "] = " +
+                                            std::to_string(col_idx[j]) +
+                                            " lies left of the diagonal of row " +
+                                            std::to_string(i + index_base) +
+                                            " (symmetric storage keeps the upper triangle)");
+    *out = create_handle(SPMV_KIND_SYMMETRIC, n, n, nnz, row_ptr, col_idx, val, index_base, p,
+                         flags);
   });
 }
 
@@ -1230,6 +1279,18 @@ void run_part(spmv_handle_s *h, Part &p, const void *B, void *C, hipStream_t s) 
 
 }  // namespace
 
+namespace {
+
+void run_sym(spmv_handle_s *h, const void *B, void *C, hipStream_t s) {
+  const Part &p = h->main;
+  if (p.n_rows == 0 || p.nnz == 0) return;
+  hip_ok(launch_spmv_sym(p.dev(), p.plan.lanes, p.plan.nontemporal, p.plan.xcd_remap,
+                         static_cast<const double *>(B), static_cast<double *>(C), s),
+         "symmetric kernel launch");
+}
+
+}  // namespace
+
 // ==== a3-a7, a9: C = C + A*B ========================================================================
 
 extern "C" spmv_status_t spmv_run(spmv_handle_t h_, const void *B, void *C,
@@ -1244,6 +1305,8 @@ extern "C" spmv_status_t spmv_run(spmv_handle_t h_, const void *B, void *C,
       if (B_halo_host) fail(SPMV_ERR_INVALID_ARG, "B_halo_host is only accepted by split handles");
       if (h->kind == SPMV_KIND_PLAIN)
         run_part(h, h->main, B, C, s);
+      else if (h->kind == SPMV_KIND_SYMMETRIC)
+        run_sym(h, B, C, s);
       else
         batch_run(h, B, C, s);
       return;
@@ -1817,6 +1880,8 @@ extern "C" spmv_status_t spmv_set_plan(spmv_handle_t h_, int32_t part, const spm
     check_plan(*plan);
     if (h->kind == SPMV_KIND_BATCH && plan->kernel == SPMV_KERNEL_VECTOR)
       fail(SPMV_ERR_UNSUPPORTED, "batch handles run the stream, tile-grid or staged kernel");
+    if (h->kind == SPMV_KIND_SYMMETRIC && (plan->kernel != SPMV_KERNEL_VECTOR || plan->panels != 1))
+      fail(SPMV_ERR_UNSUPPORTED, "symmetric handles take SPMV_KERNEL_VECTOR plans (lanes per row)");
     if (h->kind != SPMV_KIND_BATCH && plan->kernel == SPMV_KERNEL_TILE_GRID)
       fail(SPMV_ERR_UNSUPPORTED, "the tile-grid kernel serves batch handles only");
     if (h->kind == SPMV_KIND_BATCH && plan->panels != 1)
@@ -1826,10 +1891,10 @@ extern "C" spmv_status_t spmv_set_plan(spmv_handle_t h_, int32_t part, const spm
       fail(SPMV_ERR_UNSUPPORTED, "diagonal panels need a part that covers all rows");
     DeviceGuard dg(h->device);
     p.plan = *plan;
-    if (h->kind != SPMV_KIND_BATCH)
-      prepare_part(h, p);
-    else
+    if (h->kind == SPMV_KIND_BATCH)
       batch_prepare(h);
+    else if (h->kind != SPMV_KIND_SYMMETRIC)
+      prepare_part(h, p);
   });
 }
 
@@ -1873,6 +1938,28 @@ extern "C" spmv_status_t spmv_tune(spmv_handle_t h_, int32_t k, void *stream) {
       p.plan = best_p;
       if (!(h->flags & SPMV_FLAG_NO_TUNE_CACHE))
         cache_store(tune_key(h->device, h->prec, 1, "batch", p.n_rows, p.stats), p.plan);
+      return;
+    }
+    if (h->kind == SPMV_KIND_SYMMETRIC) {
+      if (k != 1) fail(SPMV_ERR_UNSUPPORTED, "symmetric handles serve one right-hand side");
+      Part &p = h->main;
+      float best = 1e30f;
+      spmv_plan_t best_p = p.plan;
+      for (int l : {4, 8, 16, 32, 64})
+        for (int nt : {1, 0}) {
+          p.plan = default_plan();
+          p.plan.kernel = SPMV_KERNEL_VECTOR;
+          p.plan.lanes = l;
+          p.plan.nontemporal = nt;
+          const float ms = tm.median_ms([&] { run_sym(h, x.p, y.p, s); }, s);
+          if (ms < best * 0.99f) {
+            best = ms;
+            best_p = p.plan;
+          }
+        }
+      p.plan = best_p;
+      if (!(h->flags & SPMV_FLAG_NO_TUNE_CACHE))
+        cache_store(tune_key(h->device, h->prec, 1, "symmetric", p.n_rows, p.stats), p.plan);
       return;
     }
     if (k == 1) {

@@ -543,6 +543,46 @@ __global__ __launch_bounds__(WG) void k_vector(CsrDev A, int64_t rows_per_wg, in
 }
 
 // ---------------------------------------------------------------------------
+// Symmetric kernel (FP64): A = U + U^T - diag(U) from its upper triangle U,
+// every stored column at or right of its row (the storage Sect. 1.3.1
+// describes and sets aside).  L lanes share a row: each entry adds
+// val * B[col] to the row's sum and, off the diagonal, scatters val * B[row]
+// into C[col] with a device-scope atomic add.  Other rows scatter into
+// C[row] at the same time, so the row's sum is added atomically too; the
+// order of the additions into one C entry is not fixed.
+// ---------------------------------------------------------------------------
+template <int L, bool NT>
+__global__ __launch_bounds__(WG) void k_sym(CsrDev A, int64_t rows_per_wg, int64_t n_wg, int remap,
+                                            const double *__restrict__ x, double *y) {
+  constexpr int G = WG / L;
+  const double *__restrict__ val = static_cast<const double *>(A.val);
+  const int64_t b = xcd_tile(blockIdx.x, n_wg, remap);
+  const int64_t rb = b * rows_per_wg;
+  const int64_t re = min(rb + rows_per_wg, A.n_rows);
+  const int g = threadIdx.x / L;
+  const int lane = threadIdx.x % L;
+  for (int64_t base = rb; base < re; base += G) {
+    const int64_t r = base + g;
+    int a = 0, e = 0;
+    double xr = 0.0;
+    if (r < re) {
+      a = A.row_ptr[r];
+      e = A.row_ptr[r + 1];
+      xr = x[r];
+    }
+    double acc = -0.0;
+    for (int j = a + lane; j < e; j += L) {
+      const int c = ld<int32_t, NT>(A.col + j);
+      const double v = ld<double, NT>(val + j);
+      acc += v * x[c];
+      if (c != r) unsafeAtomicAdd(y + c, v * xr);
+    }
+    for (int off = L >> 1; off > 0; off >>= 1) acc += __shfl_xor(acc, off);
+    if (lane == 0 && e > a) unsafeAtomicAdd(y + r, acc);
+  }
+}
+
+// ---------------------------------------------------------------------------
 // Block kernel: columns [t0, t0 + KT) of k right-hand sides.  Each row is
 // handled by G = KT / VW lanes; lane l owns columns t0 + l*VW .. + VW - 1.
 // Every stored value is multiplied by `scale` as it is staged: 1 for
@@ -987,6 +1027,33 @@ hipError_t launch_spmv(int prec, const CsrDev &A, const PlanDev &plan, const Til
                        const int32_t *runs, int64_t n_tiles, const void *x, void *y,
                        hipStream_t s) {
   SPMV_PREC_SWITCH(prec, (dispatch_spmv<PP>(A, plan, tiles, runs, n_tiles, x, y, s)))
+}
+
+template <int L>
+hipError_t run_sym(const CsrDev &A, int nt, int remap, const double *x, double *y, hipStream_t s) {
+  if (A.n_rows <= 0) return hipSuccess;
+  const int64_t rows_per_wg = (int64_t)(WG / L) * 8;
+  const int64_t n_wg = (A.n_rows + rows_per_wg - 1) / rows_per_wg;
+  if (nt)
+    hipLaunchKernelGGL((k_sym<L, true>), dim3((unsigned)n_wg), dim3(WG), 0, s, A, rows_per_wg, n_wg,
+                       remap, x, y);
+  else
+    hipLaunchKernelGGL((k_sym<L, false>), dim3((unsigned)n_wg), dim3(WG), 0, s, A, rows_per_wg,
+                       n_wg, remap, x, y);
+  return hipGetLastError();
+}
+
+hipError_t launch_spmv_sym(const CsrDev &A, int lanes, int nontemporal, int xcd_remap,
+                           const double *x, double *y, hipStream_t s) {
+  switch (lanes) {
+    case 2: return run_sym<2>(A, nontemporal, xcd_remap, x, y, s);
+    case 4: return run_sym<4>(A, nontemporal, xcd_remap, x, y, s);
+    case 8: return run_sym<8>(A, nontemporal, xcd_remap, x, y, s);
+    case 16: return run_sym<16>(A, nontemporal, xcd_remap, x, y, s);
+    case 32: return run_sym<32>(A, nontemporal, xcd_remap, x, y, s);
+    case 64: return run_sym<64>(A, nontemporal, xcd_remap, x, y, s);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 hipError_t launch_spmv_block(int prec, const CsrDev &A, const TileRP *tiles, int64_t n_tiles,

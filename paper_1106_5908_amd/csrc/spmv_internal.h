@@ -74,6 +74,11 @@ hipError_t launch_spmv(int prec, const CsrDev &A, const PlanDev &plan, const Til
                        const int32_t *runs, int64_t n_tiles, const void *x, void *y,
                        hipStream_t s);
 
+// Symmetric product from the upper triangle (FP64; `lanes` a power of two in
+// [2, 64]): C = C + (U + U^T - diag U) B with atomic adds into C.
+hipError_t launch_spmv_sym(const CsrDev &A, int lanes, int nontemporal, int xcd_remap,
+                           const double *x, double *y, hipStream_t s);
+
 // Block product C = C + scale*A*B; `scale` is 1, or a power of two so that the
 // scaled values are exact.
 hipError_t launch_spmv_block(int prec, const CsrDev &A, const TileRP *tiles, int64_t n_tiles,

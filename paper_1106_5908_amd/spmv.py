@@ -53,6 +53,7 @@ SPMV_PART_NONLOCAL = 1
 SPMV_KIND_PLAIN = 0
 SPMV_KIND_SPLIT = 1
 SPMV_KIND_BATCH = 2
+SPMV_KIND_SYMMETRIC = 3
 
 SPMV_ARR_ROW_PTR = 0
 SPMV_ARR_COL = 1
@@ -72,7 +73,8 @@ SPMV_SCHEDULE_BATCH_DIRECT = 2
 SPMV_SCHEDULE_BATCH_FLAT = 3
 
 EXPORTED = [
-    "spmv_create_crs", "spmv_split_local_nonlocal", "spmv_run", "spmv_run_block",
+    "spmv_create_crs", "spmv_create_sym_crs", "spmv_split_local_nonlocal", "spmv_run",
+    "spmv_run_block",
     "spmv_destroy", "spmv_last_error", "spmv_create_batch", "spmv_get_plan",
     "spmv_set_plan", "spmv_tune", "spmv_get_info", "spmv_export", "spmv_probe_copy",
     "spmv_probe_triad", "spmv_probe_read", "spmv_probe_spin", "spmv_set_schedule",
@@ -133,6 +135,7 @@ def load():
     lib = ctypes.CDLL(LIB_PATH)
     sig = {
         "spmv_create_crs": [_i64, _i64, _i64, _vp, _vp, _vp, _i32, _i32, ctypes.c_uint32, _vp],
+        "spmv_create_sym_crs": [_i64, _i64, _vp, _vp, _vp, _i32, _i32, ctypes.c_uint32, _vp],
         "spmv_split_local_nonlocal": [_vp, _i64, _vp],
         "spmv_run": [_vp, _vp, _vp, _vp, _vp],
         "spmv_run_block": [_vp, _i32, _vp, _i64, _vp, _i64, _vp],
@@ -239,6 +242,21 @@ def spmv_create_crs(row_ptr, col_idx, val, n_cols: int, index_base: int = 0,
                                   _hp(ci), _hp(v), index_base, PREC[prec], flags,
                                   ctypes.byref(out)))
     return Handle(out.value, prec, SPMV_KIND_PLAIN)
+
+
+def spmv_create_sym_crs(row_ptr, col_idx, val, index_base: int = 0, prec: str = "f64",
+                        flags: int = 0) -> Handle:
+    """spmv_create_sym_crs: the upper triangle (col >= row) of a symmetric
+    matrix in host CRS arrays; spmv_run then applies the whole matrix."""
+    prec = _prec(prec)
+    rp = _as(row_ptr, np.int32)
+    ci = _as(col_idx, np.int32)
+    v = _as(val, np.float64)
+    out = ctypes.c_void_p()
+    _check(load().spmv_create_sym_crs(rp.size - 1, ci.size, _hp(rp) if rp.size else rp.ctypes.data,
+                                      _hp(ci), _hp(v), index_base, PREC[prec], flags,
+                                      ctypes.byref(out)))
+    return Handle(out.value, prec, SPMV_KIND_SYMMETRIC)
 
 
 def spmv_split_local_nonlocal(h: Handle, halo_begin_col: int) -> Handle:

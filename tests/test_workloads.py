@@ -92,3 +92,23 @@ def test_random_crs_edge_features():
     assert (rl == 0).any()
     dup = any(len(set(A.col_idx[a:b])) < b - a for a, b in zip(A.row_ptr[:-1], A.row_ptr[1:]))
     assert dup
+
+
+def test_upper_triangle_expands_to_the_symmetric_matrix():
+    """U + U^T - diag(U) rebuilt densely equals the symmetric input."""
+    A = gen.irregular_symmetric(300, 40, gen.rng_for(55, 0))
+    U = gen.upper_triangle(A)
+    full = np.zeros((A.n_rows, A.n_cols))
+    for i in range(A.n_rows):
+        for j in range(A.row_ptr[i], A.row_ptr[i + 1]):
+            full[i, A.col_idx[j]] += A.val[j]
+    assert np.array_equal(full, full.T)
+    rebuilt = np.zeros_like(full)
+    for i in range(U.n_rows):
+        for j in range(U.row_ptr[i], U.row_ptr[i + 1]):
+            c = U.col_idx[j]
+            assert c >= i
+            rebuilt[i, c] += U.val[j]
+            if c != i:
+                rebuilt[c, i] += U.val[j]
+    assert np.array_equal(rebuilt, full)

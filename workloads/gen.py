@@ -255,6 +255,15 @@ def irregular_symmetric(N: int, W: int, rng: np.random.Generator,
     return CRS(N, N, row_ptr.astype(np.int32), col_idx, val)
 
 
+def upper_triangle(A: CRS) -> CRS:
+    """The entries of A with column >= row, in A's order (input of the
+    symmetric-storage handle)."""
+    rows = np.repeat(np.arange(A.n_rows, dtype=np.int64), np.diff(A.row_ptr))
+    keep = A.col_idx.astype(np.int64) >= rows
+    counts = np.bincount(rows[keep], minlength=A.n_rows)
+    return _finish(A.n_rows, A.n_cols, counts, A.col_idx[keep], A.val[keep])
+
+
 # --------------------------------------------------------------------------
 # Tiny random CRS (brute-force pins and edge cases)
 # --------------------------------------------------------------------------
