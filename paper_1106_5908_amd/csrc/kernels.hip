@@ -451,10 +451,12 @@ __device__ __forceinline__ void staged_tile(const int32_t *__restrict__ rp,
             o3 = nr > 3 ? s3 + d3 : INT_MAX;
   const int tid = (int)threadIdx.x;
   // LDS slot i holds B[i - d_r], r the last run whose slots start at or
-  // below i; slots past L load slot L - 1 again and are not stored.
+  // below i.  Passes wholly past L are skipped (a uniform branch); within the
+  // last pass, slots past L load slot L - 1 again and are not stored.
   X bst[NB];
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
+    if (i * WG >= L) break;
     const int slot = min(i * WG + tid, L - 1);
     int d = d0;
     if (slot >= o1) d = d1;
