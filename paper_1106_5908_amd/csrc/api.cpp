@@ -1,9 +1,11 @@
 // libspmv runtime: the C interface of include/spmv.h.
 //
 // Host side of the CRS product of Schubert, Fehske, Hager, Wellein (2011):
-// validation and encoding of the CRS arrays (Sect. 1.2), tiling and kernel
-// plans, the split handle and its overlap schedule (Sect. 3.4 / 3.5), batch
-// handles with their persistent launch captured in a HIP graph, and the
+// validation and encoding of the CRS arrays (Sect. 1.2), tiling, run tables
+// of the staged kernel and kernel plans, the split handle and its overlap
+// schedule (Sect. 3.4 / 3.5) with the send side of the exchange, batch
+// handles with their launch captured in a HIP graph, symmetric-storage
+// handles (Sect. 1.3.1), the Chebyshev-moment and Lanczos loops, and the
 // autotuner with its persistent cache.  No exception crosses the C boundary.
 #include <hip/hip_runtime_api.h>
 #include <sys/stat.h>

@@ -9,13 +9,19 @@
 //     col_idx with fully coalesced loads (E per lane, all issued before the
 //     gathers of B), writes the products to LDS and reduces each row there
 //     with L lanes per row (L chosen per tile from its row count).
+//   * staged stream kernel: the stream kernel's tiles, with the few column
+//     ranges a tile of a stencil-like matrix reads loaded into LDS first, so
+//     the entries read B from LDS instead of gathering it.
 //   * vector kernel: L lanes of a wavefront share a row, stride through it
 //     and combine their partial sums with cross-lane shuffles.
+//   * symmetric kernel: the upper triangle of a symmetric matrix, the
+//     transposed half scattered into C with atomic adds (Sect. 1.3.1).
 //   * block kernel: k right-hand sides; a tile's col_idx / val are staged in
 //     LDS once and each row is handled by KT/VW lanes holding VW columns.
 //   * batch kernels: many matrices; the tiles of all members are cut into
 //     eight per-XCD work queues that a persistent grid drains through atomic
-//     counters (with stealing once a workgroup's own queue is empty).
+//     counters (with stealing once a workgroup's own queue is empty), or
+//     one workgroup per tile (plain or staged).
 // val and col_idx are read with the nontemporal hint so the single-use
 // matrix stream does not evict B from L2 / MALL.  Tile numbers can be
 // remapped so that each of the eight XCDs (each with a private L2) gets a
