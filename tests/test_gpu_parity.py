@@ -751,7 +751,7 @@ def test_tuner_and_cache(tmp_path, monkeypatch):
     a, s = _split_handles(A, gen.halo_begin(A.n_cols), flags=0)
     try:
         spmv.spmv_tune(s, 1)
-        assert spmv.spmv_get_plan(s, spmv.SPMV_PART_NONLOCAL)["kernel"] in (1, 2)
+        assert spmv.spmv_get_plan(s, spmv.SPMV_PART_NONLOCAL)["kernel"] in (1, 2, 4)
     finally:
         spmv.spmv_destroy(s)
         spmv.spmv_destroy(a)

@@ -336,3 +336,33 @@ def test_batch_members(e):
         ref, den = oracle_ref(A, x, c0[sl])
         assert_close(got[sl], ref, den, FP64_TOL, f"member at {off}")
         off += A.n_rows
+
+
+def test_cached_staged_plan(tmp_path, monkeypatch):
+    """A staged plan read from the tuning cache is prepared at creation (run
+    table built), so the first spmv_run already stages and gives the
+    oracle's result."""
+    import json
+
+    monkeypatch.setenv("SPMV_TUNE_CACHE", str(tmp_path / "tune.json"))
+    A = mats()["27pt-30"]
+    h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols)
+    try:
+        spmv.spmv_tune(h, 1)
+    finally:
+        spmv.spmv_destroy(h)
+    cache = json.loads((tmp_path / "tune.json").read_text())
+    keys = [k for k in cache if "|k1|main|" in k]
+    assert len(keys) == 1
+    cache[keys[0]] = dict(kernel=spmv.SPMV_KERNEL_STAGED, tile_items=16, lanes=32, nontemporal=1,
+                          xcd_remap=1, block_kt=0, tiles_per_group=1, panels=1)
+    (tmp_path / "tune.json").write_text(json.dumps(cache))
+    h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols)
+    try:
+        assert spmv.spmv_get_plan(h)["kernel"] == spmv.SPMV_KERNEL_STAGED
+        assert spmv.spmv_get_info(h)["n_staged_tiles"] > 0
+    finally:
+        spmv.spmv_destroy(h)
+    x = gen.uniform_vector(A.n_cols, gen.rng_for(48, 0))
+    ref, den = oracle_ref(A, x)
+    assert_close(gpu_spmv(A, x, flags=0), ref, den, FP64_TOL, "cached staged plan")
