@@ -165,6 +165,35 @@ def test_determinism():
     a = gpu_spmv(A, x, runs=3)
     b = gpu_spmv(A, x, runs=3)
     assert np.array_equal(a, b)
+    A27, x27 = mats()["27pt"]
+    st = dict(kernel=spmv.SPMV_KERNEL_STAGED, tile_items=16)
+    assert np.array_equal(gpu_spmv(A27, x27, plan=st, runs=2), gpu_spmv(A27, x27, plan=st, runs=2))
+
+
+@pytest.mark.parametrize("kernel", [spmv.SPMV_KERNEL_STREAM, spmv.SPMV_KERNEL_TILE_GRID,
+                                    spmv.SPMV_KERNEL_STAGED])
+def test_batch_bit_deterministic(kernel):
+    """Random data: two handles, each run twice, give the same bits, whichever
+    workgroup the persistent queue hands a tile to."""
+    import torch
+
+    mem = _batch(count=40, seed_extra=6)
+    xs = np.concatenate([x for _, x in mem])
+    outs = []
+    for _ in range(2):
+        h = spmv.spmv_create_batch([(A.row_ptr, A.col_idx, A.val, A.n_cols) for A, _ in mem],
+                                   flags=NOTUNE)
+        try:
+            spmv.spmv_set_plan(h, kernel=kernel, tile_items=8)
+            B = to_dev(xs, "f64")
+            C = torch.zeros(sum(A.n_rows for A, _ in mem), dtype=torch.float64, device="cuda")
+            spmv.spmv_run(h, B, C)
+            spmv.spmv_run(h, B, C)
+            torch.cuda.synchronize()
+            outs.append(C.cpu().numpy())
+        finally:
+            spmv.spmv_destroy(h)
+    assert np.array_equal(outs[0].view(np.uint64), outs[1].view(np.uint64))
 
 
 def test_handles_on_threads_and_streams():
