@@ -366,3 +366,27 @@ def test_cached_staged_plan(tmp_path, monkeypatch):
     x = gen.uniform_vector(A.n_cols, gen.rng_for(48, 0))
     ref, den = oracle_ref(A, x)
     assert_close(gpu_spmv(A, x, flags=0), ref, den, FP64_TOL, "cached staged plan")
+
+
+@pytest.mark.parametrize("plan", [staged(16), staged(8), dict(kernel=spmv.SPMV_KERNEL_STREAM,
+                                                              tile_items=16)], ids=_pid)
+def test_tiles_without_entries(plan):
+    """More than 512 empty rows in a row make tiles that hold no entry at all
+    (a tile never spans more than 512 rows): they leave C untouched, signed
+    zeros included, and the stencil rows around them match the oracle."""
+    S = gen.laplace_5pt_2d(60)
+    n_gap = 3000
+    counts = np.concatenate([np.diff(S.row_ptr), np.zeros(n_gap, np.int64), np.diff(S.row_ptr)])
+    cols = np.concatenate([S.col_idx, S.col_idx])
+    vals = np.concatenate([S.val, -S.val])
+    A = gen._finish(counts.size, S.n_cols, counts, cols, vals)
+    x = gen.uniform_vector(A.n_cols, gen.rng_for(49, 0))
+    c0 = gen.uniform_vector(A.n_rows, gen.rng_for(49, 1))
+    c0[S.n_rows:S.n_rows + n_gap:2] = -0.0
+    c0[S.n_rows + 1:S.n_rows + n_gap:2] = 0.0
+    got = gpu_spmv(A, x, c0, plan=plan)
+    gap = slice(S.n_rows, S.n_rows + n_gap)
+    assert np.array_equal(got[gap], c0[gap]) and np.array_equal(np.signbit(got[gap]),
+                                                               np.signbit(c0[gap]))
+    ref, den = oracle_ref(A, x, c0)
+    assert_close(got, ref, den, FP64_TOL, f"empty tiles {plan}")
