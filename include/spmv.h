@@ -75,7 +75,7 @@ typedef enum spmv_precision {
     SPMV_PREC_F32_F64ACC = 3
 } spmv_precision_t;
 
-/* flags for spmv_create_crs / spmv_create_batch */
+/* flags for spmv_create_crs / spmv_create_sym_crs / spmv_create_batch */
 #define SPMV_FLAG_ALLOW_PAGEABLE_HALO 0x1u /* accept a pageable B_halo_host (copy then loses overlap) */
 #define SPMV_FLAG_NO_TUNE_CACHE 0x2u       /* ignore the persistent autotuner cache */
 
