@@ -59,6 +59,9 @@ MUTANTS = {
     "block_column_major": [("oracle_spmv_block", "B[((int64_t)col_idx[j] - base) * ldb + t]",
                             "B[((int64_t)col_idx[j] - base) + t * ldb]")],
     "abs_missing_fabs": [("oracle_abs_spmv", "fabs(val[j]) * ", "val[j] * ")],
+    "abs_c0_ignored": [("oracle_abs_spmv", "double d = fabs(C0[i]);", "double d = 0.0;")],
+    "block_c0_ignored": [("oracle_spmv_block", "double c = C[i * ldc + t];", "double c = 0.0;")],
+    "split_nonlocal_sign": [("oracle_spmv_split", "c = c + prod;", "c = c - prod;")],
     "split_boundary": [("oracle_split_count", "- base < h)", "- base <= h)"),
                        ("oracle_split_fill", "if (c < h)", "if (c <= h)")],
     "split_row_id": [("oracle_split_fill", "nl_rows[r] = (int32_t)i;", "nl_rows[r] = (int32_t)(i + 1);")],
