@@ -112,10 +112,14 @@ __device__ __forceinline__ void load_cv(const int32_t *__restrict__ col,
 // base = p0 - off is the entry at or below the tile start whose index in the
 // allocation is a multiple of G, so each group is one aligned vector load of
 // indices (8 or 16 bytes) and one of values (16 or 8 bytes).  Groups past the
-// tile are clamped to its last group.  The first entry of a group is always a
-// stored entry; later ones may lie past the tile -- for the part's last tile,
-// in the arrays' tail padding -- so their columns are replaced by the group's
-// first column and never used as gather indices.  Needs nnz + off <= 256 * E.
+// tile are clamped to its last group.  A group's slots may lie outside the
+// tile: the first group starts `off` entries early, inside the previous tile
+// (or, in a batch, inside the previous member, whose columns index another
+// vector), and the last one may run past it -- for the part's last tile, into
+// the arrays' tail padding.  Such slots take the column of the group's first
+// in-tile entry (slot `off` of group 0, slot 0 of every later group), so
+// every gather index is one of the tile's own columns; their products land
+// in LDS slots phase 2 never reads.  Needs nnz + off <= 256 * E.
 template <class V> constexpr int group_of() { return sizeof(V) == 8 ? 2 : 4; }
 template <class V, int G> struct VecOf;
 template <> struct VecOf<double, 2> { typedef double T __attribute__((ext_vector_type(2))); };
@@ -138,9 +142,13 @@ __device__ __forceinline__ void load_cv_groups(const int32_t *__restrict__ col,
     const int g = min(e * WG + (int)threadIdx.x, lastg);
     const IV ci = ld<IV, NT>(reinterpret_cast<const IV *>(col + base + G * g));
     const VV vi = ld<VV, NT>(reinterpret_cast<const VV *>(val + base + G * g));
+    int first = ci[0];
+#pragma unroll
+    for (int j = 1; j < G; ++j) first = (g == 0 && off == j) ? ci[j] : first;
 #pragma unroll
     for (int j = 0; j < G; ++j) {
-      c[G * e + j] = (j == 0 || G * g + j < nnz + off) ? ci[j] : ci[0];
+      const int slot = G * g + j;
+      c[G * e + j] = (slot >= off && slot < nnz + off) ? ci[j] : first;
       v[G * e + j] = vi[j];
     }
   }
