@@ -14,7 +14,9 @@ ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 OUT = os.path.join(PKG, "libspmv.so")
 BUILD = os.path.join(PKG, "_build")
-SOURCES = ["kernels.hip", "split.hip", "probes.hip", "exchange.hip", "kpm.hip", "lanczos.hip", "api.cpp"]
+SOURCES = ["kernels.hip", "split.hip", "probes.hip", "exchange.hip", "kpm.hip", "lanczos.hip",
+           "rt_core.cpp", "rt_plan.cpp", "rt_split.cpp", "rt_batch.cpp", "rt_run.cpp",
+           "rt_exchange.cpp", "rt_solvers.hip"]
 ARCH = os.environ.get("SPMV_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -41,7 +43,7 @@ def _compile(src: str) -> str:
 
 def build(verbose: bool = True) -> str:
     os.makedirs(BUILD, exist_ok=True)
-    with cf.ThreadPoolExecutor(max_workers=len(SOURCES)) as ex:
+    with cf.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
         objs = list(ex.map(_compile, SOURCES))
     tmp = OUT + ".tmp%d" % os.getpid()
     cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]

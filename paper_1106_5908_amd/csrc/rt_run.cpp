@@ -1,0 +1,164 @@
+// libspmv runtime, run unit: C = C + A*B (Listing 1) for plain, split
+// (Sect. 3.4 / 3.5), symmetric-storage and batch handles, and the block of
+// right-hand sides.
+#include <hip/hip_runtime_api.h>
+
+#include <string>
+
+#include "runtime.h"
+
+using namespace spmv;
+
+namespace spmv {
+namespace rt {
+
+void run_sym(spmv_handle_s *h, const void *B, void *C, hipStream_t s) {
+  const Part &p = h->main;
+  if (p.n_rows == 0 || p.nnz == 0) return;
+  hip_ok(launch_spmv_sym(p.dev(), p.plan.lanes, p.plan.nontemporal, p.plan.xcd_remap,
+                         static_cast<const double *>(B), static_cast<double *>(C), s),
+         "symmetric kernel launch");
+}
+
+int default_kt(int k) {
+  if (k <= 4) return 4;
+  if (k <= 8) return 8;
+  return 16;
+}
+
+// The panels are shared with the single-vector plan.
+void run_block_part(spmv_handle_s *h, Part &p, int kt, int nt, int remap, int panels, int k,
+                    const void *B, int64_t ldb, void *C, int64_t ldc, hipStream_t s,
+                    double scale) {
+  if (p.n_rows == 0 || p.nnz == 0) return;
+  if (panels > 1) {
+    for (auto &q : build_panels(h, p, panels))
+      run_block_part(h, *q, kt, nt, remap, 1, k, B, ldb, C, ldc, s, scale);
+    return;
+  }
+  auto t = p.tiles_for(4);
+  hip_ok(launch_spmv_block(h->prec, p.dev(), t.first, t.second, 4, nt, remap, kt, k, B, ldb, C,
+                           ldc, scale, s),
+         "block kernel launch");
+}
+
+spmv_plan_t block_plan(spmv_handle_s *h, int k) {
+  Part &p = h->main;
+  auto it = h->block_plans.find(k);
+  if (it != h->block_plans.end()) return it->second;
+  spmv_plan_t c = p.plan;
+  if (p.plan.block_kt != 0) return c;  // set through spmv_set_plan
+  c.block_kt = default_kt(k);
+  // the cache file is read once per k and handle, not on every product
+  if (!(h->flags & SPMV_FLAG_NO_TUNE_CACHE) && !h->block_cache_read[k]) {
+    h->block_cache_read[k] = true;
+    spmv_plan_t cached;
+    if (cache_lookup(tune_key(h->device, h->prec, k, "block", p.n_rows, p.stats), &cached) &&
+        cached.block_kt) {
+      h->block_plans[k] = cached;
+      return cached;
+    }
+  }
+  return c;
+}
+
+void block_product(spmv_handle_s *h, int k, const void *B, int64_t ldb, void *C, int64_t ldc,
+                   hipStream_t s, double scale) {
+  const spmv_plan_t c = block_plan(h, k);
+  run_block_part(h, h->main, c.block_kt, c.nontemporal, c.xcd_remap, c.panels, k, B, ldb, C, ldc,
+                 s, scale);
+}
+
+}  // namespace rt
+}  // namespace spmv
+
+using namespace spmv::rt;
+
+// ==== a3-a7, a9: C = C + A*B ========================================================================
+
+extern "C" spmv_status_t spmv_run(spmv_handle_t h_, const void *B, void *C,
+                                  const void *B_halo_host, void *stream) {
+  return guarded([&] {
+    spmv_handle_s *h = live(h_);
+    if ((!B && h->n_cols > 0) || (!C && h->n_rows > 0)) fail(SPMV_ERR_INVALID_ARG, "B or C is null");
+    if (B && C && B == C) fail(SPMV_ERR_INVALID_ARG, "C must not alias B");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    DeviceGuard dg(h->device);
+    if (h->kind != SPMV_KIND_SPLIT) {
+      if (B_halo_host) fail(SPMV_ERR_INVALID_ARG, "B_halo_host is only accepted by split handles");
+      if (h->kind == SPMV_KIND_PLAIN)
+        run_part(h, h->main, B, C, s);
+      else if (h->kind == SPMV_KIND_SYMMETRIC)
+        run_sym(h, B, C, s);
+      else
+        batch_run(h, B, C, s);
+      return;
+    }
+    // split handle: local part, halo arrival, nonlocal part (Sect. 3.4 / 3.5)
+    const int64_t n_halo = h->n_cols - h->halo_begin;
+    const size_t vb = size_t(vec_bytes(h->prec));
+    void *recv = static_cast<char *>(const_cast<void *>(B)) + size_t(h->halo_begin) * vb;
+    const bool copy = B_halo_host && n_halo > 0;
+    if (copy) require_pinned(h, B_halo_host, "B_halo_host");
+    begin_timed_call(h, s);
+    if (copy && h->schedule == SPMV_SCHEDULE_OVERLAP) {
+      hip_ok(hipEventRecord(h->ev_start, s), "event record");
+      hip_ok(hipStreamWaitEvent(h->copy_stream, h->ev_start, 0), "stream wait");
+      mark(h, T_COPY, h->copy_stream);
+      hip_ok(hipMemcpyAsync(recv, B_halo_host, size_t(n_halo) * vb, hipMemcpyHostToDevice,
+                            h->copy_stream),
+             "halo copy");
+      mark(h, T_COPY + 1, h->copy_stream);
+      hip_ok(hipEventRecord(h->ev_copied, h->copy_stream), "event record");
+      mark(h, T_LOCAL, s);
+      run_part(h, h->main, B, C, s);
+      mark(h, T_LOCAL + 1, s);
+      hip_ok(hipStreamWaitEvent(s, h->ev_copied, 0), "stream wait");
+      mark(h, T_NONLOCAL, s);
+      run_part(h, h->nl, B, C, s);
+      mark(h, T_NONLOCAL + 1, s);
+    } else {
+      if (copy) {
+        mark(h, T_COPY, s);
+        hip_ok(hipMemcpyAsync(recv, B_halo_host, size_t(n_halo) * vb, hipMemcpyHostToDevice, s),
+               "halo copy");
+        mark(h, T_COPY + 1, s);
+      }
+      mark(h, T_LOCAL, s);
+      run_part(h, h->main, B, C, s);
+      mark(h, T_LOCAL + 1, s);
+      mark(h, T_NONLOCAL, s);
+      run_part(h, h->nl, B, C, s);
+      mark(h, T_NONLOCAL + 1, s);
+    }
+    h->tran[0] = copy;
+    h->tran[1] = h->tran[2] = true;
+    h->tran[3] = false;
+  });
+}
+
+extern "C" spmv_status_t spmv_run_block(spmv_handle_t h_, int32_t k, const void *B, int64_t ldb,
+                                        void *C, int64_t ldc, void *stream) {
+  return guarded([&] {
+    spmv_handle_s *h = live(h_);
+    if (h->kind != SPMV_KIND_PLAIN)
+      fail(SPMV_ERR_UNSUPPORTED, "spmv_run_block serves plain handles only");
+    if (k < 1 || k > 64) fail(SPMV_ERR_INVALID_ARG, "k must be in [1, 64]");
+    if (ldb < k || ldc < k) fail(SPMV_ERR_INVALID_ARG, "ldb and ldc must be >= k");
+    if ((!B && h->n_cols > 0) || (!C && h->n_rows > 0)) fail(SPMV_ERR_INVALID_ARG, "B or C is null");
+    if (B && C && B == C) fail(SPMV_ERR_INVALID_ARG, "C must not alias B");
+    DeviceGuard dg(h->device);
+    block_product(h, k, B, ldb, C, ldc, static_cast<hipStream_t>(stream));
+  });
+}
+
+extern "C" spmv_status_t spmv_get_block_plan(spmv_handle_t h_, int32_t k, spmv_plan_t *plan) {
+  return guarded([&] {
+    spmv_handle_s *h = live(h_);
+    if (h->kind != SPMV_KIND_PLAIN)
+      fail(SPMV_ERR_UNSUPPORTED, "block products serve plain handles only");
+    if (k < 1 || k > 64) fail(SPMV_ERR_INVALID_ARG, "k must be in [1, 64]");
+    if (!plan) fail(SPMV_ERR_INVALID_ARG, "plan is null");
+    *plan = block_plan(h, k);
+  });
+}

@@ -1,5 +1,5 @@
-// Internal declarations shared by the runtime (api.cpp) and the gfx950
-// kernels (*.hip).  Not part of the public interface.
+// Internal declarations shared by the host runtime (rt_*.cpp, rt_solvers.hip)
+// and the gfx950 kernels (*.hip).  Not part of the public interface.
 #pragma once
 
 #include <hip/hip_runtime_api.h>

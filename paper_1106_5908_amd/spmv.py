@@ -80,6 +80,7 @@ EXPORTED = [
     "spmv_probe_triad", "spmv_probe_read", "spmv_probe_spin", "spmv_set_schedule",
     "spmv_set_send_list", "spmv_send_list_symmetric", "spmv_run_exchange", "spmv_probe_atomic",
     "spmv_kpm_moments", "spmv_set_phase_timing", "spmv_phase_times", "spmv_lanczos",
+    "spmv_get_block_plan",
 ]
 
 
@@ -159,6 +160,7 @@ def load():
         "spmv_set_phase_timing": [_vp, _i32],
         "spmv_phase_times": [_vp, _vp],
         "spmv_lanczos": [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
+        "spmv_get_block_plan": [_vp, _i32, _vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
@@ -462,6 +464,13 @@ def spmv_destroy(h: Handle) -> None:
 def spmv_get_plan(h: Handle, part: int = SPMV_PART_MAIN) -> dict:
     p = spmv_plan_t()
     _check(load().spmv_get_plan(_ptr(h), part, ctypes.byref(p)))
+    return {n: getattr(p, n) for n, _ in spmv_plan_t._fields_}
+
+
+def spmv_get_block_plan(h: Handle, k: int) -> dict:
+    """The plan spmv_run_block uses for blocks of k columns on this handle."""
+    p = spmv_plan_t()
+    _check(load().spmv_get_block_plan(_ptr(h), k, ctypes.byref(p)))
     return {n: getattr(p, n) for n, _ in spmv_plan_t._fields_}
 
 

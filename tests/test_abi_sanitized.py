@@ -1,6 +1,7 @@
-"""The host runtime (api.cpp) built with AddressSanitizer and
-UndefinedBehaviorSanitizer, host code only, linked with the regular device
-objects: every host-side interface test must pass with no sanitizer report.
+"""The host runtime (the rt_*.cpp units) built with AddressSanitizer and
+UndefinedBehaviorSanitizer, host code only, linked with the regular objects
+of the HIP sources: every host-side interface test must pass with no
+sanitizer report.
 Runs without a GPU (only the paths that fail before touching the device)."""
 import os
 import shutil
@@ -17,6 +18,12 @@ def _device_objects():
     return [os.path.splitext(src)[0] + ".o" for src in b.SOURCES if src.endswith(".hip")]
 
 
+def _host_sources():
+    from paper_1106_5908_amd import build as b
+
+    return [src for src in b.SOURCES if src.endswith(".cpp")]
+
+
 def _lib(name):
     r = subprocess.run(["gcc", f"-print-file-name={name}"], capture_output=True, text=True)
     p = r.stdout.strip()
@@ -29,13 +36,16 @@ def test_host_runtime_under_sanitizers(tmp_path):
     objs = [os.path.join(BUILD, o) for o in _device_objects()]
     if not all(os.path.exists(o) for o in objs):
         pytest.skip("device objects not built (run the package build first)")
-    api_o = str(tmp_path / "api_san.o")
     so = str(tmp_path / "libspmv_san.so")
     san = ["-fsanitize=address,undefined", "-fno-omit-frame-pointer"]
-    subprocess.check_call(["g++", "-std=c++17", "-O1", "-g", "-fPIC", "-D__HIP_PLATFORM_AMD__",
-                           "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"), *san, "-c",
-                           os.path.join(ROOT, "paper_1106_5908_amd", "csrc", "api.cpp"), "-o", api_o])
-    subprocess.check_call(["g++", "-shared", *san, "-o", so, api_o, *objs, "-L/opt/rocm/lib",
+    host_objs = []
+    for src in _host_sources():
+        o = str(tmp_path / (os.path.splitext(src)[0] + "_san.o"))
+        subprocess.check_call(["g++", "-std=c++17", "-O1", "-g", "-fPIC", "-D__HIP_PLATFORM_AMD__",
+                               "-I/opt/rocm/include", "-I" + os.path.join(ROOT, "include"), *san,
+                               "-c", os.path.join(ROOT, "paper_1106_5908_amd", "csrc", src), "-o", o])
+        host_objs.append(o)
+    subprocess.check_call(["g++", "-shared", *san, "-o", so, *host_objs, *objs, "-L/opt/rocm/lib",
                            "-lamdhip64", "-Wl,-rpath,/opt/rocm/lib"])
     env = dict(os.environ)
     pre = [_lib("libasan.so"), _lib("libubsan.so")]
