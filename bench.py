@@ -319,7 +319,7 @@ def kpm_path(A, R: int = 8, M: int = 64, reps: int = 5):
            "moments_per_s": M * R / (t["p50_ms"] * 1e-3), "gflops_products": flops / (t["p50_ms"] * 1e6),
            "block_product_ms": tb["p50_ms"], "frac_time_in_products": products * tb["p50_ms"] / t["p50_ms"],
            "moments_bounded_by_norm": bounded, "scale": 1.01 * g,
-           "plan_block": spmv.spmv_get_plan(h)}
+           "plan_block": spmv.spmv_get_block_plan(h, R)}
     spmv.spmv_destroy(h)
     del V0, W1, W2, mu
     torch.cuda.empty_cache()
@@ -600,7 +600,8 @@ def block_paths(A, steps, warmup, fp64_ms):
                  "gflops": flops / (tm["ms_per_step"] * 1e6),
                  "model_GBs": mb / (tm["ms_per_step"] * 1e6), "model_bytes": mb, **tm,
                  "max_normalized_err_sampled": max(errs), "err_bound": bound(prec, n),
-                 "speedup_vs_k_fp64_calls": k * fp64_ms / tm["ms_per_step"]}
+                 "speedup_vs_k_fp64_calls": k * fp64_ms / tm["ms_per_step"],
+                 "plan": spmv.spmv_get_block_plan(h, k)}
             log(f"block k={k} {prec}: {r['gflops']:.0f} GFlop/s, x{r['speedup_vs_k_fp64_calls']:.2f} "
                 f"vs k FP64 calls, err {max(errs):.1e}")
             out.append(r)

@@ -472,6 +472,21 @@ spmv_status_t spmv_export(spmv_handle_t h, int32_t which, void *dst, int64_t byt
  *                     last one is skipped) and writes one partial sum per
  *                     workgroup to sums[0 .. (n/2 + 1023)/1024]; sums_len is
  *                     the capacity of sums in doubles
+ *   spmv_probe_gather the indexed loads of the product alone: for k < n, the
+ *                     `width` doubles of row idx[k] of src (viewed as n_rows
+ *                     rows of width doubles, row-major; width 1 is one
+ *                     right-hand side, width k a block of k) are loaded and
+ *                     summed, the indices read with coalesced loads first;
+ *                     indices outside [0, n_rows) are clamped into it.
+ *                     xcd_remap places the index stream on the XCDs as the
+ *                     stream kernel places its tiles.  One partial sum per
+ *                     workgroup goes to sums[0 .. spmv_probe_gather_sums_needed
+ *                     (n, width)); sums_len is its capacity.  With a matrix's
+ *                     col_idx as idx it measures what the product's gathers
+ *                     of B cost on their own (the source of kappa, Eq. (1));
+ *                     with random indices in a window, the gather rate of the
+ *                     cache level the window fits.  width > 1 needs src
+ *                     16-byte aligned.
  *   spmv_probe_spin   one wavefront waits `nanoseconds` on the GPU's constant-rate
  *                     clock without touching memory (at most 10 s)
  *   spmv_probe_atomic 524288 threads each add 1.0 `iters` times (1 <= iters <=
@@ -485,6 +500,11 @@ spmv_status_t spmv_probe_triad(double *a, const double *b, const double *c, doub
                                int64_t n, void *stream);
 spmv_status_t spmv_probe_read(const double *src, int64_t n, double *sums, int64_t sums_len,
                               void *stream);
+spmv_status_t spmv_probe_gather(const double *src, int64_t n_rows, int32_t width,
+                                const int32_t *idx, int64_t n, int32_t xcd_remap, double *sums,
+                                int64_t sums_len, void *stream);
+/* Capacity spmv_probe_gather needs in sums (-1 for a bad n or width). */
+int64_t spmv_probe_gather_sums_needed(int64_t n, int32_t width);
 spmv_status_t spmv_probe_spin(int64_t nanoseconds, void *stream);
 spmv_status_t spmv_probe_atomic(double *C, int64_t n, int32_t scattered, int32_t iters,
                                 void *stream);

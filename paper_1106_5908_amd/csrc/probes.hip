@@ -5,6 +5,13 @@
 //   atomic: throughput of FP64 atomic adds into HBM, coalesced or scattered
 //     (what a scatter into C, such as the transposed half of a symmetric
 //     product, would pay per contribution);
+//   gather: the indexed loads of B alone -- a stream of int32 indices read
+//     with coalesced loads and, for each index, W consecutive doubles gathered
+//     from B (W = 1 for one right-hand side, W = k for a row-major block) --
+//     the part of the spMV whose extra traffic the paper calls kappa
+//     (Sect. 1.2, Eq. (1)); fed with a matrix's own col_idx it gives the rate
+//     the product's gathers alone reach, with random indices in a window of
+//     chosen size the rate of the cache level that window fits;
 //   spin: a workgroup that stays busy for a given time without touching
 //     memory, the device-side "do_work" of the asynchrony test of Listing 2
 //     (Sect. 3.1), used to check that a host-to-device copy on another stream
@@ -113,6 +120,60 @@ __global__ __launch_bounds__(WG) void k_atomic(double *__restrict__ C, uint32_t 
   }
 }
 
+// Gathers: lane group g of L = max(1, W/2) lanes takes indices
+// base + e*NI + g (e < GE, NI = 256 / L indices per pass), loads all GE indices
+// first (coalesced, streaming hint), then gathers row idx of src (W doubles,
+// 16 bytes per lane, or 8 bytes for W = 1).  Indices are clamped into
+// [0, n_rows) so no load leaves src.  Workgroups are placed on the XCDs as
+// the stream kernel places its tiles (contiguous ranges per XCD when remap
+// is set).  Each workgroup writes the sum of what it gathered.
+constexpr int GE = 8;
+
+__device__ __forceinline__ int64_t probe_tile(int64_t bid, int64_t n, int remap) {
+  if (!remap) return bid;
+  const int64_t x = bid % 8, i = bid / 8;
+  const int64_t q = n / 8, r = n % 8;
+  return x * q + (x < r ? x : r) + i;
+}
+
+template <int W>
+__global__ __launch_bounds__(WG) void k_gather(const double *__restrict__ src, int64_t n_rows,
+                                               const int32_t *__restrict__ idx, int64_t n,
+                                               int remap, double *__restrict__ sums) {
+  constexpr int L = W >= 2 ? W / 2 : 1;
+  constexpr int NI = WG / L;
+  __shared__ double s_red[WG];
+  const int64_t b = probe_tile(blockIdx.x, gridDim.x, remap);
+  const int64_t base = b * NI * GE;
+  const int g = (int)threadIdx.x / L, lane = (int)threadIdx.x % L;
+  int64_t c[GE];
+#pragma unroll
+  for (int e = 0; e < GE; ++e) {
+    const int64_t j = base + (int64_t)e * NI + g;
+    const int64_t v = j < n ? (int64_t)__builtin_nontemporal_load(idx + j) : 0;
+    c[e] = v < 0 ? 0 : (v >= n_rows ? n_rows - 1 : v);
+  }
+  double acc = 0.0;
+#pragma unroll
+  for (int e = 0; e < GE; ++e) {
+    const bool in = base + (int64_t)e * NI + g < n;
+    if constexpr (W == 1) {
+      const double v = src[c[e]];
+      acc += in ? v : 0.0;
+    } else {
+      const dv2 v = *reinterpret_cast<const dv2 *>(src + c[e] * W + 2 * lane);
+      acc += in ? v.x + v.y : 0.0;
+    }
+  }
+  s_red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = WG / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) s_red[threadIdx.x] += s_red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) sums[blockIdx.x] = s_red[0];
+}
+
 // Busy-waits until `ticks` ticks of the constant-rate wall clock have passed.
 __global__ void k_spin(int64_t ticks) {
   const int64_t t0 = wall_clock64();
@@ -161,6 +222,33 @@ hipError_t launch_read(const double *src, int64_t n, double *sums, hipStream_t s
 hipError_t launch_atomic(double *C, int64_t n, int scattered, int iters, hipStream_t s) {
   hipLaunchKernelGGL(k_atomic, dim3(ATOMIC_BLOCKS), dim3(WG), 0, s, C, (uint32_t)(n - 1),
                      scattered, iters);
+  return hipGetLastError();
+}
+
+int64_t gather_sums_needed(int64_t n, int width) {
+  const int64_t per = (int64_t)(WG / (width >= 2 ? width / 2 : 1)) * GE;
+  return n > 0 ? (n + per - 1) / per : 0;
+}
+
+template <int W>
+static void gather_w(const double *src, int64_t n_rows, const int32_t *idx, int64_t n, int remap,
+                     double *sums, hipStream_t s) {
+  const int64_t nb = gather_sums_needed(n, W);
+  hipLaunchKernelGGL(k_gather<W>, dim3((unsigned)nb), dim3(WG), 0, s, src, n_rows, idx, n, remap,
+                     sums);
+}
+
+hipError_t launch_gather(const double *src, int64_t n_rows, const int32_t *idx, int64_t n,
+                         int width, int remap, double *sums, hipStream_t s) {
+  if (n <= 0) return hipSuccess;
+  switch (width) {
+    case 1: gather_w<1>(src, n_rows, idx, n, remap, sums, s); break;
+    case 2: gather_w<2>(src, n_rows, idx, n, remap, sums, s); break;
+    case 4: gather_w<4>(src, n_rows, idx, n, remap, sums, s); break;
+    case 8: gather_w<8>(src, n_rows, idx, n, remap, sums, s); break;
+    case 16: gather_w<16>(src, n_rows, idx, n, remap, sums, s); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

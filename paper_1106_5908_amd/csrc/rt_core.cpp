@@ -528,6 +528,31 @@ extern "C" spmv_status_t spmv_probe_read(const double *src, int64_t n, double *s
   });
 }
 
+extern "C" spmv_status_t spmv_probe_gather(const double *src, int64_t n_rows, int32_t width,
+                                           const int32_t *idx, int64_t n, int32_t xcd_remap,
+                                           double *sums, int64_t sums_len, void *stream) {
+  return guarded([&] {
+    if (width != 1 && width != 2 && width != 4 && width != 8 && width != 16)
+      fail(SPMV_ERR_INVALID_ARG, "width must be 1, 2, 4, 8 or 16");
+    if (n < 0 || n_rows < 1 || n_rows > INT32_MAX) fail(SPMV_ERR_INVALID_ARG, "bad gather sizes");
+    if (!src || !sums || (n > 0 && !idx)) fail(SPMV_ERR_INVALID_ARG, "null gather buffer");
+    if (xcd_remap != 0 && xcd_remap != 1) fail(SPMV_ERR_INVALID_ARG, "xcd_remap must be 0 or 1");
+    if (sums_len < gather_sums_needed(n, width))
+      fail(SPMV_ERR_INVALID_ARG,
+           "sums must hold " + std::to_string(gather_sums_needed(n, width)) + " values");
+    if (width > 1 && reinterpret_cast<uintptr_t>(src) % 16)
+      fail(SPMV_ERR_INVALID_ARG, "src must be 16-byte aligned for width > 1");
+    hip_ok(launch_gather(src, n_rows, idx, n, width, xcd_remap, sums,
+                         static_cast<hipStream_t>(stream)),
+           "gather launch");
+  });
+}
+
+extern "C" int64_t spmv_probe_gather_sums_needed(int64_t n, int32_t width) {
+  if (n < 0 || (width != 1 && width != 2 && width != 4 && width != 8 && width != 16)) return -1;
+  return gather_sums_needed(n, width);
+}
+
 extern "C" spmv_status_t spmv_probe_spin(int64_t nanoseconds, void *stream) {
   return guarded([&] {
     if (nanoseconds < 0 || nanoseconds > int64_t(10) * 1000 * 1000 * 1000)

@@ -714,31 +714,38 @@ extern "C" spmv_status_t spmv_tune(spmv_handle_t h_, int32_t k, void *stream) {
     Part &p = h->main;
     float best = 1e30f;
     int best_kt = default_kt(k), best_nt = p.plan.nontemporal, best_pn = 1;
-    for (int pn : {1, 2, 4, 8})
-      for (int kt : {4, 8, 16}) {
-        if (kt > 2 * k && kt != 4) continue;
-        for (int nt : {1, 0}) {
-          const float ms = tm.median_ms(
-              [&] { run_block_part(h, p, kt, nt, p.plan.xcd_remap, pn, k, x.p, k, y.p, k, s); }, s);
-          if (ms < best * 0.99f) {
-            best = ms;
-            best_kt = kt;
-            best_nt = nt;
-            best_pn = pn;
+    int best_rm = p.plan.xcd_remap;
+    // remap 0 spreads every row range over all eight XCDs, so the XCDs
+    // gather from one shared window of B, which the MALL can hold where a
+    // window per XCD would not (wide blocks)
+    for (int rm : {p.plan.xcd_remap, 1 - p.plan.xcd_remap})
+      for (int pn : {1, 2, 4, 8})
+        for (int kt : {4, 8, 16}) {
+          if (kt > 2 * k && kt != 4) continue;
+          for (int nt : {1, 0}) {
+            const float ms = tm.median_ms(
+                [&] { run_block_part(h, p, kt, nt, rm, pn, k, x.p, k, y.p, k, s); }, s);
+            if (ms < best * 0.99f) {
+              best = ms;
+              best_kt = kt;
+              best_nt = nt;
+              best_pn = pn;
+              best_rm = rm;
+            }
           }
         }
-      }
     spmv_plan_t c = p.plan;
     c.block_kt = best_kt;
     c.nontemporal = best_nt;
     c.panels = best_pn;
+    c.xcd_remap = best_rm;
     h->block_plans[k] = c;
     std::vector<int> keep{p.plan.panels};
     for (auto &bp : h->block_plans) keep.push_back(bp.second.panels);
     prune_panels(p, keep);
     if (std::getenv("SPMV_LOG"))
-      std::fprintf(stderr, "libspmv: tuned block k=%d: kt=%d nt=%d panels=%d (%.1f us)\n", k,
-                   best_kt, best_nt, best_pn, best * 1000.0f);
+      std::fprintf(stderr, "libspmv: tuned block k=%d: kt=%d nt=%d panels=%d remap=%d (%.1f us)\n",
+                   k, best_kt, best_nt, best_pn, best_rm, best * 1000.0f);
     if (!(h->flags & SPMV_FLAG_NO_TUNE_CACHE))
       cache_store(tune_key(h->device, h->prec, k, "block", p.n_rows, p.stats), c);
   });

@@ -178,6 +178,12 @@ hipError_t launch_copy(double *dst, const double *src, int64_t n, hipStream_t s)
 hipError_t launch_triad(double *a, const double *b, const double *c, double sc, int64_t n,
                         hipStream_t s);
 hipError_t launch_spin(int64_t nanoseconds, hipStream_t s);
+// Gather probe: for k < n, row clamp(idx[k]) of src viewed as n_rows rows of
+// `width` doubles (1, 2, 4, 8 or 16); one partial sum per workgroup into sums,
+// which must hold gather_sums_needed(n, width) doubles.
+int64_t gather_sums_needed(int64_t n, int width);
+hipError_t launch_gather(const double *src, int64_t n_rows, const int32_t *idx, int64_t n,
+                         int width, int remap, double *sums, hipStream_t s);
 // sums must hold read_sums_needed(n) doubles
 int64_t read_sums_needed(int64_t n);
 hipError_t launch_read(const double *src, int64_t n, double *sums, hipStream_t s);

@@ -80,7 +80,8 @@ EXPORTED = [
     "spmv_probe_triad", "spmv_probe_read", "spmv_probe_spin", "spmv_set_schedule",
     "spmv_set_send_list", "spmv_send_list_symmetric", "spmv_run_exchange", "spmv_probe_atomic",
     "spmv_kpm_moments", "spmv_set_phase_timing", "spmv_phase_times", "spmv_lanczos",
-    "spmv_get_block_plan",
+    "spmv_get_block_plan", "spmv_probe_gather",
+    "spmv_probe_gather_sums_needed",
 ]
 
 
@@ -161,11 +162,14 @@ def load():
         "spmv_phase_times": [_vp, _vp],
         "spmv_lanczos": [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
         "spmv_get_block_plan": [_vp, _i32, _vp],
+        "spmv_probe_gather": [_vp, _i64, _i32, _vp, _i64, _i32, _vp, _i64, _vp],
     }
     for name, args in sig.items():
         fn = getattr(lib, name)
         fn.argtypes = args
         fn.restype = ctypes.c_int
+    lib.spmv_probe_gather_sums_needed.argtypes = [_i64, _i32]
+    lib.spmv_probe_gather_sums_needed.restype = _i64
     lib.spmv_last_error.argtypes = []
     lib.spmv_last_error.restype = ctypes.c_char_p
     _lib = lib
@@ -548,6 +552,34 @@ def spmv_probe_atomic(C, scattered: bool, iters: int, stream=None) -> int:
     _check(load().spmv_probe_atomic(_dev(C, "float64", "C"), C.numel(), int(bool(scattered)),
                                     int(iters), _stream(stream)))
     return ATOMIC_THREADS * int(iters)
+
+
+def gather_sums_needed(n: int, width: int) -> int:
+    v = int(load().spmv_probe_gather_sums_needed(int(n), int(width)))
+    if v < 0:
+        raise ValueError("bad n or width")
+    return v
+
+
+def spmv_probe_gather(src, idx, width: int = 1, xcd_remap: bool = True, sums=None,
+                      stream=None):
+    """Gather probe: `width` doubles of row idx[k] of src (float64, viewed as
+    rows of width doubles) for every index of idx (int32); returns the
+    per-workgroup sums (float64 CUDA tensor)."""
+    import torch
+
+    if src.numel() % width:
+        raise ValueError("src length must be a multiple of width")
+    if idx.dtype != torch.int32 or not idx.is_contiguous():
+        raise ValueError("idx must be a contiguous int32 tensor")
+    need = gather_sums_needed(idx.numel(), width)
+    if sums is None:
+        sums = torch.empty(max(need, 1), dtype=torch.float64, device=src.device)
+    _check(load().spmv_probe_gather(_dev(src, "float64", "src"), src.numel() // width, int(width),
+                                    ctypes.c_void_p(idx.data_ptr()), idx.numel(),
+                                    int(bool(xcd_remap)), _dev(sums, "float64", "sums"),
+                                    sums.numel(), _stream(stream)))
+    return sums
 
 
 def spmv_probe_spin(nanoseconds: int, stream=None) -> None:

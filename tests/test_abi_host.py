@@ -125,6 +125,12 @@ def test_probe_argument_checks():
     assert lib.spmv_probe_spin(-1, None) == spmv.SPMV_ERR_INVALID_ARG
     assert lib.spmv_probe_copy(None, None, 5, None) == spmv.SPMV_ERR_INVALID_ARG
     assert lib.spmv_probe_triad(None, None, None, 1.0, -1, None) == spmv.SPMV_ERR_INVALID_ARG
+    assert lib.spmv_probe_gather(None, 10, 3, None, 0, 1, None, 0, None) == spmv.SPMV_ERR_INVALID_ARG
+    assert lib.spmv_probe_gather(None, 10, 1, None, 5, 1, None, 0, None) == spmv.SPMV_ERR_INVALID_ARG
+    assert lib.spmv_probe_gather_sums_needed(100, 3) == -1
+    assert lib.spmv_probe_gather_sums_needed(0, 1) == 0
+    assert lib.spmv_probe_gather_sums_needed(2049, 1) == 2
+    assert lib.spmv_probe_gather_sums_needed(2049, 16) == 9
 
 
 def test_errors_are_per_thread():

@@ -848,3 +848,27 @@ def test_probes():
         spmv.spmv_probe_atomic(torch.zeros(100, dtype=torch.float64, device="cuda"), False, 1)
     with pytest.raises(spmv.SpmvError):
         spmv.spmv_probe_atomic(torch.zeros(64, dtype=torch.float64, device="cuda"), False, 0)
+
+
+@pytest.mark.parametrize("width", [1, 2, 4, 8, 16])
+@pytest.mark.parametrize("remap", [0, 1])
+def test_gather_probe_sums(width, remap):
+    """The gather probe's per-workgroup sums add up to the sum of the gathered
+    rows (integer values: exact in any order), including a ragged last
+    workgroup, and out-of-range indices are clamped to the first or last row."""
+    import torch
+
+    rng = np.random.default_rng(77 + width)
+    n_rows = 5000
+    src = rng.integers(-50, 51, size=n_rows * width).astype(np.float64)
+    idx = rng.integers(0, n_rows, size=30_011).astype(np.int32)
+    idx[:3] = [-7, n_rows, 2 ** 31 - 1]  # clamped to rows 0, n_rows - 1, n_rows - 1
+    S = torch.from_numpy(src).cuda()
+    I = torch.from_numpy(idx).cuda()
+    sums = spmv.spmv_probe_gather(S, I, width, bool(remap))
+    torch.cuda.synchronize()
+    rows = src.reshape(n_rows, width)
+    want = rows[np.clip(idx.astype(np.int64), 0, n_rows - 1)].sum()
+    assert sums.numel() == spmv.gather_sums_needed(idx.size, width)
+    assert float(sums.sum().item()) == float(want)
+
