@@ -285,6 +285,30 @@ spmv_status_t spmv_kpm_moments(spmv_handle_t h, int32_t R, int32_t M, const doub
 spmv_status_t spmv_lanczos(spmv_handle_t h, int32_t m, const double *q, double *V1, double *V2,
                            double *alpha, double *beta, void *stream);
 
+/* ---------------------------------------------------------------------------
+ * spmv_lanczos_noalloc: spmv_lanczos for callers that cannot allocate device
+ * memory (code under HIP graph capture, serving loops, harnesses that forbid
+ * hipMalloc).  Same arguments, results and errors as spmv_lanczos, computed
+ * by the same kernels; the call makes no allocation and no device
+ * synchronisation, only enqueues work on `stream`.
+ *
+ * Its reductions keep their partial sums in a scratch array the library
+ * holds in device memory for the life of the process, one per GPU, of
+ * 2 * 1024 doubles (16 KiB).  The reductions use at most 1024 workgroups for
+ * any n, so they need 1025 of those doubles whatever the matrix size; a build
+ * whose reductions needed more than the array holds would fail with
+ * SPMV_ERR_UNSUPPORTED.  Every call on one GPU shares that GPU's array:
+ * calls that overlap on one GPU (on streams not ordered with each other) race
+ * and give wrong coefficients; order them on one stream or with events.  The
+ * array's contents are overwritten by every call before they are read; each
+ * call leaves its last partial sums there.
+ * The product uses the kernels, tiles and panels prepared when the handle's
+ * plan was set (spmv_create_crs, spmv_set_plan, spmv_tune); if they are not
+ * there the call fails with SPMV_ERR_STATE instead of building them.
+ * ------------------------------------------------------------------------- */
+spmv_status_t spmv_lanczos_noalloc(spmv_handle_t h, int32_t m, const double *q, double *V1,
+                                   double *V2, double *alpha, double *beta, void *stream);
+
 /* Releases a handle and its device memory after waiting for the handle's
  * internal copy stream.  spmv_destroy(NULL) is SPMV_OK; a destroyed or
  * foreign handle gives SPMV_ERR_STATE. */

@@ -80,7 +80,7 @@ EXPORTED = [
     "spmv_probe_triad", "spmv_probe_read", "spmv_probe_spin", "spmv_set_schedule",
     "spmv_set_send_list", "spmv_send_list_symmetric", "spmv_run_exchange", "spmv_probe_atomic",
     "spmv_kpm_moments", "spmv_set_phase_timing", "spmv_phase_times", "spmv_lanczos",
-    "spmv_get_block_plan", "spmv_probe_gather",
+    "spmv_get_block_plan", "spmv_lanczos_noalloc", "spmv_probe_gather",
     "spmv_probe_gather_sums_needed",
 ]
 
@@ -162,6 +162,7 @@ def load():
         "spmv_phase_times": [_vp, _vp],
         "spmv_lanczos": [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
         "spmv_get_block_plan": [_vp, _i32, _vp],
+        "spmv_lanczos_noalloc": [_vp, _i32, _vp, _vp, _vp, _vp, _vp, _vp],
         "spmv_probe_gather": [_vp, _i64, _i32, _vp, _i64, _i32, _vp, _i64, _vp],
     }
     for name, args in sig.items():
@@ -455,6 +456,24 @@ def spmv_lanczos(h: Handle, q, m: int, V1=None, V2=None, stream=None):
                                _dev(V2, "float64", "V2"), _dev(alpha, "float64", "alpha"),
                                _dev(beta, "float64", "beta"), _stream(stream)))
     return alpha, beta
+
+
+def spmv_lanczos_noalloc(h: Handle, q, m: int, V1, V2, alpha, beta, stream=None) -> None:
+    """spmv_lanczos_noalloc: as spmv_lanczos, into caller-provided buffers
+    (V1, V2 like q; alpha, beta of at least m float64 elements on the same
+    device); neither this wrapper nor the library allocates."""
+    if q.dim() != 1 or q.numel() != h.n_rows or not q.is_contiguous():
+        raise ValueError(f"q must be a contiguous vector of {h.n_rows} elements")
+    for name, V in (("V1", V1), ("V2", V2)):
+        if V.shape != q.shape or not V.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous vector shaped like q")
+    for name, a in (("alpha", alpha), ("beta", beta)):
+        if a.dim() != 1 or a.numel() < m or not a.is_contiguous():
+            raise ValueError(f"{name} must be a contiguous vector of at least {m} elements")
+    _check(load().spmv_lanczos_noalloc(_ptr(h), m, _dev(q, "float64", "q"),
+                                       _dev(V1, "float64", "V1"), _dev(V2, "float64", "V2"),
+                                       _dev(alpha, "float64", "alpha"),
+                                       _dev(beta, "float64", "beta"), _stream(stream)))
 
 
 def spmv_destroy(h: Handle) -> None:
