@@ -43,7 +43,6 @@ if ROOT not in sys.path:
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, published
 PROFILES = os.path.join(ROOT, "profiles")
-TRAFFIC_GLOB = os.path.join(PROFILES, "traffic_*_27pt160_f64.txt")
 KERNEL_SRC = os.path.join(ROOT, "paper_1106_5908_amd", "csrc", "kernels.hip")
 
 VAL_BYTES = {"f64": 8, "f32": 4, "bf16": 2, "f32f64": 4}
@@ -140,19 +139,29 @@ def kernel_hash() -> str:
         return hashlib.sha256(f.read()).hexdigest()[:16]
 
 
-def read_traffic(plan: dict):
-    """HBM bytes per launch from the committed counter summary of the
-    27-point workload taken with the current kernel source and this plan;
-    None if there is none."""
-    for path in sorted(glob.glob(TRAFFIC_GLOB)):
+def read_traffic(plan, workload: str = "27pt160"):
+    """HBM bytes per product from the committed counter summary of `workload`
+    taken with the current kernel source and this plan (a plan dict, or for
+    the split {"local": ..., "nonlocal": ...}); None if there is none."""
+    for path in sorted(glob.glob(os.path.join(PROFILES, "traffic_*.txt"))):
         try:
             with open(path) as f:
                 t = json.load(f)
         except (OSError, ValueError):
             continue
-        if t.get("kernel_sha") == kernel_hash() and t.get("plan") == plan:
+        if (t.get("kernel_sha") == kernel_hash() and t.get("plan") == plan
+                and t.get("pmc_workload", "27pt160") == workload):
             return t.get("traffic_bytes")
     return None
+
+
+def traffic_report(traffic, model_bytes: float, flops: float):
+    """Measured bytes, their ratio to the algorithmic bytes and the GPU kappa
+    (Eq. (1) analogue); all None without a matching counter summary."""
+    if not traffic:
+        return {"traffic_bytes": None, "traffic_over_model": None, "kappa_gpu": None}
+    return {"traffic_bytes": traffic, "traffic_over_model": traffic / model_bytes,
+            "kappa_gpu": kappa_gpu(traffic, flops, model_bytes)}
 
 
 # ----------------------------------------------------------------------------
@@ -501,6 +510,8 @@ def split_paths(A, x, steps, warmup):
         "plans": {"local": spmv.spmv_get_plan(s, spmv.SPMV_PART_MAIN),
                   "nonlocal": spmv.spmv_get_plan(s, spmv.SPMV_PART_NONLOCAL)},
     })
+    res.update(traffic_report(read_traffic(res["plans"], "irregular8M-split"),
+                              res["split_model_bytes"], flops))
     log(f"split: (a) {ta['p50_ms']*1e3:.0f} us, (b) {tb['p50_ms']*1e3:.0f} us, "
         f"(c) {tc['p50_ms']*1e3:.0f} us, kernels only {tk['p50_ms']*1e3:.0f} us, "
         f"unsplit {tu['p50_ms']*1e3:.0f} us")
@@ -602,12 +613,95 @@ def block_paths(A, steps, warmup, fp64_ms):
                  "max_normalized_err_sampled": max(errs), "err_bound": bound(prec, n),
                  "speedup_vs_k_fp64_calls": k * fp64_ms / tm["ms_per_step"],
                  "plan": spmv.spmv_get_block_plan(h, k)}
+            if prec == "f64":
+                r.update(traffic_report(read_traffic(r["plan"], f"irregular8M-k{k}"), mb, flops))
             log(f"block k={k} {prec}: {r['gflops']:.0f} GFlop/s, x{r['speedup_vs_k_fp64_calls']:.2f} "
                 f"vs k FP64 calls, err {max(errs):.1e}")
             out.append(r)
             del B, C
             torch.cuda.empty_cache()
         spmv.spmv_destroy(h)
+    return out
+
+
+def _plan_index_stream(A, plan, fused_rows: int = 512):
+    """The order in which a plan's launches gather B, as (col_idx order,
+    launch cuts): the matrix order without panels; with K diagonal panels
+    (the library's slices of col - row) panel after panel, one launch each;
+    for the fused-panel kernel row block after row block (fused_rows rows),
+    each block's panels in turn, in one launch."""
+    K = int(plan.get("panels", 1))
+    n = A.nnz
+    if K <= 1:
+        return A.col_idx, [0, n]
+    rows = np.repeat(np.arange(A.n_rows, dtype=np.int64), np.diff(A.row_ptr))
+    d = A.col_idx.astype(np.int64) - rows
+    dmin, dmax = int(d.min()), int(d.max())
+    p = np.clip(((d - dmin) * K) // (dmax - dmin + 1), 0, K - 1)
+    if plan.get("kernel") == 5:
+        key = (rows // fused_rows) * K + p
+        return A.col_idx[np.argsort(key, kind="stable")], [0, n]
+    cuts = [0] + [int(c) for c in np.cumsum(np.bincount(p, minlength=K))]
+    return A.col_idx[np.argsort(p, kind="stable")], cuts
+
+
+def gather_ceiling(A, plan, kernel_ms, block_rows, reps: int = 10):
+    """What the irregular matrix's gathers of B cost on their own
+    (spmv_probe_gather): random 8-byte gathers, as many as the matrix has
+    entries, from a 1 MiB window (resident in every XCD's L2) and from a
+    1 GiB one (HBM); then the index stream of the tuned plan itself (the
+    matrix's col_idx in the plan's launch order and XCD placement) against
+    the product's own time; and the same for each block product, gathering
+    its k doubles per index.  `block_rows`: [(k, plan, ms)]."""
+    import torch
+
+    from paper_1106_5908_amd import spmv
+
+    n = A.nnz
+    rng = np.random.default_rng(1106)
+
+    def timed(fn):
+        return time_launches(fn, reps, 3)["p50_ms"]
+
+    out = {"gathers": n}
+    src = torch.rand(1 << 27, dtype=torch.float64, device="cuda")
+    for name, rows in (("l2_1MiB", 1 << 17), ("hbm_1GiB", 1 << 27)):
+        idx = torch.from_numpy(rng.integers(0, rows, size=n).astype(np.int32)).cuda()
+        t = timed(lambda: spmv.spmv_probe_gather(src[:rows], idx, 1, True))
+        out[f"random_{name}_ms"] = t
+        out[f"random_{name}_G_per_s"] = n / (t * 1e6)
+        del idx
+    del src
+
+    def own(width, pl):
+        order, cuts = _plan_index_stream(A, pl)
+        idx = torch.from_numpy(np.ascontiguousarray(order)).cuda()
+        Bw = torch.rand(A.n_cols * width, dtype=torch.float64, device="cuda")
+        rm = bool(pl.get("xcd_remap", 1))
+
+        def run():
+            for a, b in zip(cuts[:-1], cuts[1:]):
+                spmv.spmv_probe_gather(Bw, idx[a:b], width, rm)
+
+        t = timed(run)
+        del idx, Bw
+        torch.cuda.empty_cache()
+        return t
+
+    t_own = own(1, plan)
+    out.update({"plan": plan, "own_stream_ms": t_own, "kernel_ms": kernel_ms,
+                "kernel_rate_over_own_stream": t_own / kernel_ms,
+                "kernel_rate_over_l2_random": out["random_l2_1MiB_ms"] / kernel_ms})
+    blocks = []
+    for k, pl, ms in block_rows:
+        t = own(k, pl)
+        blocks.append({"k": k, "plan": pl, "own_stream_ms": t, "kernel_ms": ms,
+                       "kernel_rate_over_own_stream": t / ms})
+    out["blocks_f64"] = blocks
+    log(f"gather ceiling: L2-resident random {out['random_l2_1MiB_ms'] * 1e3:.0f} us, HBM random "
+        f"{out['random_hbm_1GiB_ms'] * 1e3:.0f} us, own stream {t_own * 1e3:.0f} us vs kernel "
+        f"{kernel_ms * 1e3:.0f} us ({out['kernel_rate_over_own_stream'] * 100:.0f}%); blocks " +
+        ", ".join(f"k={b['k']} {b['own_stream_ms'] * 1e3:.0f}/{b['kernel_ms'] * 1e3:.0f} us" for b in blocks))
     return out
 
 
@@ -864,7 +958,10 @@ PMC_WORKLOADS = {
     # name: (matrix, k, description)
     "27pt160": ("c2", 1, "27-point 160^3 FP64"),
     "irregular8M": ("c3", 1, "irregular 8M FP64"),
+    "irregular8M-split": ("c3", 0, "irregular 8M FP64, local and nonlocal parts (h = 7,520,000)"),
     "irregular8M-k4": ("c3", 4, "irregular 8M FP64, block of k = 4"),
+    "irregular8M-k8": ("c3", 8, "irregular 8M FP64, block of k = 8"),
+    "irregular8M-k16": ("c3", 16, "irregular 8M FP64, block of k = 16"),
 }
 
 
@@ -872,7 +969,9 @@ def pmc_pass(steps: int, plan_json: str | None, workload: str = "27pt160"):
     """The product of one workload `steps` times with the given plan (no
     tuning, so the profile holds only these dispatches), then a copy of 2^27
     doubles (the calibration kernel of known size), each bracketed by
-    synchronisation."""
+    synchronisation.  Block workloads take the block plan (block_kt set);
+    the split takes {"local": plan, "nonlocal": plan} and runs with the halo
+    resident (no copy)."""
     import torch
 
     from paper_1106_5908_amd import spmv
@@ -881,23 +980,39 @@ def pmc_pass(steps: int, plan_json: str | None, workload: str = "27pt160"):
     mat, k, _ = PMC_WORKLOADS[workload]
     A, x = gen.workload_c2() if mat == "c2" else gen.workload_c3()
     h = make_handle(A, "f64", tune=False)
-    if plan_json:
-        spmv.spmv_set_plan(h, **json.loads(plan_json))
-    if k == 1:
+    handles = [h]
+    plan = json.loads(plan_json) if plan_json else None
+    if k == 0:
+        s = spmv.spmv_split_local_nonlocal(h, gen.halo_begin(A.n_cols))
+        handles.append(s)
+        if plan:
+            spmv.spmv_set_plan(s, spmv.SPMV_PART_MAIN, **plan["local"])
+            spmv.spmv_set_plan(s, spmv.SPMV_PART_NONLOCAL, **plan["nonlocal"])
         B = dev_vec(x, "f64")
         C = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
-        call = lambda: spmv.spmv_run(h, B, C)  # noqa: E731
+        call = lambda: spmv.spmv_run(s, B, C)  # noqa: E731
+        got = {"local": spmv.spmv_get_plan(s, spmv.SPMV_PART_MAIN),
+               "nonlocal": spmv.spmv_get_plan(s, spmv.SPMV_PART_NONLOCAL)}
     else:
-        B = torch.from_numpy(np.repeat(x[:, None], k, axis=1)).to("cuda")
-        C = torch.zeros((A.n_rows, k), dtype=torch.float64, device="cuda")
-        call = lambda: spmv.spmv_run_block(h, B, C)  # noqa: E731
+        if plan:
+            spmv.spmv_set_plan(h, **plan)
+        if k == 1:
+            B = dev_vec(x, "f64")
+            C = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+            call = lambda: spmv.spmv_run(h, B, C)  # noqa: E731
+            got = spmv.spmv_get_plan(h)
+        else:
+            B = torch.from_numpy(gen.block_rhs(A.n_cols, k)).to("cuda")
+            C = torch.zeros((A.n_rows, k), dtype=torch.float64, device="cuda")
+            call = lambda: spmv.spmv_run_block(h, B, C)  # noqa: E731
+            got = spmv.spmv_get_block_plan(h, k)
     for _ in range(steps):
         call()
     torch.cuda.synchronize()
-    plan = spmv.spmv_get_plan(h)
-    # release the handle (its device arrays) before the calibration copy and
-    # before the process ends
-    spmv.spmv_destroy(h)
+    # release the handles (their device arrays) before the calibration copy
+    # and before the process ends
+    for hh in reversed(handles):
+        spmv.spmv_destroy(hh)
     del B, C, call
     n = 1 << 27
     a = torch.empty(n, dtype=torch.float64, device="cuda")
@@ -907,8 +1022,8 @@ def pmc_pass(steps: int, plan_json: str | None, workload: str = "27pt160"):
     torch.cuda.synchronize()
     del a, b
     torch.cuda.empty_cache()
-    print(json.dumps({"pmc_pass": "done", "plan": plan, "copy_bytes_read": 8 * n,
-                      "copy_bytes_written": 8 * n}), flush=True)
+    print(json.dumps({"pmc_pass": "done", "workload": workload, "plan": got,
+                      "copy_bytes_read": 8 * n, "copy_bytes_written": 8 * n}), flush=True)
 
 
 def trace_pass(steps: int):
@@ -1088,7 +1203,7 @@ def summarize_pmc(fetch_dir, write_dir, out_path, plan_json, workload="27pt160",
                 continue
             name = r["Kernel_Name"]
             spmv_kernel = "spmv::" in name and any(
-                k in name for k in ("k_stream", "k_staged", "k_vector", "k_block"))
+                k in name for k in ("k_stream", "k_staged", "k_vector", "k_block", "k_fused"))
             key = "spmv" if spmv_kernel else ("copy" if "k_copy" in name else None)
             if key is None:
                 continue
@@ -1108,23 +1223,29 @@ def summarize_pmc(fetch_dir, write_dir, out_path, plan_json, workload="27pt160",
     fetch_b = fetch["spmv"] * 1024.0 * f_fac
     write_b = write["spmv"] * 1024.0 * w_fac
     mat, k, desc = PMC_WORKLOADS[workload]
+    extra = 0
     if mat == "c2":
         n, nnz = 4096000, 109215352
     else:
         from workloads import gen
 
+        import oracle
+
         A, _ = gen.workload_c3()
         n, nnz = A.n_rows, A.nnz
+        if k == 0:
+            parts = oracle.split(A.row_ptr, A.col_idx, A.val, gen.halo_begin(A.n_cols))
+            extra = split_extra_bytes(int(parts["nl_rows"].size))
     wl = "" if workload == "27pt160" else f" --pmc-workload {workload}"
     res = {
         "kernel_sha": kernel_hash(), "plan": json.loads(plan_json),
-        "workload": desc,
+        "workload": desc, "pmc_workload": workload,
         "fetch_kib_per_product": fetch["spmv"], "write_kib_per_product": write["spmv"],
         "dispatches_per_product": fetch["spmv_dispatches"] / steps,
         "copy_fetch_kib": fetch["copy"], "copy_write_kib": write["copy"],
         "fetch_scale": f_fac, "write_scale": w_fac,
         "traffic_bytes": fetch_b + write_b,
-        "algorithmic_bytes": algorithmic_bytes(n, n, nnz, "f64", k),
+        "algorithmic_bytes": algorithmic_bytes(n, n, nnz, "f64", max(k, 1)) + extra,
         "commands": [
             "rocprofv3 --pmc FETCH_SIZE -d <fetch_dir> -o p --output-format csv -- "
             f"python3 bench.py --pmc-pass --steps {steps} --plan '<plan>'{wl}",
@@ -1151,7 +1272,7 @@ def summarize_counters(out_path, command, *dirs):
         for r in _counter_rows(d):
             name = r["Kernel_Name"]
             spmv_kernel = "spmv::" in name and any(
-                k in name for k in ("k_stream", "k_staged", "k_vector", "k_block"))
+                k in name for k in ("k_stream", "k_staged", "k_vector", "k_block", "k_fused"))
             key = "spmv" if spmv_kernel else ("copy" if "k_copy" in name else None)
             if key is None:
                 continue
@@ -1263,7 +1384,7 @@ def main():
                                      plan=json.loads(args.plan) if args.plan else None)
     flops = 2.0 * A2.nnz
     mb = head["model_bytes"]
-    traffic = read_traffic(head["plan"])
+    traffic = read_traffic(head["plan"], "27pt160")
     # the same time basis as `value`: the timed region's events over K steps
     achieved = mb / (head["ms_per_step"] * 1e6)
     roof = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
@@ -1298,6 +1419,8 @@ def main():
         A3, x3 = gen.workload_c3()
         log(f"irregular N=8e6 generated in {time.time() - t0:.1f}s ({A3.nnz} entries)")
         r3, ref3, den3 = run_spmv_path(A3, x3, "f64", args.steps, args.warmup, "irregular8M")
+        r3.update(traffic_report(read_traffic(r3["plan"], "irregular8M"), r3["model_bytes"],
+                                 2.0 * A3.nnz))
         paths["irregular8M_f64"] = r3
         p3 = []
         for prec in ("f32", "bf16", "f32f64"):
@@ -1310,6 +1433,9 @@ def main():
         paths["split_irregular8M"] = sp
         paths["overlap_probe"] = overlap_probe()
         paths["block_irregular8M"] = block_paths(A3, max(10, args.steps // 4), 3, r3["ms_per_step"])
+        paths["gather_ceiling_irregular8M"] = gather_ceiling(
+            A3, r3["plan"], r3["ms_per_step"],
+            [(b["k"], b["plan"], b["ms_per_step"]) for b in paths["block_irregular8M"] if b["prec"] == "f64"])
         paths["kpm_irregular8M"] = kpm_path(A3)
         paths["lanczos_irregular8M"] = lanczos_path(A3, r3["ms_per_step"])
         del A3, x3

@@ -383,7 +383,16 @@ spmv_status_t spmv_create_sym_crs(int64_t n, int64_t nnz, const int32_t *row_ptr
  *                gain; the run table (48 bytes per tile) is built on the host
  *                from a copy of col_idx read back once.  For batch handles:
  *                one workgroup per batch tile, as SPMV_KERNEL_TILE_GRID.
- *   tile_items   4, 8 or 16 (stream kernel); 8 or 16 (staged kernel)
+ *                SPMV_KERNEL_FUSED_PANELS: the diagonal panels of the plan
+ *                (`panels`, 1 to 8) walked by one launch: a workgroup takes
+ *                up to 512 consecutive rows and, panel after panel, streams
+ *                that panel's entries of its rows as the stream kernel does,
+ *                keeping the rows' sums in registers, so C is read and
+ *                written once per call however many panels there are (parts
+ *                that cover all rows; not for split nonlocal parts, batches or
+ *                symmetric handles).  In a block plan (spmv_get_block_plan)
+ *                the same walk with the block kernel's column layout.
+ *   tile_items   4, 8 or 16 (stream and fused-panel kernels); 8 or 16 (staged)
  *   lanes        2, 4, 8, 16, 32 or 64 (vector kernel)
  *   nontemporal  1: val and col_idx are loaded with the streaming hint so
  *                they do not displace B from the caches
@@ -405,6 +414,7 @@ spmv_status_t spmv_create_sym_crs(int64_t n, int64_t nnz, const int32_t *row_ptr
 #define SPMV_KERNEL_VECTOR 2
 #define SPMV_KERNEL_TILE_GRID 3
 #define SPMV_KERNEL_STAGED 4
+#define SPMV_KERNEL_FUSED_PANELS 5
 #define SPMV_PART_MAIN 0
 #define SPMV_PART_NONLOCAL 1
 

@@ -435,8 +435,22 @@ __global__ __launch_bounds__(WG) void k_stream(CsrDev A, const TileRP *__restric
 // LDS elements of B a staged tile may hold.
 template <class X> constexpr int stage_slots() { return RUN_STAGE_BYTES / (int)sizeof(X); }
 
+// In the F32-value / F64-vector mode the staged B shares the products'
+// LDS buffer: every lane reads its B values into registers before the
+// products overwrite them (one more barrier), so a workgroup needs 32 KB
+// instead of 44 KB at 16 entries per lane and five workgroups fit a CU
+// instead of three (on the 27-point matrix 184 against 202 us; the other
+// modes, whose staging costs less, gain nothing from it).
+template <int P> constexpr bool stage_shares_products() { return P == P_F32_F64; }
+template <int P, int E> constexpr int staged_lds_elems() {
+  using X = typename Ty<P>::X;
+  return stage_shares_products<P>()
+             ? (WG * E > stage_slots<X>() ? WG * E : stage_slots<X>())
+             : WG * E + stage_slots<X>();
+}
+
 // One tile of the staged kernel; `rt` is its run-table row and s_prod holds
-// WG * E + stage_slots<X>() elements.  `bias` as in tile_grouped.
+// staged_lds_elems<P, E>() elements.  `bias` as in tile_grouped.
 template <int P, int E, bool NT, bool IND>
 __device__ __forceinline__ void staged_tile(const int32_t *__restrict__ rp,
                                             const int32_t *__restrict__ col,
@@ -450,7 +464,8 @@ __device__ __forceinline__ void staged_tile(const int32_t *__restrict__ rp,
   using X = typename Ty<P>::X;
   constexpr int G = group_of<V>();
   constexpr int NB = stage_slots<X>() / WG;
-  X *s_b = s_prod + WG * E;
+  constexpr bool share = stage_shares_products<P>();
+  X *s_b = share ? s_prod : s_prod + WG * E;
   const int nr = rt[0];
   if (nr == 0) {
     tile_grouped<P, E, NT, IND>(rp, col, val, row_ids, m0, m1, bias, x, y, s_prod);
@@ -500,6 +515,7 @@ __device__ __forceinline__ void staged_tile(const int32_t *__restrict__ rp,
     if (cc >= s3) d = d3;
     xg[e] = s_b[cc + d];
   }
+  if constexpr (share) lds_barrier();  // B read by every lane before the products overwrite it
 #pragma unroll
   for (int e = 0; e < E / G; ++e) {
     const int g = e * WG + tid;
@@ -516,11 +532,86 @@ __global__ __launch_bounds__(WG) void k_staged(CsrDev A, const TileRP *__restric
                                                int remap, const void *xv, void *yv) {
   using V = typename Ty<P>::V;
   using X = typename Ty<P>::X;
-  __shared__ X s_prod[WG * E + stage_slots<X>()];
+  __shared__ X s_prod[staged_lds_elems<P, E>()];
   const int64_t t = xcd_tile(blockIdx.x, n_tiles, remap);
   staged_tile<P, E, NT, IND>(A.row_ptr, A.col, static_cast<const V *>(A.val), A.row_ids, tiles[t],
                              tiles[t + 1], 0, runs + t * RUN_WORDS, static_cast<const X *>(xv),
                              static_cast<X *>(yv), s_prod);
+}
+
+// ---------------------------------------------------------------------------
+// Diagonal panels in one launch.  The panels of a part split its entries by
+// their distance from the diagonal so that the workgroups running at one time
+// gather from a narrow window of B (one that stays in L2); applied as K
+// launches, every launch reads and writes C again.  Here workgroup b takes
+// rows [b*R, b*R + R) and walks the K panels of those rows in turn: for each
+// panel the block's entries are loaded as in the stream kernel (grouped,
+// coalesced), their products go to LDS, and each lane adds the sums of its
+// two rows (tid and tid + 256) to registers.  C is read once before the
+// first panel and written once after the last; a row with no entry in any
+// panel is left untouched.  Workgroups started together walk the panels
+// together, so the window of B stays narrow.  A panel whose entries in the
+// block exceed one tile is summed row by row from global memory (the
+// planner sizes R so that this is rare).
+// ---------------------------------------------------------------------------
+template <int P, int E, bool NT>
+__global__ __launch_bounds__(WG) void k_fused(PanelSetDev S, int R, int64_t n_blocks, int remap,
+                                              const void *xv, void *yv) {
+  using V = typename Ty<P>::V;
+  using X = typename Ty<P>::X;
+  constexpr int TILE = WG * E;
+  constexpr int G = group_of<V>();
+  __shared__ X s_prod[TILE];
+  const X *__restrict__ x = static_cast<const X *>(xv);
+  X *__restrict__ y = static_cast<X *>(yv);
+  const int64_t b = xcd_tile(blockIdx.x, n_blocks, remap);
+  const int64_t r0 = b * R;
+  const int64_t r1 = min(r0 + (int64_t)R, S.n_rows);
+  const int nrows = (int)(r1 - r0);
+  const int tid = (int)threadIdx.x;
+  const bool has0 = tid < nrows, has1 = tid + WG < nrows;
+  const int64_t row0 = r0 + (has0 ? tid : 0), row1 = r0 + (has1 ? tid + WG : 0);
+  const X c0 = y[row0], c1 = y[row1];
+  X acc0 = neg_zero<X>(), acc1 = neg_zero<X>();
+  int cnt0 = 0, cnt1 = 0;
+  for (int k = 0; k < S.K; ++k) {
+    const int32_t *__restrict__ rp = S.rp[k];
+    const int32_t *__restrict__ col = S.col[k];
+    const V *__restrict__ val = static_cast<const V *>(S.val[k]);
+    const int pa = rp[r0], pb = rp[r1];
+    const int a0 = rp[row0], e0 = has0 ? rp[row0 + 1] : a0;
+    const int a1 = rp[row1], e1 = has1 ? rp[row1 + 1] : a1;
+    cnt0 += e0 - a0;
+    cnt1 += e1 - a1;
+    const int nnz = pb - pa;
+    if (nnz == 0) continue;
+    if (nnz > TILE - (G - 1)) {
+      for (int j = a0; j < e0; ++j) acc0 += widen<X>(ld<V, NT>(val + j)) * x[ld<int32_t, NT>(col + j)];
+      for (int j = a1; j < e1; ++j) acc1 += widen<X>(ld<V, NT>(val + j)) * x[ld<int32_t, NT>(col + j)];
+      continue;
+    }
+    // each panel is an allocation of its own, so entry 0 is group-aligned
+    const int off = pa % G;
+    const int base = pa - off;
+    int c[E];
+    V v[E];
+    load_cv_groups<E, NT>(col, val, base, nnz, off, c, v);
+    X xg[E];
+#pragma unroll
+    for (int e = 0; e < E; ++e) xg[e] = x[c[e]];
+#pragma unroll
+    for (int e = 0; e < E / G; ++e) {
+      const int g = e * WG + tid;
+#pragma unroll
+      for (int j = 0; j < G; ++j) s_prod[G * g + j] = widen<X>(v[G * e + j]) * xg[G * e + j];
+    }
+    lds_barrier();
+    acc0 += lds_row_sum(s_prod, a0 - base, e0 - base, 1);
+    acc1 += lds_row_sum(s_prod, a1 - base, e1 - base, 1);
+    lds_barrier();
+  }
+  if (has0 && cnt0 > 0) y[row0] = c0 + acc0;
+  if (has1 && cnt1 > 0) y[row1] = c1 + acc1;
 }
 
 // ---------------------------------------------------------------------------
@@ -736,6 +827,128 @@ __global__ __launch_bounds__(WG) void k_block(CsrDev A, const TileRP *__restrict
   }
 }
 
+// Block product over a panel set in one launch (see k_fused): workgroup b
+// takes rows [b*R, b*R + R), R = NR * NG; lane group g (G = KT/VW lanes)
+// owns rows g, g + NG, ..., g + (NR-1)*NG of the block and keeps their VW
+// column sums in registers across the K panels.  Per panel the block's
+// col_idx / val are staged in LDS (values scaled as in k_block) and each
+// group walks its rows; C is read and written once, after the last panel.
+template <int P, int E, int KT, int VW, int NR, bool NT>
+__global__ __launch_bounds__(WG) void k_block_fused(PanelSetDev S, int64_t n_blocks, int remap,
+                                                    int k, int t0, const void *Bv, int64_t ldb,
+                                                    void *Cv, int64_t ldc,
+                                                    typename Ty<P>::X scale) {
+  using V = typename Ty<P>::V;
+  using X = typename Ty<P>::X;
+  constexpr int TILE = WG * E;
+  constexpr int G = KT / VW;
+  constexpr int NG = WG / G;
+  constexpr int R = NG * NR;
+  __shared__ int32_t s_col[TILE];
+  __shared__ X s_val[TILE];
+  const X *__restrict__ B = static_cast<const X *>(Bv);
+  X *__restrict__ C = static_cast<X *>(Cv);
+  const int tid = threadIdx.x;
+  const int64_t b = xcd_tile(blockIdx.x, n_blocks, remap);
+  const int64_t r0 = b * R;
+  const int64_t r1 = min(r0 + (int64_t)R, S.n_rows);
+  const int nrows = (int)(r1 - r0);
+  const int g = tid / G;
+  const int lane = tid % G;
+  const int cb = t0 + lane * VW;
+  const bool active = cb < k;  // VW divides k whenever VW > 1
+  X acc[NR][VW];
+  int cnt[NR];
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    cnt[i] = 0;
+#pragma unroll
+    for (int w = 0; w < VW; ++w) acc[i][w] = neg_zero<X>();
+  }
+  for (int kk = 0; kk < S.K; ++kk) {
+    const int32_t *__restrict__ rp = S.rp[kk];
+    const int32_t *__restrict__ col = S.col[kk];
+    const V *__restrict__ val = static_cast<const V *>(S.val[kk]);
+    const int pa = rp[r0], pb = rp[r1];
+    const int nnz = pb - pa;
+    if (nnz == 0) continue;
+    if (nnz > TILE) {
+#pragma unroll
+      for (int i = 0; i < NR; ++i) {
+        const int rr = g + i * NG;
+        if (rr >= nrows) continue;
+        const int a = rp[r0 + rr], e = rp[r0 + rr + 1];
+        cnt[i] += e - a;
+        if (!active) continue;
+        for (int j = a; j < e; ++j) {
+          const X av = widen<X>(ld<V, NT>(val + j)) * scale;
+          X bv[VW];
+          load_vec<X, VW>(B + (int64_t)ld<int32_t, NT>(col + j) * ldb + cb, bv);
+#pragma unroll
+          for (int w = 0; w < VW; ++w) acc[i][w] += av * bv[w];
+        }
+      }
+      continue;
+    }
+    {
+      const int last = nnz - 1;
+      int cc[E];
+      V vv[E];
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int q = min(e * WG + tid, last);
+        cc[e] = ld<int32_t, NT>(col + pa + q);
+        vv[e] = ld<V, NT>(val + pa + q);
+      }
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        s_col[e * WG + tid] = cc[e];
+        s_val[e * WG + tid] = widen<X>(vv[e]) * scale;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NR; ++i) {
+      const int rr = g + i * NG;
+      if (rr >= nrows) continue;
+      const int a = rp[r0 + rr] - pa, e = rp[r0 + rr + 1] - pa;
+      cnt[i] += e - a;
+      if (!active) continue;
+      int j = a;
+      for (; j + 2 <= e; j += 2) {
+        const int c0 = s_col[j], c1 = s_col[j + 1];
+        const X a0 = s_val[j], a1 = s_val[j + 1];
+        X b0[VW], b1[VW];
+        load_vec<X, VW>(B + (int64_t)c0 * ldb + cb, b0);
+        load_vec<X, VW>(B + (int64_t)c1 * ldb + cb, b1);
+#pragma unroll
+        for (int w = 0; w < VW; ++w) {
+          acc[i][w] += a0 * b0[w];
+          acc[i][w] += a1 * b1[w];
+        }
+      }
+      if (j < e) {
+        const int c0 = s_col[j];
+        const X a0 = s_val[j];
+        X b0[VW];
+        load_vec<X, VW>(B + (int64_t)c0 * ldb + cb, b0);
+#pragma unroll
+        for (int w = 0; w < VW; ++w) acc[i][w] += a0 * b0[w];
+      }
+    }
+    __syncthreads();
+  }
+  if (!active) return;
+#pragma unroll
+  for (int i = 0; i < NR; ++i) {
+    const int rr = g + i * NG;
+    if (rr >= nrows || cnt[i] == 0) continue;
+    const int64_t o = r0 + rr;
+#pragma unroll
+    for (int w = 0; w < VW; ++w) C[o * ldc + cb + w] = C[o * ldc + cb + w] + acc[i][w];
+  }
+}
+
 // ---------------------------------------------------------------------------
 // Batch kernels: tile t of the queue is (member, r0, r1); member arrays are
 // found through the descriptor table.
@@ -827,7 +1040,7 @@ __global__ __launch_bounds__(WG) void k_batch_staged(const int32_t *__restrict__
                                                      int64_t n_tiles, const void *xv, void *yv) {
   using V = typename Ty<P>::V;
   using X = typename Ty<P>::X;
-  __shared__ X s_prod[WG * E + stage_slots<X>()];
+  __shared__ X s_prod[staged_lds_elems<P, E>()];
   const int64_t t = xcd_tile(blockIdx.x, n_tiles, 1);
   const BatchTile T = tiles[t];
   const BatchDesc D = desc[T.member];
@@ -1028,6 +1241,116 @@ int persistent_grid_for(int device) {
   return (per_cu < 1 ? 1 : per_cu) * n_cu;
 }
 
+template <int P, int E>
+hipError_t run_fused(const PanelSetDev &S, int R, int nt, int remap, const void *x, void *y,
+                     hipStream_t s) {
+  if (S.n_rows <= 0) return hipSuccess;
+  const int64_t nb = (S.n_rows + R - 1) / R;
+  if (nt)
+    hipLaunchKernelGGL((k_fused<P, E, true>), dim3((unsigned)nb), dim3(WG), 0, s, S, R, nb, remap, x,
+                       y);
+  else
+    hipLaunchKernelGGL((k_fused<P, E, false>), dim3((unsigned)nb), dim3(WG), 0, s, S, R, nb, remap, x,
+                       y);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t dispatch_fused(const PanelSetDev &S, int R, int items, int nt, int remap, const void *x,
+                          void *y, hipStream_t s) {
+  switch (items) {
+    case 4: return run_fused<P, 4>(S, R, nt, remap, x, y, s);
+    case 8: return run_fused<P, 8>(S, R, nt, remap, x, y, s);
+    case 16: return run_fused<P, 16>(S, R, nt, remap, x, y, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+// Rows per lane group of the fused block kernel for a workgroup of at most
+// want_rows rows (at least one pass of the NG lane groups).
+constexpr int block_nr_for(int ng, int want_rows) {
+  return want_rows >= 8 * ng ? 8 : want_rows >= 4 * ng ? 4 : want_rows >= 2 * ng ? 2 : 1;
+}
+
+template <int P, int KT, int VW, int NR>
+hipError_t run_block_fused_nr(const PanelSetDev &S, int nt, int remap, int k, int t0, const void *B,
+                              int64_t ldb, void *C, int64_t ldc, double scale, hipStream_t s) {
+  using X = typename Ty<P>::X;
+  constexpr int R = (WG / (KT / VW)) * NR;
+  const int64_t nb = (S.n_rows + R - 1) / R;
+  const X sc = static_cast<X>(scale);
+  if (nt)
+    hipLaunchKernelGGL((k_block_fused<P, 8, KT, VW, NR, true>), dim3((unsigned)nb), dim3(WG), 0, s, S,
+                       nb, remap, k, t0, B, ldb, C, ldc, sc);
+  else
+    hipLaunchKernelGGL((k_block_fused<P, 8, KT, VW, NR, false>), dim3((unsigned)nb), dim3(WG), 0, s,
+                       S, nb, remap, k, t0, B, ldb, C, ldc, sc);
+  return hipGetLastError();
+}
+
+template <int P, int KT, int VW>
+hipError_t run_block_fused_kt(const PanelSetDev &S, int want_rows, int nt, int remap, int k, int t0,
+                              const void *B, int64_t ldb, void *C, int64_t ldc, double scale,
+                              hipStream_t s) {
+  switch (block_nr_for(WG / (KT / VW), want_rows)) {
+    case 8: return run_block_fused_nr<P, KT, VW, 8>(S, nt, remap, k, t0, B, ldb, C, ldc, scale, s);
+    case 4: return run_block_fused_nr<P, KT, VW, 4>(S, nt, remap, k, t0, B, ldb, C, ldc, scale, s);
+    case 2: return run_block_fused_nr<P, KT, VW, 2>(S, nt, remap, k, t0, B, ldb, C, ldc, scale, s);
+    default: return run_block_fused_nr<P, KT, VW, 1>(S, nt, remap, k, t0, B, ldb, C, ldc, scale, s);
+  }
+}
+
+template <int P, int VW>
+hipError_t run_block_fused_vw(const PanelSetDev &S, int want_rows, int nt, int remap, int kt, int k,
+                              int t0, const void *B, int64_t ldb, void *C, int64_t ldc, double scale,
+                              hipStream_t s) {
+  switch (kt) {
+    case 4:
+      return run_block_fused_kt<P, 4, VW>(S, want_rows, nt, remap, k, t0, B, ldb, C, ldc, scale, s);
+    case 8:
+      return run_block_fused_kt<P, 8, VW>(S, want_rows, nt, remap, k, t0, B, ldb, C, ldc, scale, s);
+    case 16:
+      return run_block_fused_kt<P, 16, VW>(S, want_rows, nt, remap, k, t0, B, ldb, C, ldc, scale, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <int P>
+bool block_wide(int kt, int k, int64_t ldb, int64_t ldc, const void *B, const void *C) {
+  using X = typename Ty<P>::X;
+  constexpr int VWIDE = sizeof(X) == 8 ? 2 : 4;
+  return (k % VWIDE == 0) && (ldb % VWIDE == 0) && (ldc % VWIDE == 0) && (kt % VWIDE == 0) &&
+         (reinterpret_cast<uintptr_t>(B) % (sizeof(X) * VWIDE) == 0) &&
+         (reinterpret_cast<uintptr_t>(C) % (sizeof(X) * VWIDE) == 0);
+}
+
+template <int P>
+hipError_t dispatch_block_fused(const PanelSetDev &S, int want_rows, int nt, int remap, int kt, int k,
+                                const void *B, int64_t ldb, void *C, int64_t ldc, double scale,
+                                hipStream_t s) {
+  using X = typename Ty<P>::X;
+  constexpr int VWIDE = sizeof(X) == 8 ? 2 : 4;
+  const bool wide = block_wide<P>(kt, k, ldb, ldc, B, C);
+  for (int t0 = 0; t0 < k; t0 += kt) {
+    hipError_t e = wide ? run_block_fused_vw<P, VWIDE>(S, want_rows, nt, remap, kt, k, t0, B, ldb, C,
+                                                       ldc, scale, s)
+                        : run_block_fused_vw<P, 1>(S, want_rows, nt, remap, kt, k, t0, B, ldb, C,
+                                                   ldc, scale, s);
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+template <int P>
+int block_fused_rows_p(int kt, int k, int64_t ldb, int64_t ldc, const void *B, const void *C,
+                       int want_rows) {
+  using X = typename Ty<P>::X;
+  constexpr int VWIDE = sizeof(X) == 8 ? 2 : 4;
+  const int vw = block_wide<P>(kt, k, ldb, ldc, B, C) ? VWIDE : 1;
+  const int ng = WG / (kt / vw);
+  return ng * block_nr_for(ng, want_rows);
+}
+
 }  // namespace
 
 #define SPMV_PREC_SWITCH(prec, CALL) \
@@ -1080,6 +1403,27 @@ hipError_t launch_spmv_block(int prec, const CsrDev &A, const TileRP *tiles, int
   if (n_tiles <= 0) return hipSuccess;
   SPMV_PREC_SWITCH(prec, (dispatch_block<PP>(A, tiles, n_tiles, nontemporal, xcd_remap, kt, k, B,
                                               ldb, C, ldc, scale, s)))
+}
+
+hipError_t launch_spmv_fused(int prec, const PanelSetDev &S, int R, int tile_items, int nontemporal,
+                             int xcd_remap, const void *x, void *y, hipStream_t s) {
+  if (R < 1 || R > 2 * WG || S.K < 1 || S.K > PANEL_MAX) return hipErrorInvalidValue;
+  SPMV_PREC_SWITCH(prec, (dispatch_fused<PP>(S, R, tile_items, nontemporal, xcd_remap, x, y, s)))
+}
+
+int block_fused_rows(int prec, int kt, int k, int64_t ldb, int64_t ldc, const void *B, const void *C,
+                     int want_rows) {
+  if (kt != 4 && kt != 8 && kt != 16) return 0;
+  SPMV_PREC_SWITCH(prec, (block_fused_rows_p<PP>(kt, k, ldb, ldc, B, C, want_rows)))
+}
+
+hipError_t launch_spmv_block_fused(int prec, const PanelSetDev &S, int want_rows, int nontemporal,
+                                   int xcd_remap, int kt, int k, const void *B, int64_t ldb, void *C,
+                                   int64_t ldc, double scale, hipStream_t s) {
+  if (S.K < 1 || S.K > PANEL_MAX) return hipErrorInvalidValue;
+  if (S.n_rows <= 0) return hipSuccess;
+  SPMV_PREC_SWITCH(prec, (dispatch_block_fused<PP>(S, want_rows, nontemporal, xcd_remap, kt, k, B,
+                                                    ldb, C, ldc, scale, s)))
 }
 
 hipError_t launch_batch_reset(int32_t *counter, hipStream_t s) {

@@ -143,9 +143,10 @@ spmv_plan_t default_plan() {
 
 void check_plan(const spmv_plan_t &p) {
   if (p.kernel != SPMV_KERNEL_STREAM && p.kernel != SPMV_KERNEL_VECTOR &&
-      p.kernel != SPMV_KERNEL_TILE_GRID && p.kernel != SPMV_KERNEL_STAGED)
+      p.kernel != SPMV_KERNEL_TILE_GRID && p.kernel != SPMV_KERNEL_STAGED &&
+      p.kernel != SPMV_KERNEL_FUSED_PANELS)
     fail(SPMV_ERR_INVALID_ARG,
-         "plan.kernel must be SPMV_KERNEL_STREAM, _VECTOR, _TILE_GRID or _STAGED");
+         "plan.kernel must be SPMV_KERNEL_STREAM, _VECTOR, _TILE_GRID, _STAGED or _FUSED_PANELS");
   if (p.tile_items != 4 && p.tile_items != 8 && p.tile_items != 16)
     fail(SPMV_ERR_INVALID_ARG, "plan.tile_items must be 4, 8 or 16");
   if (p.kernel == SPMV_KERNEL_STAGED && p.tile_items == 4)
@@ -356,6 +357,8 @@ void choose_plan(spmv_handle_s *h, Part &p, const char *part_name) {
     if (cache_lookup(tune_key(h->device, h->prec, 1, part_name, p.n_rows, p.stats), &c)) p.plan = c;
   }
   if (p.plan.panels > 1 && (p.row_ids.p || h->kind == SPMV_KIND_BATCH)) p.plan.panels = 1;
+  if (p.plan.kernel == SPMV_KERNEL_FUSED_PANELS && (p.row_ids.p || h->kind == SPMV_KIND_BATCH))
+    p.plan.kernel = SPMV_KERNEL_STREAM;
   if (p.plan.panels > 1) build_panels(h, p, p.plan.panels);
   if (h->kind != SPMV_KIND_BATCH) prepare_part(h, p);
   if (std::getenv("SPMV_LOG"))
@@ -373,6 +376,10 @@ void prepare_part(spmv_handle_s *h, Part &p) {
   const int items = p.plan.tile_items;
   const bool staged = p.plan.kernel == SPMV_KERNEL_STAGED;
   const int xb = vec_bytes(h->prec);
+  if (p.plan.kernel == SPMV_KERNEL_FUSED_PANELS) {
+    (void)fused_rows_for(h, p, p.plan.panels, kWG * items - 4);
+    return;
+  }
   if (p.plan.panels > 1) {
     for (auto &q : build_panels(h, p, p.plan.panels)) {
       (void)q->tiles_for(items);
@@ -388,6 +395,10 @@ void prepare_part(spmv_handle_s *h, Part &p) {
 bool part_prepared(const Part &p, int x_bytes) {
   (void)x_bytes;
   const int items = p.plan.tile_items;
+  if (p.plan.kernel == SPMV_KERNEL_FUSED_PANELS) {
+    if (p.plan.panels > 1 && p.panel_sets.find(p.plan.panels) == p.panel_sets.end()) return false;
+    return p.fused_rows.find(std::make_pair(p.plan.panels, kWG * items - 4)) != p.fused_rows.end();
+  }
   const bool staged = p.plan.kernel == SPMV_KERNEL_STAGED;
   auto ready = [&](const Part &q) {
     if (q.n_rows == 0 || q.nnz == 0) return true;
@@ -405,8 +416,63 @@ bool part_prepared(const Part &p, int x_bytes) {
   return ready(p);
 }
 
+PanelSetDev panel_set_dev(spmv_handle_s *h, Part &p, int K) {
+  PanelSetDev S{};
+  S.n_rows = p.n_rows;
+  if (K <= 1) {
+    S.K = 1;
+    S.rp[0] = p.row_ptr.as<const int32_t>();
+    S.col[0] = p.col.as<const int32_t>();
+    S.val[0] = p.val.p;
+    return S;
+  }
+  auto &set = build_panels(h, p, K);
+  S.K = int(set.size());
+  for (int k = 0; k < S.K; ++k) {
+    S.rp[k] = set[size_t(k)]->row_ptr.as<const int32_t>();
+    S.col[k] = set[size_t(k)]->col.as<const int32_t>();
+    S.val[k] = set[size_t(k)]->val.p;
+  }
+  return S;
+}
+
+int fused_rows_for(spmv_handle_s *h, Part &p, int K, int cap) {
+  const auto key = std::make_pair(K, cap);
+  auto it = p.fused_rows.find(key);
+  if (it != p.fused_rows.end()) return it->second;
+  std::vector<const std::vector<int32_t> *> rps;
+  if (K > 1) {
+    for (auto &q : build_panels(h, p, K)) rps.push_back(&q->h_row_ptr);
+  } else {
+    rps.push_back(&p.h_row_ptr);
+  }
+  const int64_t n = p.n_rows;
+  int R = 512;
+  for (; R > 16; R /= 2) {
+    bool ok = true;
+    for (const std::vector<int32_t> *rp : rps) {
+      for (int64_t b = 0; b < n && ok; b += R) {
+        const int64_t e = std::min<int64_t>(b + R, n);
+        if (int64_t((*rp)[size_t(e)]) - (*rp)[size_t(b)] > cap) ok = false;
+      }
+      if (!ok) break;
+    }
+    if (ok) break;
+  }
+  p.fused_rows.emplace(key, R);
+  return R;
+}
+
 void run_part(spmv_handle_s *h, Part &p, const void *B, void *C, hipStream_t s) {
   if (p.n_rows == 0 || p.nnz == 0) return;
+  if (p.plan.kernel == SPMV_KERNEL_FUSED_PANELS) {
+    const PanelSetDev S = panel_set_dev(h, p, p.plan.panels);
+    const int R = fused_rows_for(h, p, p.plan.panels, kWG * p.plan.tile_items - 4);
+    hip_ok(launch_spmv_fused(h->prec, S, R, p.plan.tile_items, p.plan.nontemporal,
+                             p.plan.xcd_remap, B, C, s),
+           "kernel launch");
+    return;
+  }
   const bool staged = p.plan.kernel == SPMV_KERNEL_STAGED;
   const int xb = vec_bytes(h->prec);
   if (p.plan.panels > 1) {
@@ -502,9 +568,20 @@ std::vector<spmv_plan_t> candidates() {
   return c;
 }
 
-// Diagonal-panel candidates (parts that cover all rows only).
+// Diagonal-panel candidates (parts that cover all rows only): the panels
+// applied one launch each, and walked by the fused-panel kernel.
 std::vector<spmv_plan_t> panel_candidates() {
   std::vector<spmv_plan_t> c;
+  for (int k : {1, 2, 4, 8})
+    for (int e : {8, 16})
+      for (int rm : {1, 0}) {
+        spmv_plan_t p = default_plan();
+        p.kernel = SPMV_KERNEL_FUSED_PANELS;
+        p.panels = k;
+        p.tile_items = e;
+        p.xcd_remap = rm;
+        c.push_back(p);
+      }
   for (int k : {2, 4, 8})
     for (int e : {4, 8, 16})
       for (int rm : {0, 1}) {
@@ -632,6 +709,9 @@ extern "C" spmv_status_t spmv_set_plan(spmv_handle_t h_, int32_t part, const spm
     Part &p = part_of(h, part);
     if (plan->panels > 1 && p.row_ids.p)
       fail(SPMV_ERR_UNSUPPORTED, "diagonal panels need a part that covers all rows");
+    if (plan->kernel == SPMV_KERNEL_FUSED_PANELS && (p.row_ids.p || h->kind == SPMV_KIND_BATCH ||
+                                                     h->kind == SPMV_KIND_SYMMETRIC))
+      fail(SPMV_ERR_UNSUPPORTED, "the fused-panel kernel needs a part that covers all rows");
     DeviceGuard dg(h->device);
     p.plan = *plan;
     if (h->kind == SPMV_KIND_BATCH)
@@ -718,34 +798,42 @@ extern "C" spmv_status_t spmv_tune(spmv_handle_t h_, int32_t k, void *stream) {
     // remap 0 spreads every row range over all eight XCDs, so the XCDs
     // gather from one shared window of B, which the MALL can hold where a
     // window per XCD would not (wide blocks)
-    for (int rm : {p.plan.xcd_remap, 1 - p.plan.xcd_remap})
-      for (int pn : {1, 2, 4, 8})
-        for (int kt : {4, 8, 16}) {
-          if (kt > 2 * k && kt != 4) continue;
-          for (int nt : {1, 0}) {
-            const float ms = tm.median_ms(
-                [&] { run_block_part(h, p, kt, nt, rm, pn, k, x.p, k, y.p, k, s); }, s);
-            if (ms < best * 0.99f) {
-              best = ms;
-              best_kt = kt;
-              best_nt = nt;
-              best_pn = pn;
-              best_rm = rm;
+    bool best_fused = false;
+    for (int fused : {0, 1})
+      for (int rm : {p.plan.xcd_remap, 1 - p.plan.xcd_remap})
+        for (int pn : {1, 2, 4, 8})
+          for (int kt : {4, 8, 16}) {
+            if (kt > 2 * k && kt != 4) continue;
+            for (int nt : {1, 0}) {
+              const float ms = tm.median_ms(
+                  [&] {
+                    run_block_part(h, p, kt, nt, rm, pn, k, x.p, k, y.p, k, s, 1.0, fused != 0);
+                  },
+                  s);
+              if (ms < best * 0.99f) {
+                best = ms;
+                best_kt = kt;
+                best_nt = nt;
+                best_pn = pn;
+                best_rm = rm;
+                best_fused = fused != 0;
+              }
             }
           }
-        }
     spmv_plan_t c = p.plan;
     c.block_kt = best_kt;
     c.nontemporal = best_nt;
     c.panels = best_pn;
     c.xcd_remap = best_rm;
+    c.kernel = best_fused ? SPMV_KERNEL_FUSED_PANELS : SPMV_KERNEL_STREAM;
     h->block_plans[k] = c;
     std::vector<int> keep{p.plan.panels};
     for (auto &bp : h->block_plans) keep.push_back(bp.second.panels);
     prune_panels(p, keep);
     if (std::getenv("SPMV_LOG"))
-      std::fprintf(stderr, "libspmv: tuned block k=%d: kt=%d nt=%d panels=%d remap=%d (%.1f us)\n",
-                   k, best_kt, best_nt, best_pn, best_rm, best * 1000.0f);
+      std::fprintf(stderr,
+                   "libspmv: tuned block k=%d: kt=%d nt=%d panels=%d remap=%d fused=%d (%.1f us)\n",
+                   k, best_kt, best_nt, best_pn, best_rm, int(best_fused), best * 1000.0f);
     if (!(h->flags & SPMV_FLAG_NO_TUNE_CACHE))
       cache_store(tune_key(h->device, h->prec, k, "block", p.n_rows, p.stats), c);
   });

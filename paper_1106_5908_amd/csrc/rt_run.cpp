@@ -29,8 +29,17 @@ int default_kt(int k) {
 // The panels are shared with the single-vector plan.
 void run_block_part(spmv_handle_s *h, Part &p, int kt, int nt, int remap, int panels, int k,
                     const void *B, int64_t ldb, void *C, int64_t ldc, hipStream_t s,
-                    double scale) {
+                    double scale, bool fused) {
   if (p.n_rows == 0 || p.nnz == 0) return;
+  if (fused) {
+    // 8 entries per lane are staged per panel: rows per workgroup sized so a
+    // panel's entries in a block fit them
+    const PanelSetDev S = panel_set_dev(h, p, panels);
+    const int want = fused_rows_for(h, p, panels, kWG * 8);
+    hip_ok(launch_spmv_block_fused(h->prec, S, want, nt, remap, kt, k, B, ldb, C, ldc, scale, s),
+           "block kernel launch");
+    return;
+  }
   if (panels > 1) {
     for (auto &q : build_panels(h, p, panels))
       run_block_part(h, *q, kt, nt, remap, 1, k, B, ldb, C, ldc, s, scale);
@@ -66,7 +75,7 @@ void block_product(spmv_handle_s *h, int k, const void *B, int64_t ldb, void *C,
                    hipStream_t s, double scale) {
   const spmv_plan_t c = block_plan(h, k);
   run_block_part(h, h->main, c.block_kt, c.nontemporal, c.xcd_remap, c.panels, k, B, ldb, C, ldc,
-                 s, scale);
+                 s, scale, c.kernel == SPMV_KERNEL_FUSED_PANELS);
 }
 
 }  // namespace rt

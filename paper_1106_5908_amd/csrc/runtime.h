@@ -190,6 +190,8 @@ struct Part {
   int64_t d_min = 0, d_max = 0;
   std::map<int, std::pair<DevBuf, int64_t>> tiles;  // tile_items -> (tile starts, count)
   std::map<int, std::pair<DevBuf, int64_t>> runs;   // tile_items -> (run table, staged tiles)
+  // (panel count, entry capacity) -> rows per workgroup of the fused-panel kernels
+  std::map<std::pair<int, int>, int> fused_rows;
 
   CsrDev dev() const {
     CsrDev d;
@@ -309,6 +311,13 @@ void prepare_part(spmv_handle_s *h, Part &p);
 bool part_prepared(const Part &p, int x_bytes);
 // C = C + A*B over one part with its plan, on s.
 void run_part(spmv_handle_s *h, Part &p, const void *B, void *C, hipStream_t s);
+// The part's K diagonal panels (the part itself for K = 1) as the fused-panel
+// kernels take them; builds the panels on first use.
+PanelSetDev panel_set_dev(spmv_handle_s *h, Part &p, int K);
+// Rows per workgroup of the fused-panel kernels: the largest R in
+// {512, 256, ..., 16} such that no panel holds more than `cap` entries in any
+// block of R rows (16 if none does); cached per (K, cap).  Needs the panels.
+int fused_rows_for(spmv_handle_s *h, Part &p, int K, int cap);
 
 // ---- split and panels (rt_split.cpp) -------------------------------------------------------
 
@@ -330,7 +339,7 @@ int default_kt(int k);
 // in turn when `panels` > 1.  `scale` is 1 or a power of two (exact).
 void run_block_part(spmv_handle_s *h, Part &p, int kt, int nt, int remap, int panels, int k,
                     const void *B, int64_t ldb, void *C, int64_t ldc, hipStream_t s,
-                    double scale = 1.0);
+                    double scale = 1.0, bool fused = false);
 // The plan block products with k columns use on this handle: chosen by
 // spmv_tune, else read from the cache, else the defaults.
 spmv_plan_t block_plan(spmv_handle_s *h, int k);

@@ -149,6 +149,36 @@ hipError_t panel_fill(int prec, const int32_t *row_ptr, const int32_t *col, cons
                       int64_t n_rows, int64_t dmin, int64_t span, int K, const int32_t *starts,
                       const PanelOut &out, hipStream_t s);
 
+// ---- diagonal panels in one launch (kernels.hip) ---------------------------------
+// The K diagonal panels of a part (each a CRS over all n_rows rows, see
+// panel_fill) handed to one launch: a workgroup takes rows [b*R, b*R + R) and
+// walks the K panels of those rows in turn, keeping the rows' sums in
+// registers, so C is read and written once per call instead of once per panel.
+struct PanelSetDev {
+  const int32_t *rp[PANEL_MAX];
+  const int32_t *col[PANEL_MAX];
+  const void *val[PANEL_MAX];
+  int K;
+  int64_t n_rows;
+};
+// Plain product over a panel set: R <= 512 rows per workgroup, tile_items
+// (4, 8, 16) entries per lane for the entries one panel holds in a row block
+// (blocks holding more are summed row by row from global memory).
+hipError_t launch_spmv_fused(int prec, const PanelSetDev &S, int R, int tile_items, int nontemporal,
+                             int xcd_remap, const void *x, void *y, hipStream_t s);
+// Block product C = C + scale*A*B over a panel set, 8 entries per lane
+// staged per panel.  A workgroup takes block_fused_rows(...) consecutive
+// rows: the largest supported count not above `want_rows` (at least the
+// rows one pass of its lane groups covers); the host sizes want_rows so a
+// panel's entries in a row block fit the 2048 staged (blocks holding more
+// are summed row by row from global memory).
+int block_fused_rows(int prec, int kt, int k, int64_t ldb, int64_t ldc, const void *B, const void *C,
+                     int want_rows);
+hipError_t launch_spmv_block_fused(int prec, const PanelSetDev &S, int want_rows, int nontemporal,
+                                   int xcd_remap, int kt, int k, const void *B, int64_t ldb, void *C,
+                                   int64_t ldc, double scale, hipStream_t s);
+
+
 // ---- send side of the exchange (exchange.hip) -----------------------------------
 // out[k] = B[idx[k]] for k < n, copying words of word_bytes (4 or 8) bytes.
 hipError_t launch_pack(int word_bytes, const void *B, const int32_t *idx, int64_t n, void *out,

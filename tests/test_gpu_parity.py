@@ -42,7 +42,10 @@ PLANS = ([dict(kernel=1, tile_items=e, nontemporal=nt, xcd_remap=rm)
           for e in (4, 8) for k in (2, 4, 8) for rm in (0, 1)] +
          [dict(kernel=1, tile_items=8, panels=4, tiles_per_group=4)] +
          [dict(kernel=2, lanes=l) for l in (2, 4, 8, 16, 32, 64)] +
-         [dict(kernel=4, tile_items=e, nontemporal=nt) for e in (8, 16) for nt in (0, 1)])
+         [dict(kernel=4, tile_items=e, nontemporal=nt) for e in (8, 16) for nt in (0, 1)] +
+         [dict(kernel=5, tile_items=e, panels=k, xcd_remap=rm)
+          for e in (4, 8, 16) for k in (1, 2, 4, 8) for rm in (0, 1)] +
+         [dict(kernel=5, tile_items=8, panels=4, nontemporal=0)])
 
 
 def _pid(p):
@@ -95,7 +98,9 @@ def _long_row_matrix(long_len, n_short=300, n_cols=20000, seed=3):
                           for t in (3, 16)] +
                          [dict(kernel=1, tile_items=8, panels=k) for k in (2, 8)] +
                          [dict(kernel=2, lanes=64)] +
-                         [dict(kernel=4, tile_items=e) for e in (8, 16)], ids=_pid)
+                         [dict(kernel=4, tile_items=e) for e in (8, 16)] +
+                         [dict(kernel=5, tile_items=e, panels=k) for e in (4, 16) for k in (1, 4)],
+                         ids=_pid)
 def test_long_rows(long_len, plan):
     A = _long_row_matrix(long_len)
     x = gen.uniform_vector(A.n_cols, gen.rng_for(10, 5))
@@ -129,6 +134,8 @@ def test_edge_shapes():
         ref, den = oracle_ref(A, x, c0)
         for k in (2, 8):
             assert_close(gpu_spmv(A, x, c0, plan=dict(panels=k)), ref, den, FP64_TOL, f"{m}x{n} panels")
+            assert_close(gpu_spmv(A, x, c0, plan=dict(kernel=5, panels=k)), ref, den, FP64_TOL,
+                         f"{m}x{n} fused panels")
     # 1-based input gives the same product
     A = gen.random_crs(2000, 2000, rng, max_len=20)
     x = gen.uniform_vector(2000, rng)
@@ -397,8 +404,10 @@ def test_split_run_matches_oracle(schedule):
 
 @pytest.mark.parametrize("plan", [None, dict(kernel=1, tile_items=8, panels=4),
                                   dict(kernel=2, lanes=8), dict(kernel=1, tile_items=16, tiles_per_group=4),
-                                  dict(kernel=4, tile_items=8)],
-                         ids=["default", "panels4", "vector8", "pipelined", "staged8"])
+                                  dict(kernel=4, tile_items=8), dict(kernel=5, tile_items=8, panels=2),
+                                  dict(kernel=5, tile_items=16, panels=1)],
+                         ids=["default", "panels4", "vector8", "pipelined", "staged8", "fused2",
+                              "fused1"])
 def test_local_part_never_reads_halo(plan):
     """The receive area B[h:] holds NaN and no halo is copied: rows without a
     halo entry are computed by the local part alone and must be finite and
@@ -442,6 +451,9 @@ def test_split_local_part_panels():
         spmv.spmv_set_plan(s, spmv.SPMV_PART_MAIN, panels=4)
         with pytest.raises(spmv.SpmvError) as ei:
             spmv.spmv_set_plan(s, spmv.SPMV_PART_NONLOCAL, panels=2)
+        assert ei.value.status == spmv.SPMV_ERR_UNSUPPORTED
+        with pytest.raises(spmv.SpmvError) as ei:
+            spmv.spmv_set_plan(s, spmv.SPMV_PART_NONLOCAL, kernel=5, panels=1)
         assert ei.value.status == spmv.SPMV_ERR_UNSUPPORTED
         B = to_dev(x, "f64")
         C = to_dev(np.zeros(A.n_rows), "f64")
@@ -633,6 +645,62 @@ def test_block_with_panels(k, panels):
         assert_close(got[:, t], ref[:, t], den, FP64_TOL, f"block k={k} panels={panels} col {t}")
     den = oracle.abs_spmv(A.row_ptr, A.col_idx, A.val, X[:, 0])
     assert_close(c1.cpu().numpy(), ref[:, 0], den, FP64_TOL, "single vector with panels")
+
+
+def _gpu_block_plan(A, X, plan, c0=None, prec="f64", ldb_pad=0, ldc_pad=0):
+    import torch
+
+    h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, prec=prec, flags=NOTUNE)
+    try:
+        spmv.spmv_set_plan(h, **plan)
+        bp = spmv.spmv_get_block_plan(h, X.shape[1])
+        assert all(bp[f] == v for f, v in plan.items()), (bp, plan)
+        k = X.shape[1]
+        dt = torch.float64 if spmv.VEC_DTYPE[prec] == "float64" else torch.float32
+        Bw = torch.zeros((A.n_cols, k + ldb_pad), dtype=dt, device="cuda")
+        Bw[:, :k] = torch.from_numpy(X).to(dt)
+        Cw = torch.zeros((A.n_rows, k + ldc_pad), dtype=dt, device="cuda")
+        if c0 is not None:
+            Cw[:, :k] = torch.from_numpy(c0).to(dt)
+        spmv.spmv_run_block(h, Bw[:, :k], Cw[:, :k])
+        torch.cuda.synchronize()
+        return Cw[:, :k].cpu().numpy().astype(np.float64), Cw[:, k:].cpu().numpy()
+    finally:
+        spmv.spmv_destroy(h)
+
+
+@pytest.mark.parametrize("panels", [1, 2, 4, 8])
+@pytest.mark.parametrize("kt", [4, 8, 16])
+@pytest.mark.parametrize("k", [1, 3, 4, 8, 16, 17])
+def test_block_fused_panels(k, kt, panels):
+    """The fused-panel block kernel (all panels of a row block in one
+    workgroup, C written once) against the oracle, with C0, padded leading
+    dimensions (odd k takes the one-column-per-lane layout)."""
+    A, _ = mats()["irregular"]
+    X = gen.block_rhs(A.n_cols, k, extra=11)
+    c0 = gen.block_rhs(A.n_rows, k, extra=12)
+    plan = dict(kernel=5, panels=panels, block_kt=kt, xcd_remap=panels % 2)
+    got, pad = _gpu_block_plan(A, X, plan, c0, ldb_pad=1 if k % 2 else 2, ldc_pad=3)
+    assert np.all(pad == 0)
+    ref = oracle.spmv_block(A.row_ptr, A.col_idx, A.val, X, c0)
+    for t in range(k):
+        den = oracle.abs_spmv(A.row_ptr, A.col_idx, A.val, X[:, t], c0[:, t])
+        assert_close(got[:, t], ref[:, t], den, FP64_TOL, f"fused block k={k} kt={kt} panels={panels} col {t}")
+
+
+@pytest.mark.parametrize("panels", [1, 4])
+@pytest.mark.parametrize("k", [3, 16])
+def test_block_fused_integer_exact_long_rows(k, panels):
+    """Rows far longer than a staged tile (the row-by-row path) and ordinary
+    ones, integer data: bit for bit against the oracle; F32 too."""
+    rng = gen.rng_for(17, 1)
+    A = _long_row_matrix(3000, n_short=2000, n_cols=5000)
+    A.val = np.round(A.val * 4)
+    X = rng.integers(-5, 6, size=(A.n_cols, k)).astype(np.float64)
+    want = oracle.spmv_block(A.row_ptr, A.col_idx, A.val, X)
+    for prec in ("f64", "f32"):
+        got, _ = _gpu_block_plan(A, X, dict(kernel=5, panels=panels, block_kt=8), prec=prec)
+        assert np.array_equal(got, want), prec
 
 
 def test_block_rejects_split_and_bad_k():
