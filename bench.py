@@ -489,6 +489,9 @@ def split_paths(A, x, steps, warmup):
 
     spmv.spmv_set_schedule(s, spmv.SPMV_SCHEDULE_SERIAL)
     tb = time_launches(mode_b, steps, warmup)
+    spmv.spmv_set_schedule(s, spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL)
+    tc1 = time_launches(mode_b, steps, warmup)
+    tk1 = time_launches(lambda: spmv.spmv_run(s, B, C), steps, warmup)  # nonlocal beside local, resident
     spmv.spmv_set_schedule(s, spmv.SPMV_SCHEDULE_OVERLAP)
     tc = time_launches(mode_b, steps, warmup)
     ta = time_launches(mode_a, steps, warmup)
@@ -500,11 +503,15 @@ def split_paths(A, x, steps, warmup):
         "a_blocking_copy_then_unsplit_ms": ta["p50_ms"],
         "b_split_serial_copy_ms": tb["p50_ms"],
         "c_split_overlap_copy_ms": tc["p50_ms"],
+        "c_nonlocal_beside_local_ms": tc1["p50_ms"],
         "split_kernels_only_ms": tk["p50_ms"],
+        "split_kernels_nonlocal_beside_local_ms": tk1["p50_ms"],
         "unsplit_kernel_only_ms": tu["p50_ms"],
         "c_gflops": flops / (tc["p50_ms"] * 1e6),
         "split_model_bytes": mb + split_extra_bytes(info["n_nonlocal_rows"]),
+        "split_model_penalty": split_extra_bytes(info["n_nonlocal_rows"]) / mb,
         "split_kernel_penalty": tk["p50_ms"] / tu["p50_ms"] - 1.0,
+        "split_kernel_penalty_nonlocal_beside_local": tk1["p50_ms"] / tu["p50_ms"] - 1.0,
         "overlap_speedup_vs_a": ta["p50_ms"] / tc["p50_ms"],
         "overlap_speedup_vs_b": tb["p50_ms"] / tc["p50_ms"],
         "plans": {"local": spmv.spmv_get_plan(s, spmv.SPMV_PART_MAIN),
@@ -513,7 +520,8 @@ def split_paths(A, x, steps, warmup):
     res.update(traffic_report(read_traffic(res["plans"], "irregular8M-split"),
                               res["split_model_bytes"], flops))
     log(f"split: (a) {ta['p50_ms']*1e3:.0f} us, (b) {tb['p50_ms']*1e3:.0f} us, "
-        f"(c) {tc['p50_ms']*1e3:.0f} us, kernels only {tk['p50_ms']*1e3:.0f} us, "
+        f"(c) {tc['p50_ms']*1e3:.0f} us (nonlocal beside local {tc1['p50_ms']*1e3:.0f} us), kernels only "
+        f"{tk['p50_ms']*1e3:.0f} us (nonlocal beside local {tk1['p50_ms']*1e3:.0f} us), "
         f"unsplit {tu['p50_ms']*1e3:.0f} us")
 
     # (d) / (e): the whole exchange cycle of task mode (Sect. 3.5): the send

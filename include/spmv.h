@@ -546,7 +546,15 @@ spmv_status_t spmv_probe_atomic(double *C, int64_t n, int32_t scattered, int32_t
 /* Schedule used by spmv_run (for measurement and for callers that need it).
  * Split handles:
  *   SPMV_SCHEDULE_OVERLAP       halo copy on the copy stream beside the local
- *                               kernel (default)
+ *                               kernel, then the nonlocal kernel on `stream`
+ *                               (default)
+ *   SPMV_SCHEDULE_OVERLAP_NONLOCAL  as OVERLAP, and the nonlocal kernel runs on
+ *                               the handle's nonlocal stream beside the local
+ *                               rows above the first row that has a nonlocal
+ *                               entry, as soon as the halo is in; the
+ *                               remaining local rows follow on `stream` (local
+ *                               plans of the stream or staged kernel; others
+ *                               run as OVERLAP)
  *   SPMV_SCHEDULE_SERIAL        halo copy, local and nonlocal kernels in order
  *                               on `stream` (split without asynchrony)
  * Batch handles:
@@ -559,6 +567,7 @@ spmv_status_t spmv_probe_atomic(double *C, int64_t n, int32_t scattered, int32_t
 #define SPMV_SCHEDULE_BATCH_GRAPH 0
 #define SPMV_SCHEDULE_BATCH_DIRECT 2
 #define SPMV_SCHEDULE_BATCH_FLAT 3
+#define SPMV_SCHEDULE_OVERLAP_NONLOCAL 4
 spmv_status_t spmv_set_schedule(spmv_handle_t h, int32_t schedule);
 
 #ifdef __cplusplus

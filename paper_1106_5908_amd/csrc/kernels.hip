@@ -844,8 +844,10 @@ __global__ __launch_bounds__(WG) void k_block_fused(PanelSetDev S, int64_t n_blo
   constexpr int G = KT / VW;
   constexpr int NG = WG / G;
   constexpr int R = NG * NR;
+  constexpr int RB = (R + 1 + WG - 1) / WG;  // row bounds per lane to stage
   __shared__ int32_t s_col[TILE];
   __shared__ X s_val[TILE];
+  __shared__ int32_t s_rp[R + 1];
   const X *__restrict__ B = static_cast<const X *>(Bv);
   X *__restrict__ C = static_cast<X *>(Cv);
   const int tid = threadIdx.x;
@@ -891,6 +893,8 @@ __global__ __launch_bounds__(WG) void k_block_fused(PanelSetDev S, int64_t n_blo
       continue;
     }
     {
+      // the block's entries of this panel and its row bounds, staged in LDS
+      // (rows past the block's end take its last bound)
       const int last = nnz - 1;
       int cc[E];
       V vv[E];
@@ -900,18 +904,24 @@ __global__ __launch_bounds__(WG) void k_block_fused(PanelSetDev S, int64_t n_blo
         cc[e] = ld<int32_t, NT>(col + pa + q);
         vv[e] = ld<V, NT>(val + pa + q);
       }
+      int rb[RB];
+#pragma unroll
+      for (int q = 0; q < RB; ++q) rb[q] = rp[r0 + min(q * WG + tid, nrows)];
 #pragma unroll
       for (int e = 0; e < E; ++e) {
         s_col[e * WG + tid] = cc[e];
         s_val[e * WG + tid] = widen<X>(vv[e]) * scale;
       }
+#pragma unroll
+      for (int q = 0; q < RB; ++q)
+        if (q * WG + tid <= R) s_rp[q * WG + tid] = rb[q] - pa;
     }
     __syncthreads();
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
       const int rr = g + i * NG;
       if (rr >= nrows) continue;
-      const int a = rp[r0 + rr] - pa, e = rp[r0 + rr + 1] - pa;
+      const int a = s_rp[rr], e = s_rp[rr + 1];
       cnt[i] += e - a;
       if (!active) continue;
       int j = a;

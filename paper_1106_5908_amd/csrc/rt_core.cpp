@@ -357,6 +357,9 @@ spmv_handle_s::spmv_handle_s() : magic(spmv::rt::kMagic) {}
 spmv_handle_s::~spmv_handle_s() {
   if (copy_stream) (void)hipStreamSynchronize(copy_stream);
   if (send_stream) (void)hipStreamSynchronize(send_stream);
+  if (nl_stream) (void)hipStreamSynchronize(nl_stream);
+  if (ev_nl_done) (void)hipEventDestroy(ev_nl_done);
+  if (nl_stream) (void)hipStreamDestroy(nl_stream);
   if (ev_sent) (void)hipEventDestroy(ev_sent);
   for (hipEvent_t &e : tev)
     if (e) (void)hipEventDestroy(e);
@@ -484,7 +487,8 @@ extern "C" spmv_status_t spmv_set_schedule(spmv_handle_t h_, int32_t schedule) {
   return guarded([&] {
     spmv_handle_s *h = live(h_);
     const bool ok_split = h->kind == SPMV_KIND_SPLIT &&
-                          (schedule == SPMV_SCHEDULE_OVERLAP || schedule == SPMV_SCHEDULE_SERIAL);
+                          (schedule == SPMV_SCHEDULE_OVERLAP || schedule == SPMV_SCHEDULE_SERIAL ||
+                           schedule == SPMV_SCHEDULE_OVERLAP_NONLOCAL);
     const bool ok_batch = h->kind == SPMV_KIND_BATCH &&
                           (schedule == SPMV_SCHEDULE_BATCH_GRAPH ||
                            schedule == SPMV_SCHEDULE_BATCH_DIRECT ||

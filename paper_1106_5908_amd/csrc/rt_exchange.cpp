@@ -151,12 +151,7 @@ extern "C" spmv_status_t spmv_run_exchange(spmv_handle_t h_, const void *B, void
                "halo copy");
         mark(h, T_COPY + 1, s);
       }
-      mark(h, T_LOCAL, s);
-      run_part(h, h->main, B, C, s);
-      mark(h, T_LOCAL + 1, s);
-      mark(h, T_NONLOCAL, s);
-      run_part(h, h->nl, B, C, s);
-      mark(h, T_NONLOCAL + 1, s);
+      split_compute(h, B, C, nullptr, false, s);
       return;
     }
     hip_ok(hipEventRecord(h->ev_start, s), "event record");
@@ -180,13 +175,8 @@ extern "C" spmv_status_t spmv_run_exchange(spmv_handle_t h_, const void *B, void
       mark(h, T_COPY + 1, h->copy_stream);
       hip_ok(hipEventRecord(h->ev_copied, h->copy_stream), "event record");
     }
-    mark(h, T_LOCAL, s);
-    run_part(h, h->main, B, C, s);
-    mark(h, T_LOCAL + 1, s);
-    if (copy) hip_ok(hipStreamWaitEvent(s, h->ev_copied, 0), "stream wait");
-    mark(h, T_NONLOCAL, s);
-    run_part(h, h->nl, B, C, s);
-    mark(h, T_NONLOCAL + 1, s);
+    split_compute(h, B, C, copy ? h->ev_copied : h->ev_start,
+                  h->schedule == SPMV_SCHEDULE_OVERLAP_NONLOCAL, s);
     if (ns > 0) hip_ok(hipStreamWaitEvent(s, h->ev_sent, 0), "stream wait");
   });
 }

@@ -183,10 +183,21 @@ const char *prec_name(int p) {
 
 // ---- one CRS part on the device -------------------------------------------------
 
+std::vector<int32_t> Part::host_tiles(int items) const {
+  const int64_t cap = int64_t(kWG) * items;
+  if (cut_row <= 0 || cut_row >= n_rows) return make_tiles(h_row_ptr.data(), n_rows, cap);
+  std::vector<int32_t> t = make_tiles(h_row_ptr.data(), cut_row, cap);
+  const std::vector<int32_t> t2 = make_tiles(h_row_ptr.data() + cut_row, n_rows - cut_row, cap);
+  for (size_t i = 1; i < t2.size(); ++i) t.push_back(int32_t(t2[i] + cut_row));
+  return t;
+}
+
 std::pair<const TileRP *, int64_t> Part::tiles_for(int items) {
   auto it = tiles.find(items);
   if (it == tiles.end()) {
-    const std::vector<int32_t> t = make_tiles(h_row_ptr.data(), n_rows, int64_t(kWG) * items);
+    const std::vector<int32_t> t = host_tiles(items);
+    if (cut_row > 0 && cut_row < n_rows)
+      cut_tile[items] = int64_t(std::lower_bound(t.begin(), t.end(), int32_t(cut_row)) - t.begin());
     std::vector<TileRP> tr(t.size());
     for (size_t i = 0; i < t.size(); ++i) tr[i] = TileRP{t[i], h_row_ptr[size_t(t[i])]};
     DevBuf d;
@@ -198,7 +209,7 @@ std::pair<const TileRP *, int64_t> Part::tiles_for(int items) {
 const int32_t *Part::runs_for(int items, int x_bytes) {
   auto it = runs.find(items);
   if (it == runs.end()) {
-    const std::vector<int32_t> t = make_tiles(h_row_ptr.data(), n_rows, int64_t(kWG) * items);
+    const std::vector<int32_t> t = host_tiles(items);
     std::vector<int32_t> hc(static_cast<size_t>(nnz));
     if (nnz > 0)
       hip_ok(hipMemcpy(hc.data(), col.p, size_t(nnz) * 4, hipMemcpyDeviceToHost), "col readback");
@@ -461,6 +472,37 @@ int fused_rows_for(spmv_handle_s *h, Part &p, int K, int cap) {
   }
   p.fused_rows.emplace(key, R);
   return R;
+}
+
+bool part_runs_halves(const Part &p) {
+  return p.cut_row > 0 && p.cut_row < p.n_rows &&
+         (p.plan.kernel == SPMV_KERNEL_STREAM || p.plan.kernel == SPMV_KERNEL_STAGED);
+}
+
+void run_part_half(spmv_handle_s *h, Part &p, int half, const void *B, void *C, hipStream_t s) {
+  if (p.n_rows == 0 || p.nnz == 0) return;
+  const bool staged = p.plan.kernel == SPMV_KERNEL_STAGED;
+  const int xb = vec_bytes(h->prec);
+  const int items = p.plan.tile_items;
+  spmv_plan_t sub = p.plan;
+  sub.panels = 1;
+  const PlanDev pl = to_dev(sub);
+  auto one = [&](Part &q) {
+    if (q.nnz == 0) return;
+    auto t = q.tiles_for(items);
+    const int32_t *r = staged ? q.runs_for(items, xb) : nullptr;
+    const int64_t tc = q.cut_tile.at(items);
+    const int64_t t0 = half == 0 ? 0 : tc, t1 = half == 0 ? tc : t.second;
+    if (t1 <= t0) return;
+    hip_ok(launch_spmv(h->prec, q.dev(), pl, t.first + t0, r ? r + t0 * RUN_WORDS : nullptr,
+                       t1 - t0, B, C, s),
+           "kernel launch");
+  };
+  if (p.plan.panels > 1) {
+    for (auto &q : build_panels(h, p, p.plan.panels)) one(*q);
+  } else {
+    one(p);
+  }
 }
 
 void run_part(spmv_handle_s *h, Part &p, const void *B, void *C, hipStream_t s) {

@@ -78,6 +78,32 @@ void block_product(spmv_handle_s *h, int k, const void *B, int64_t ldb, void *C,
                  s, scale, c.kernel == SPMV_KERNEL_FUSED_PANELS);
 }
 
+void split_compute(spmv_handle_s *h, const void *B, void *C, hipEvent_t nl_after, bool beside,
+                   hipStream_t s) {
+  if (beside && part_runs_halves(h->main) && h->nl.n_rows > 0 && h->nl.nnz > 0) {
+    // rows above the first nonlocal row on s, the nonlocal part beside them
+    // on its own stream once the halo is in, then the remaining local rows
+    mark(h, T_LOCAL, s);
+    run_part_half(h, h->main, 0, B, C, s);
+    hip_ok(hipStreamWaitEvent(h->nl_stream, nl_after, 0), "stream wait");
+    mark(h, T_NONLOCAL, h->nl_stream);
+    run_part(h, h->nl, B, C, h->nl_stream);
+    mark(h, T_NONLOCAL + 1, h->nl_stream);
+    hip_ok(hipEventRecord(h->ev_nl_done, h->nl_stream), "event record");
+    hip_ok(hipStreamWaitEvent(s, h->ev_nl_done, 0), "stream wait");
+    run_part_half(h, h->main, 1, B, C, s);
+    mark(h, T_LOCAL + 1, s);
+    return;
+  }
+  mark(h, T_LOCAL, s);
+  run_part(h, h->main, B, C, s);
+  mark(h, T_LOCAL + 1, s);
+  if (nl_after && nl_after != h->ev_start) hip_ok(hipStreamWaitEvent(s, nl_after, 0), "stream wait");
+  mark(h, T_NONLOCAL, s);
+  run_part(h, h->nl, B, C, s);
+  mark(h, T_NONLOCAL + 1, s);
+}
+
 }  // namespace rt
 }  // namespace spmv
 
@@ -110,35 +136,28 @@ extern "C" spmv_status_t spmv_run(spmv_handle_t h_, const void *B, void *C,
     const bool copy = B_halo_host && n_halo > 0;
     if (copy) require_pinned(h, B_halo_host, "B_halo_host");
     begin_timed_call(h, s);
-    if (copy && h->schedule == SPMV_SCHEDULE_OVERLAP) {
-      hip_ok(hipEventRecord(h->ev_start, s), "event record");
-      hip_ok(hipStreamWaitEvent(h->copy_stream, h->ev_start, 0), "stream wait");
-      mark(h, T_COPY, h->copy_stream);
-      hip_ok(hipMemcpyAsync(recv, B_halo_host, size_t(n_halo) * vb, hipMemcpyHostToDevice,
-                            h->copy_stream),
-             "halo copy");
-      mark(h, T_COPY + 1, h->copy_stream);
-      hip_ok(hipEventRecord(h->ev_copied, h->copy_stream), "event record");
-      mark(h, T_LOCAL, s);
-      run_part(h, h->main, B, C, s);
-      mark(h, T_LOCAL + 1, s);
-      hip_ok(hipStreamWaitEvent(s, h->ev_copied, 0), "stream wait");
-      mark(h, T_NONLOCAL, s);
-      run_part(h, h->nl, B, C, s);
-      mark(h, T_NONLOCAL + 1, s);
-    } else {
+    if (h->schedule == SPMV_SCHEDULE_SERIAL) {
       if (copy) {
         mark(h, T_COPY, s);
         hip_ok(hipMemcpyAsync(recv, B_halo_host, size_t(n_halo) * vb, hipMemcpyHostToDevice, s),
                "halo copy");
         mark(h, T_COPY + 1, s);
       }
-      mark(h, T_LOCAL, s);
-      run_part(h, h->main, B, C, s);
-      mark(h, T_LOCAL + 1, s);
-      mark(h, T_NONLOCAL, s);
-      run_part(h, h->nl, B, C, s);
-      mark(h, T_NONLOCAL + 1, s);
+      split_compute(h, B, C, nullptr, false, s);
+    } else {
+      hip_ok(hipEventRecord(h->ev_start, s), "event record");
+      hipEvent_t after = h->ev_start;
+      if (copy) {
+        hip_ok(hipStreamWaitEvent(h->copy_stream, h->ev_start, 0), "stream wait");
+        mark(h, T_COPY, h->copy_stream);
+        hip_ok(hipMemcpyAsync(recv, B_halo_host, size_t(n_halo) * vb, hipMemcpyHostToDevice,
+                              h->copy_stream),
+               "halo copy");
+        mark(h, T_COPY + 1, h->copy_stream);
+        hip_ok(hipEventRecord(h->ev_copied, h->copy_stream), "event record");
+        after = h->ev_copied;
+      }
+      split_compute(h, B, C, after, h->schedule == SPMV_SCHEDULE_OVERLAP_NONLOCAL, s);
     }
     h->tran[0] = copy;
     h->tran[1] = h->tran[2] = true;

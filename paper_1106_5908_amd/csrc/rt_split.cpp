@@ -47,6 +47,7 @@ std::vector<std::unique_ptr<Part>> &build_panels(spmv_handle_s *h, Part &p, int 
   for (int k = 0; k < K; ++k) {
     std::unique_ptr<Part> q(new Part());
     q->n_rows = n;
+    q->cut_row = p.cut_row;
     q->h_row_ptr.resize(size_t(m));
     hip_ok(hipMemcpyAsync(q->h_row_ptr.data(), counts.as<int32_t>() + int64_t(k) * m, size_t(m) * 4,
                           hipMemcpyDeviceToHost, s),
@@ -160,6 +161,14 @@ extern "C" spmv_status_t spmv_split_local_nonlocal(spmv_handle_t a_, int64_t hal
     hip_ok(hipStreamSynchronize(s), "split");
     L.stats = row_stats(L.h_row_ptr.data(), n);
     N.stats = row_stats(N.h_row_ptr.data(), R);
+    // The local part is tiled in two halves, cut at the first row that has a
+    // nonlocal entry, so that under SPMV_SCHEDULE_OVERLAP_NONLOCAL the rows
+    // above it can run beside the nonlocal part.
+    if (R > 0) {
+      int32_t first = 0;
+      hip_ok(hipMemcpy(&first, N.row_ids.p, 4, hipMemcpyDeviceToHost), "nonlocal rows readback");
+      L.cut_row = first;
+    }
     choose_plan(h.get(), L, "local");
     choose_plan(h.get(), N, "nonlocal");
     hip_ok(hipStreamCreateWithFlags(&h->copy_stream, hipStreamNonBlocking), "copy stream");
@@ -167,6 +176,8 @@ extern "C" spmv_status_t spmv_split_local_nonlocal(spmv_handle_t a_, int64_t hal
     hip_ok(hipEventCreateWithFlags(&h->ev_copied, hipEventDisableTiming), "event");
     hip_ok(hipStreamCreateWithFlags(&h->send_stream, hipStreamNonBlocking), "send stream");
     hip_ok(hipEventCreateWithFlags(&h->ev_sent, hipEventDisableTiming), "event");
+    hip_ok(hipStreamCreateWithFlags(&h->nl_stream, hipStreamNonBlocking), "nonlocal stream");
+    hip_ok(hipEventCreateWithFlags(&h->ev_nl_done, hipEventDisableTiming), "event");
     register_handle(h.get());
     *out_split = h.release();
   });

@@ -192,6 +192,11 @@ struct Part {
   std::map<int, std::pair<DevBuf, int64_t>> runs;   // tile_items -> (run table, staged tiles)
   // (panel count, entry capacity) -> rows per workgroup of the fused-panel kernels
   std::map<std::pair<int, int>, int> fused_rows;
+  // Rows [0, cut_row) and [cut_row, n_rows) are tiled separately, so each
+  // half can be launched on its own (the local part of a split handle, cut at
+  // its first row with a nonlocal entry); -1: no cut.
+  int64_t cut_row = -1;
+  std::map<int, int64_t> cut_tile;  // tile_items -> first tile of the second half
 
   CsrDev dev() const {
     CsrDev d;
@@ -204,6 +209,8 @@ struct Part {
   }
   // Tile starts for `items` entries per lane (built and uploaded on first use).
   std::pair<const TileRP *, int64_t> tiles_for(int items);
+  // The tiles of the part's own rows as make_tiles cuts them, honouring cut_row.
+  std::vector<int32_t> host_tiles(int items) const;
   // Run table of the staged kernel for tiles of `items` (built on first use
   // from a copy of col_idx read back from the device; synchronous).
   const int32_t *runs_for(int items, int x_bytes);
@@ -236,6 +243,10 @@ struct spmv_handle_s {
   int64_t n_send = 0;
   hipStream_t send_stream = nullptr;
   hipEvent_t ev_sent = nullptr;
+  // split: the nonlocal part's own stream (it runs beside the local part's
+  // rows that have no nonlocal entry) and its completion event
+  hipStream_t nl_stream = nullptr;
+  hipEvent_t ev_nl_done = nullptr;
   // batch
   int32_t count = 0;
   std::vector<int64_t> m_rows, m_cols;
@@ -311,6 +322,12 @@ void prepare_part(spmv_handle_s *h, Part &p);
 bool part_prepared(const Part &p, int x_bytes);
 // C = C + A*B over one part with its plan, on s.
 void run_part(spmv_handle_s *h, Part &p, const void *B, void *C, hipStream_t s);
+// Whether the part's plan can run the two halves of a cut part separately
+// (tile-based kernels: stream and staged, with or without panels).
+bool part_runs_halves(const Part &p);
+// C = C + A*B over rows [0, cut_row) (half 0) or [cut_row, n_rows) (half 1)
+// of a cut part whose plan part_runs_halves allows.
+void run_part_half(spmv_handle_s *h, Part &p, int half, const void *B, void *C, hipStream_t s);
 // The part's K diagonal panels (the part itself for K = 1) as the fused-panel
 // kernels take them; builds the panels on first use.
 PanelSetDev panel_set_dev(spmv_handle_s *h, Part &p, int K);
@@ -359,6 +376,16 @@ void begin_timed_call(spmv_handle_s *h, hipStream_t s);
 // pageable memory (a pageable copy is staged by the runtime and does not
 // proceed beside the kernels; nonblocking is not asynchronous, Sect. 3.1).
 void require_pinned(const spmv_handle_s *h, const void *p, const char *what);
+// The local and nonlocal parts of a split handle on stream s.  With `beside`
+// and a local plan that can run its halves (part_runs_halves), the local
+// rows above the first nonlocal row run on s while the nonlocal part runs on
+// the handle's nonlocal stream after `nl_after` (the halo copy's event, or
+// the call's start event), and the remaining local rows follow on s once
+// the nonlocal part is done; otherwise the local part, then (after
+// `nl_after` unless it is null or the start event) the nonlocal part, in
+// order on s.  Either way every row gets its local and nonlocal sums.
+void split_compute(spmv_handle_s *h, const void *B, void *C, hipEvent_t nl_after, bool beside,
+                   hipStream_t s);
 
 }  // namespace rt
 }  // namespace spmv

@@ -14,7 +14,7 @@ from workloads import gen
 pytestmark = pytest.mark.gpu
 
 NOTUNE = spmv.SPMV_FLAG_NO_TUNE_CACHE
-MODES = [spmv.SPMV_SCHEDULE_OVERLAP, spmv.SPMV_SCHEDULE_SERIAL]
+MODES = [spmv.SPMV_SCHEDULE_OVERLAP, spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL, spmv.SPMV_SCHEDULE_SERIAL]
 
 
 def _irregular():
@@ -277,7 +277,12 @@ def test_phase_timing():
                     if ph:
                         assert -eps <= ph[0] <= ph[1] + eps
                 assert t["copy"][1] <= t["nonlocal"][0] + eps
-                assert t["local"][1] <= t["nonlocal"][0] + eps
+                if schedule == spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL:
+                    # the nonlocal part runs inside the local part's span, beside its upper rows
+                    assert t["local"][0] <= t["nonlocal"][0] + eps
+                    assert t["nonlocal"][1] <= t["local"][1] + eps
+                else:
+                    assert t["local"][1] <= t["nonlocal"][0] + eps
                 if schedule == spmv.SPMV_SCHEDULE_SERIAL:
                     assert t["copy"][1] <= t["local"][0] + eps
                     if exchange:

@@ -389,7 +389,8 @@ def _run_split(A, x, h_begin, schedule, prec="f64", halo="pinned", c0=None, flag
         spmv.spmv_destroy(a)
 
 
-@pytest.mark.parametrize("schedule", [spmv.SPMV_SCHEDULE_OVERLAP, spmv.SPMV_SCHEDULE_SERIAL])
+@pytest.mark.parametrize("schedule", [spmv.SPMV_SCHEDULE_OVERLAP, spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL,
+                                      spmv.SPMV_SCHEDULE_SERIAL])
 def test_split_run_matches_oracle(schedule):
     A, x = mats()["irregular"]
     h_begin = gen.halo_begin(A.n_cols)
@@ -493,9 +494,59 @@ def test_split_integer_bit_exact_and_edges():
     x = gen.integer_vector(A.n_cols, rng)
     exact = oracle.spmv(A.row_ptr, A.col_idx, A.val, x)
     for h_begin in (0, 1, 18800, 19999, 20000):
-        for sch in (spmv.SPMV_SCHEDULE_OVERLAP, spmv.SPMV_SCHEDULE_SERIAL):
+        for sch in (spmv.SPMV_SCHEDULE_OVERLAP, spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL,
+                    spmv.SPMV_SCHEDULE_SERIAL):
             got, _ = _run_split(A, x, h_begin, sch)
             assert np.array_equal(got, exact), (h_begin, sch)
+
+
+@pytest.mark.parametrize("plan", [dict(kernel=1, tile_items=8), dict(kernel=1, tile_items=8, panels=4),
+                                  dict(kernel=1, tile_items=4, tiles_per_group=4),
+                                  dict(kernel=4, tile_items=8), dict(kernel=2, lanes=8),
+                                  dict(kernel=5, tile_items=8, panels=2)],
+                         ids=["stream", "panels4", "pipelined", "staged", "vector", "fused"])
+def test_split_local_halves_beside_nonlocal(plan):
+    """The banded irregular matrix's nonlocal rows are a tail of the rows, so
+    the local part is tiled in two halves cut at the first nonlocal row: the
+    upper half runs while the nonlocal part runs on its own stream.  Its tile
+    table has a tile starting exactly at that row, and on integer data every
+    schedule gives the oracle's product bit for bit (with C0); plans that
+    cannot run halves (vector, fused) take the ordered path."""
+    import torch
+
+    A, _ = mats()["irregular"]
+    rng = gen.rng_for(15, 1)
+    A = gen.CRS(A.n_rows, A.n_cols, A.row_ptr, A.col_idx,
+                rng.integers(-9, 10, size=A.nnz).astype(np.float64))
+    x = gen.integer_vector(A.n_cols, rng)
+    c0 = gen.integer_vector(A.n_rows, rng)
+    h_begin = gen.halo_begin(A.n_cols)
+    exact = oracle.spmv(A.row_ptr, A.col_idx, A.val, x, c0)
+    parts = oracle.split(A.row_ptr, A.col_idx, A.val, h_begin)
+    first_nl = int(parts["nl_rows"][0])
+    assert 0 < first_nl < A.n_rows
+    a, s = _split_handles(A, h_begin)
+    try:
+        spmv.spmv_set_plan(s, spmv.SPMV_PART_MAIN, **plan)
+        if plan["kernel"] in (1, 4) and plan.get("panels", 1) == 1:
+            tiles = spmv.spmv_export(s, spmv.SPMV_ARR_TILES).view(np.int32).reshape(-1, 2)
+            assert first_nl in set(tiles[:, 0].tolist())
+        halo = torch.from_numpy(np.ascontiguousarray(x[h_begin:])).pin_memory()
+        for sch in (spmv.SPMV_SCHEDULE_OVERLAP, spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL,
+                    spmv.SPMV_SCHEDULE_SERIAL):
+            spmv.spmv_set_schedule(s, sch)
+            for with_copy in (True, False):
+                Bh = x.copy()
+                if with_copy:
+                    Bh[h_begin:] = np.nan
+                B = to_dev(Bh, "f64")
+                C = to_dev(c0, "f64")
+                spmv.spmv_run(s, B, C, halo if with_copy else None)
+                torch.cuda.synchronize()
+                assert np.array_equal(C.cpu().numpy(), exact), (sch, with_copy)
+    finally:
+        spmv.spmv_destroy(s)
+        spmv.spmv_destroy(a)
 
 
 def test_split_resident_halo_and_pageable_rejection():
