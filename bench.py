@@ -1131,6 +1131,7 @@ def summarize_trace(trace_dir, out_path, command):
              "# per call: copy durations, local-part span, the share of each copy that ran while "
              "local kernels ran, and the gap from the halo copy's end to the first nonlocal kernel"]
     result = {}
+    per_call = {}
     for name, evs in series.items():
         calls, cur, last_end = [], [], None
         for e in evs:
@@ -1165,6 +1166,12 @@ def summarize_trace(trace_dir, out_path, command):
             gap = (first_nl - max(e[3] for e in h2d)) if first_nl is not None else None
             span = max(e[3] for e in c) - min(e[2] for e in c)
             rows.append((th, oh, td, od, l1 - l0, gap, span))
+            t0c = min(e[2] for e in c)
+            nl_end = max((e[3] for e in nl), default=None)
+            per_call.setdefault(name, []).append(
+                (min(e[2] for e in h2d) - t0c, max(e[3] for e in h2d) - t0c, l0 - t0c, l1 - t0c,
+                 None if first_nl is None else first_nl - t0c,
+                 None if nl_end is None else nl_end - t0c, oh))
         if not rows:
             continue
         a = np.array([[r[0], r[1], r[2], r[3], r[4], r[6]] for r in rows], dtype=float)
@@ -1181,6 +1188,12 @@ def summarize_trace(trace_dir, out_path, command):
         lines.append(f"  local part {med[4] / 1e3:8.1f} us, whole call {med[5] / 1e3:8.1f} us")
         if gaps:
             lines.append(f"  first nonlocal kernel starts {min(gaps) / 1e3:.1f} us (min) after the halo copy ends")
+        lines.append("  per call, us from the call's first event: halo copy [start, end], local kernels "
+                     "[start, end], nonlocal kernels [start, end], share of the copy under the local kernels")
+        for i, (c0, c1, l0_, l1_, n0, n1, o) in enumerate(per_call.get(name, [])):
+            nl_txt = "-" if n0 is None else f"[{n0 / 1e3:7.1f}, {n1 / 1e3:7.1f}]"
+            lines.append(f"  {i:3d}  copy [{c0 / 1e3:7.1f}, {c1 / 1e3:7.1f}]  local [{l0_ / 1e3:7.1f}, "
+                         f"{l1_ / 1e3:7.1f}]  nonlocal {nl_txt}  {o * 100:5.1f}%")
     with open(out_path, "w") as f:
         f.write("\n".join(lines) + "\n")
     print("\n".join(lines))

@@ -915,7 +915,7 @@ def test_set_plan_validation():
     A, _ = mats()["irregular"]
     h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, flags=NOTUNE)
     try:
-        for bad in (dict(kernel=5), dict(kernel=0), dict(kernel=3), dict(kernel=4, tile_items=4),
+        for bad in (dict(kernel=6), dict(kernel=0), dict(kernel=3), dict(kernel=4, tile_items=4),
                     dict(tile_items=5), dict(lanes=3), dict(block_kt=2),
                     dict(tiles_per_group=0), dict(tiles_per_group=65), dict(panels=3)):
             with pytest.raises(spmv.SpmvError):
