@@ -1084,6 +1084,77 @@ def trace_pass(steps: int):
                       "send_bytes": 8 * n_send, "plans": plans}), flush=True)
 
 
+def phases_pass(steps: int, out_path: str, command: str):
+    """Per-call phase events of the split product of the irregular 8M matrix
+    (the library's own hipEvents on the GPU clock, spmv_phase_times): `steps`
+    calls of schedule (c) (halo copy overlapped with the local part) and of
+    the exchange cycle (d), each call alone; writes one line per call with
+    the halo copy, local, nonlocal and send intervals (us from the call's
+    start) and checks the overlap: the copy inside the local part's interval,
+    the nonlocal part after both."""
+    import torch
+
+    from paper_1106_5908_amd import spmv
+    from workloads import gen
+
+    A, x = gen.workload_c3()
+    hb = gen.halo_begin(A.n_cols)
+    a = make_handle(A, "f64", tune=False)
+    s = spmv.spmv_split_local_nonlocal(a, hb)
+    spmv.spmv_tune(s, 1)
+    n_send = spmv.spmv_send_list_symmetric(s)
+    halo = torch.from_numpy(np.ascontiguousarray(x[hb:])).pin_memory()
+    send = torch.empty(n_send, dtype=torch.float64).pin_memory()
+    B = dev_vec(x, "f64")
+    C = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
+    lines = ["# Split product of the irregular 8M matrix, one line per call: phase intervals from the "
+             "library's events (spmv_set_phase_timing / spmv_phase_times), us from the call's start",
+             f"# command: {command}",
+             f"# plans: local {spmv.spmv_get_plan(s, spmv.SPMV_PART_MAIN)}, "
+             f"nonlocal {spmv.spmv_get_plan(s, spmv.SPMV_PART_NONLOCAL)}; halo {8 * (A.n_cols - hb)} B, "
+             f"send buffer {8 * n_send} B"]
+    summary = {}
+    try:
+        spmv.spmv_set_phase_timing(s, True)
+        for name, call in (("c_split_overlap", lambda: spmv.spmv_run(s, B, C, halo)),
+                           ("d_exchange_overlap", lambda: spmv.spmv_run_exchange(s, B, C, halo, send))):
+            for _ in range(3):
+                call()
+            torch.cuda.synchronize()
+            lines.append(f"{name}:")
+            inside = after = 0
+            for i in range(steps):
+                call()
+                torch.cuda.synchronize()
+                t = spmv.spmv_phase_times(s)
+                us = {k: (v[0] * 1e3, v[1] * 1e3) for k, v in t.items() if v}
+                c, lo, nl = us["copy"], us["local"], us["nonlocal"]
+                ok_in = c[0] >= lo[0] - 1.0 and c[1] <= lo[1] + 1.0
+                ok_after = nl[0] >= max(c[1], lo[1]) - 1.0
+                inside += ok_in
+                after += ok_after
+                snd = us.get("send")
+                lines.append(f"  {i:3d}  copy [{c[0]:7.1f}, {c[1]:7.1f}]  local [{lo[0]:7.1f}, {lo[1]:7.1f}]  "
+                             f"nonlocal [{nl[0]:7.1f}, {nl[1]:7.1f}]" +
+                             (f"  send [{snd[0]:7.1f}, {snd[1]:7.1f}]" if snd else "") +
+                             f"  copy inside local: {'yes' if ok_in else 'no'}, nonlocal after both: "
+                             f"{'yes' if ok_after else 'no'}")
+            lines.append(f"  {inside} of {steps} calls with the copy inside the local part, {after} of "
+                         f"{steps} with the nonlocal part after both")
+            summary[name] = {"calls": steps, "copy_inside_local": inside, "nonlocal_after_both": after}
+        spmv.spmv_set_phase_timing(s, False)
+    finally:
+        torch.cuda.synchronize()
+        spmv.spmv_destroy(s)
+        spmv.spmv_destroy(a)
+        del halo, send, B, C
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    with open(out_path, "w") as f:
+        f.write("\n".join(lines) + "\n")
+    print(json.dumps({"phases_pass": "done", **summary}), flush=True)
+
+
 def _template_args(name: str):
     i = name.find("<")
     if i < 0:
@@ -1359,6 +1430,7 @@ def main():
     ap.add_argument("--pmc-workload", default="27pt160", choices=sorted(PMC_WORKLOADS))
     ap.add_argument("--summarize-stats", nargs=3, metavar=("STATS_CSV", "OUT", "COMMAND"))
     ap.add_argument("--trace-pass", action="store_true")
+    ap.add_argument("--phases-pass", nargs=2, metavar=("OUT", "COMMAND"))
     ap.add_argument("--summarize-counters", nargs="+", metavar="OUT COMMAND DIR")
     ap.add_argument("--summarize-trace", nargs=3, metavar=("TRACE_DIR", "OUT", "COMMAND"))
     args = ap.parse_args()
@@ -1394,6 +1466,9 @@ def main():
         return 0
     if args.trace_pass:
         trace_pass(args.steps)
+        return 0
+    if args.phases_pass:
+        phases_pass(args.steps, *args.phases_pass)
         return 0
 
     t_start = time.time()
