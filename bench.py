@@ -1090,8 +1090,9 @@ def phases_pass(steps: int, out_path: str, command: str):
     calls of schedule (c) (halo copy overlapped with the local part) and of
     the exchange cycle (d), each call alone; writes one line per call with
     the halo copy, local, nonlocal and send intervals (us from the call's
-    start) and checks the overlap: the copy inside the local part's interval,
-    the nonlocal part after both."""
+    start), the share of the copy (and of the send side) that ran while the
+    local part ran, and whether the copy ended before the local part and the
+    nonlocal part started after both."""
     import torch
 
     from paper_1106_5908_amd import spmv
@@ -1122,26 +1123,36 @@ def phases_pass(steps: int, out_path: str, command: str):
                 call()
             torch.cuda.synchronize()
             lines.append(f"{name}:")
-            inside = after = 0
+            def share(a, lo):
+                return max(0.0, min(a[1], lo[1]) - max(a[0], lo[0])) / max(a[1] - a[0], 1e-9)
+
+            ends_first = after = 0
+            shares, send_shares = [], []
             for i in range(steps):
                 call()
                 torch.cuda.synchronize()
                 t = spmv.spmv_phase_times(s)
                 us = {k: (v[0] * 1e3, v[1] * 1e3) for k, v in t.items() if v}
                 c, lo, nl = us["copy"], us["local"], us["nonlocal"]
-                ok_in = c[0] >= lo[0] - 1.0 and c[1] <= lo[1] + 1.0
-                ok_after = nl[0] >= max(c[1], lo[1]) - 1.0
-                inside += ok_in
+                ok_end = c[1] <= lo[1]
+                ok_after = nl[0] >= max(c[1], lo[1])
+                ends_first += ok_end
                 after += ok_after
+                shares.append(share(c, lo))
                 snd = us.get("send")
+                if snd:
+                    send_shares.append(share(snd, lo))
                 lines.append(f"  {i:3d}  copy [{c[0]:7.1f}, {c[1]:7.1f}]  local [{lo[0]:7.1f}, {lo[1]:7.1f}]  "
                              f"nonlocal [{nl[0]:7.1f}, {nl[1]:7.1f}]" +
-                             (f"  send [{snd[0]:7.1f}, {snd[1]:7.1f}]" if snd else "") +
-                             f"  copy inside local: {'yes' if ok_in else 'no'}, nonlocal after both: "
-                             f"{'yes' if ok_after else 'no'}")
-            lines.append(f"  {inside} of {steps} calls with the copy inside the local part, {after} of "
-                         f"{steps} with the nonlocal part after both")
-            summary[name] = {"calls": steps, "copy_inside_local": inside, "nonlocal_after_both": after}
+                             (f"  send [{snd[0]:7.1f}, {snd[1]:7.1f}] {send_shares[-1] * 100:5.1f}%" if snd else "") +
+                             f"  copy under local {shares[-1] * 100:5.1f}%")
+            lines.append(f"  copy under the local part: median {np.median(shares) * 100:.1f}%, min "
+                         f"{min(shares) * 100:.1f}%; the copy ends before the local part in {ends_first} of "
+                         f"{steps} calls; the nonlocal part starts after both in {after} of {steps}" +
+                         (f"; send side under the local part: median {np.median(send_shares) * 100:.1f}%"
+                          if send_shares else ""))
+            summary[name] = {"calls": steps, "copy_share_under_local_median": float(np.median(shares)),
+                             "copy_ends_before_local": ends_first, "nonlocal_after_both": after}
         spmv.spmv_set_phase_timing(s, False)
     finally:
         torch.cuda.synchronize()

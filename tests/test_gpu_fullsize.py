@@ -188,16 +188,28 @@ def test_irregular8M_kpm_moments(c3):
     assert np.all(np.abs(mu - ref) <= tol[None, :]), np.abs(mu - ref).max()
 
 
+BLOCK_FIXED = {4: dict(kernel=5, panels=8, xcd_remap=0, block_kt=4),
+               8: dict(kernel=5, panels=4, xcd_remap=0, block_kt=8),
+               16: dict(kernel=5, panels=1, xcd_remap=0, block_kt=16)}
+
+
+@pytest.mark.parametrize("plan", ["tuned", "fixed"])
 @pytest.mark.parametrize("prec", ["f64", "f32"])
 @pytest.mark.parametrize("k", [4, 8, 16])
-def test_block_irregular8M_sampled(k, prec, c3):
+def test_block_irregular8M_sampled(k, prec, plan, c3):
+    """Block products at full size, with the tuner's plan and with the
+    fused-panel plans the tuner picked on the MI355X (fused panels, XCD remap
+    off), 2000 sampled rows against the oracle."""
     import torch
 
     A, _, _, _ = c3
     X = gen.block_rhs(A.n_cols, k)
     h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, prec=prec, flags=NOTUNE)
     try:
-        spmv.spmv_tune(h, k)
+        if plan == "tuned":
+            spmv.spmv_tune(h, k)
+        else:
+            spmv.spmv_set_plan(h, **BLOCK_FIXED[k])
         dt = torch.float64 if prec == "f64" else torch.float32
         B = torch.from_numpy(X).to("cuda", dtype=dt)
         C = torch.zeros((A.n_rows, k), dtype=dt, device="cuda")
