@@ -1548,6 +1548,17 @@ def main():
         del A3, x3
         paths["batch_512_stencils"] = batch_paths(max(10, args.steps // 4), 3)
 
+    # the paper's node-level figures, quoted with their hardware (context, not targets)
+    paths["paper_context"] = {
+        "hardware_socket": "Intel Xeon X5550 (Nehalem EP), one socket, 2.66 GHz, 3x DDR3-1333",
+        "HMeP_socket": {"spmv_GBs": 18.1, "stream_triad_GBs": 21.2, "gflops": 2.25, "kappa": 2.5,
+                        "model_limit_gflops": 2.66, "source": "Sect. 2"},
+        "HMEp_socket": {"kappa": 3.79, "source": "Sect. 2"},
+        "UHBR_socket": {"spmv_GBs": 18.9, "gflops": 2.99, "kappa": 0.43, "source": "Sect. 2"},
+        "hardware_node": "2x Intel Xeon X5650 (Westmere EP)",
+        "node_gflops": {"HMeP": 4.34, "HMEp": 3.89, "source": "Sect. 3.5"},
+        "note": "another machine's figures, quoted as context; not targets",
+    }
     line = {
         "metric": "spMV GFlop/s + achieved HBM GB/s vs 8 TB/s peak; FP64 vs mixed-prec at stated error",
         "value": flops / (head["ms_per_step"] * 1e6),
