@@ -41,6 +41,7 @@ namespace {
 
 constexpr int WG = 256;
 constexpr int NXCD = 8;
+static_assert(NXCD == NXCD_QUEUES, "one queue counter per XCD");
 
 template <int P> struct Ty;
 template <> struct Ty<P_F64> { using V = double;   using X = double; };
@@ -960,68 +961,78 @@ __global__ __launch_bounds__(WG) void k_block_fused(PanelSetDev S, int64_t n_blo
 }
 
 // ---------------------------------------------------------------------------
-// Batch kernels: tile t of the queue is (member, r0, r1); member arrays are
-// found through the descriptor table.
+// Batch kernels: tile t of the queue carries its member's row range, entry
+// range and array offsets.
 // ---------------------------------------------------------------------------
 template <int P, int E, bool NT>
 __device__ __forceinline__ void batch_tile(const int32_t *rp, const int32_t *col, const void *val,
-                                           const BatchDesc *desc, const BatchTile &T,
+                                           const BatchTile &T,
                                            const void *xv, void *yv,
                                            typename Ty<P>::X *s_prod) {
   using V = typename Ty<P>::V;
   using X = typename Ty<P>::X;
-  const BatchDesc D = desc[T.member];
-  const int32_t *mrp = rp + D.rp_off;
-  const TileRP m0{T.r0, mrp[T.r0]}, m1{T.r1, mrp[T.r1]};
-  tile_grouped<P, E, NT, false>(mrp, col + D.nz_off, static_cast<const V *>(val) + D.nz_off, nullptr,
-                               m0, m1, (int)(D.nz_off % group_of<V>()),
-                               static_cast<const X *>(xv) + D.x_off,
-                               static_cast<X *>(yv) + D.y_off, s_prod);
+  const int32_t *mrp = rp + T.rp_off;
+  const TileRP m0{T.r0, T.p0}, m1{T.r1, T.p1};
+  tile_grouped<P, E, NT, false>(mrp, col + T.nz_off, static_cast<const V *>(val) + T.nz_off, nullptr,
+                               m0, m1, (int)(T.nz_off % group_of<V>()),
+                               static_cast<const X *>(xv) + T.x_off,
+                               static_cast<X *>(yv) + T.y_off, s_prod);
 }
 
 __global__ void k_batch_reset(int32_t *counters) {
-  if (threadIdx.x < NXCD && blockIdx.x == 0) counters[threadIdx.x] = 0;
+  if (threadIdx.x < NXCD && blockIdx.x == 0) counters[threadIdx.x * QUEUE_STRIDE] = 0;
 }
 
 // Persistent grid with one work queue per XCD.  The tiles are cut into eight
 // contiguous ranges (as xcd_tile does); workgroup g, placed on XCD g % 8,
-// claims `chunk` consecutive tiles at a time from its XCD's range through
-// that range's counter, so each XCD's L2 sees one compact stretch of the
-// batch.  When its own range is used up a workgroup claims from the other
-// ranges in turn; it exits once all eight are used up (counters only grow,
-// so every workgroup reaches the exit).
+// claims one tile at a time from its XCD's range through that range's
+// counter, so the XCD's resident workgroups work on neighbouring tiles and
+// its L2 sees one compact stretch of the batch.  The claim of the next tile
+// is issued before the current tile's loads, so its latency hides under
+// them.  Each counter has a 128-byte line of its own: counters sharing a
+// line serialise the claims of all eight XCDs.  When its own range is used
+// up a workgroup claims from the other ranges in turn; it exits once all
+// eight are used up (counters only grow, so every workgroup reaches the
+// exit).
 template <int P, int E, bool NT>
 __global__ __launch_bounds__(WG) void k_batch_persistent(const int32_t *__restrict__ rp,
                                                          const int32_t *__restrict__ col,
-                                                         const void *val, const BatchDesc *desc,
+                                                         const void *val,
                                                          const BatchTile *tiles, int64_t n_tiles,
-                                                         int32_t *counters, int chunk,
+                                                         int32_t *counters,
                                                          const void *xv, void *yv) {
   using X = typename Ty<P>::X;
   __shared__ X s_prod[WG * E];
   __shared__ int32_t s_claim;
   const int64_t q = n_tiles / NXCD, r = n_tiles % NXCD;
   int xq = (int)(blockIdx.x % NXCD);
-  for (int tried = 0; tried < NXCD;) {
+  int tried = 0;
+  if (threadIdx.x == 0) s_claim = atomicAdd(&counters[xq * QUEUE_STRIDE], 1);
+  lds_barrier();
+  int64_t c = s_claim;
+  lds_barrier();
+  while (true) {
     const int64_t start = xq * q + (xq < r ? xq : r);
     const int64_t size = q + (xq < r ? 1 : 0);
-    if (threadIdx.x == 0) s_claim = atomicAdd(&counters[xq], chunk);
-    lds_barrier();
-    const int64_t c0 = s_claim;
-    lds_barrier();
-    if (c0 >= size) {
+    if (c >= size) {
+      if (++tried >= NXCD) break;
       xq = (xq + 1) % NXCD;
-      ++tried;
+      if (threadIdx.x == 0) s_claim = atomicAdd(&counters[xq * QUEUE_STRIDE], 1);
+      lds_barrier();
+      c = s_claim;
+      lds_barrier();
       continue;
     }
-    const int64_t c1 = min(c0 + chunk, size);
-    // LDS-only barriers: the previous tile's stores of C need not complete
-    // before the next tile starts (each tile writes its own rows)
-    for (int64_t t = start + c0; t < start + c1; ++t) {
-      const BatchTile T = tiles[t];
-      batch_tile<P, E, NT>(rp, col, val, desc, T, xv, yv, s_prod);
-      lds_barrier();
-    }
+    int32_t next = 0;
+    if (threadIdx.x == 0) next = atomicAdd(&counters[xq * QUEUE_STRIDE], 1);
+    const BatchTile T = tiles[start + c];
+    batch_tile<P, E, NT>(rp, col, val, T, xv, yv, s_prod);
+    // LDS-only barriers: the tile's stores of C need not complete before
+    // the next tile starts (each tile writes its own rows)
+    if (threadIdx.x == 0) s_claim = next;
+    lds_barrier();
+    c = s_claim;
+    lds_barrier();
   }
 }
 
@@ -1029,14 +1040,14 @@ __global__ __launch_bounds__(WG) void k_batch_persistent(const int32_t *__restri
 template <int P, int E, bool NT>
 __global__ __launch_bounds__(WG) void k_batch_flat(const int32_t *__restrict__ rp,
                                                    const int32_t *__restrict__ col,
-                                                   const void *val, const BatchDesc *desc,
+                                                   const void *val,
                                                    const BatchTile *tiles, int64_t n_tiles,
                                                    const void *xv, void *yv) {
   using X = typename Ty<P>::X;
   __shared__ X s_prod[WG * E];
   const int64_t t = xcd_tile(blockIdx.x, n_tiles, 1);
   const BatchTile T = tiles[t];
-  batch_tile<P, E, NT>(rp, col, val, desc, T, xv, yv, s_prod);
+  batch_tile<P, E, NT>(rp, col, val, T, xv, yv, s_prod);
 }
 
 // Batch tiles with the staged kernel's tile: one workgroup per tile, the run
@@ -1044,7 +1055,7 @@ __global__ __launch_bounds__(WG) void k_batch_flat(const int32_t *__restrict__ r
 template <int P, int E, bool NT>
 __global__ __launch_bounds__(WG) void k_batch_staged(const int32_t *__restrict__ rp,
                                                      const int32_t *__restrict__ col,
-                                                     const void *val, const BatchDesc *desc,
+                                                     const void *val,
                                                      const BatchTile *tiles,
                                                      const int32_t *__restrict__ runs,
                                                      int64_t n_tiles, const void *xv, void *yv) {
@@ -1053,13 +1064,12 @@ __global__ __launch_bounds__(WG) void k_batch_staged(const int32_t *__restrict__
   __shared__ X s_prod[staged_lds_elems<P, E>()];
   const int64_t t = xcd_tile(blockIdx.x, n_tiles, 1);
   const BatchTile T = tiles[t];
-  const BatchDesc D = desc[T.member];
-  const int32_t *mrp = rp + D.rp_off;
-  const TileRP m0{T.r0, mrp[T.r0]}, m1{T.r1, mrp[T.r1]};
-  staged_tile<P, E, NT, false>(mrp, col + D.nz_off, static_cast<const V *>(val) + D.nz_off, nullptr,
-                               m0, m1, (int)(D.nz_off % group_of<V>()), runs + t * RUN_WORDS,
-                               static_cast<const X *>(xv) + D.x_off,
-                               static_cast<X *>(yv) + D.y_off, s_prod);
+  const int32_t *mrp = rp + T.rp_off;
+  const TileRP m0{T.r0, T.p0}, m1{T.r1, T.p1};
+  staged_tile<P, E, NT, false>(mrp, col + T.nz_off, static_cast<const V *>(val) + T.nz_off, nullptr,
+                               m0, m1, (int)(T.nz_off % group_of<V>()), runs + t * RUN_WORDS,
+                               static_cast<const X *>(xv) + T.x_off,
+                               static_cast<X *>(yv) + T.y_off, s_prod);
 }
 
 // ---------------------------------------------------------------------------
@@ -1212,31 +1222,28 @@ hipError_t dispatch_block(const CsrDev &A, const TileRP *tiles, int64_t n_tiles,
 
 template <int P, int E>
 hipError_t run_persistent(const int32_t *rp, const int32_t *col, const void *val,
-                          const BatchDesc *desc, const BatchTile *tiles, int64_t n_tiles, int nt,
+                          const BatchTile *tiles, int64_t n_tiles, int nt,
                           int32_t *counter, int grid, const void *x, void *y, hipStream_t s) {
-  // about eight claims per workgroup, at most 16 tiles per claim
-  int64_t chunk = n_tiles / ((int64_t)grid * 8);  // grid workgroups share n_tiles
-  chunk = chunk < 1 ? 1 : (chunk > 16 ? 16 : chunk);
   if (nt)
     hipLaunchKernelGGL((k_batch_persistent<P, E, true>), dim3(grid), dim3(WG), 0, s, rp, col, val,
-                       desc, tiles, n_tiles, counter, (int)chunk, x, y);
+                       tiles, n_tiles, counter, x, y);
   else
     hipLaunchKernelGGL((k_batch_persistent<P, E, false>), dim3(grid), dim3(WG), 0, s, rp, col, val,
-                       desc, tiles, n_tiles, counter, (int)chunk, x, y);
+                       tiles, n_tiles, counter, x, y);
   return hipGetLastError();
 }
 
 template <int P, int E>
-hipError_t run_flat(const int32_t *rp, const int32_t *col, const void *val, const BatchDesc *desc,
+hipError_t run_flat(const int32_t *rp, const int32_t *col, const void *val,
                     const BatchTile *tiles, int64_t n_tiles, int nt, const void *x, void *y,
                     hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   if (nt)
     hipLaunchKernelGGL((k_batch_flat<P, E, true>), dim3((unsigned)n_tiles), dim3(WG), 0, s, rp, col,
-                       val, desc, tiles, n_tiles, x, y);
+                       val, tiles, n_tiles, x, y);
   else
     hipLaunchKernelGGL((k_batch_flat<P, E, false>), dim3((unsigned)n_tiles), dim3(WG), 0, s, rp,
-                       col, val, desc, tiles, n_tiles, x, y);
+                       col, val, tiles, n_tiles, x, y);
   return hipGetLastError();
 }
 
@@ -1443,77 +1450,77 @@ hipError_t launch_batch_reset(int32_t *counter, hipStream_t s) {
 
 template <int P>
 static hipError_t persistent_e(const int32_t *rp, const int32_t *col, const void *val,
-                               const BatchDesc *desc, const BatchTile *tiles, int64_t n_tiles,
+                               const BatchTile *tiles, int64_t n_tiles,
                                int tile_items, int nt, int32_t *counter, int grid, const void *x,
                                void *y, hipStream_t s) {
   switch (tile_items) {
-    case 4: return run_persistent<P, 4>(rp, col, val, desc, tiles, n_tiles, nt, counter, grid, x, y, s);
-    case 8: return run_persistent<P, 8>(rp, col, val, desc, tiles, n_tiles, nt, counter, grid, x, y, s);
-    case 16: return run_persistent<P, 16>(rp, col, val, desc, tiles, n_tiles, nt, counter, grid, x, y, s);
+    case 4: return run_persistent<P, 4>(rp, col, val, tiles, n_tiles, nt, counter, grid, x, y, s);
+    case 8: return run_persistent<P, 8>(rp, col, val, tiles, n_tiles, nt, counter, grid, x, y, s);
+    case 16: return run_persistent<P, 16>(rp, col, val, tiles, n_tiles, nt, counter, grid, x, y, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_batch_persistent(int prec, const int32_t *rp, const int32_t *col, const void *val,
-                                   const BatchDesc *desc, const BatchTile *tiles, int64_t n_tiles,
+                                   const BatchTile *tiles, int64_t n_tiles,
                                    int tile_items, int nontemporal, int32_t *counter, int grid,
                                    const void *x, void *y, hipStream_t s) {
-  SPMV_PREC_SWITCH(prec, (persistent_e<PP>(rp, col, val, desc, tiles, n_tiles, tile_items,
+  SPMV_PREC_SWITCH(prec, (persistent_e<PP>(rp, col, val, tiles, n_tiles, tile_items,
                                            nontemporal, counter, grid, x, y, s)))
 }
 
 template <int P>
 static hipError_t flat_e(const int32_t *rp, const int32_t *col, const void *val,
-                         const BatchDesc *desc, const BatchTile *tiles, int64_t n_tiles,
+                         const BatchTile *tiles, int64_t n_tiles,
                          int tile_items, int nt, const void *x, void *y, hipStream_t s) {
   switch (tile_items) {
-    case 4: return run_flat<P, 4>(rp, col, val, desc, tiles, n_tiles, nt, x, y, s);
-    case 8: return run_flat<P, 8>(rp, col, val, desc, tiles, n_tiles, nt, x, y, s);
-    case 16: return run_flat<P, 16>(rp, col, val, desc, tiles, n_tiles, nt, x, y, s);
+    case 4: return run_flat<P, 4>(rp, col, val, tiles, n_tiles, nt, x, y, s);
+    case 8: return run_flat<P, 8>(rp, col, val, tiles, n_tiles, nt, x, y, s);
+    case 16: return run_flat<P, 16>(rp, col, val, tiles, n_tiles, nt, x, y, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int P, int E>
 hipError_t run_batch_staged(const int32_t *rp, const int32_t *col, const void *val,
-                            const BatchDesc *desc, const BatchTile *tiles, const int32_t *runs,
+                            const BatchTile *tiles, const int32_t *runs,
                             int64_t n_tiles, int nt, const void *x, void *y, hipStream_t s) {
   if (n_tiles <= 0) return hipSuccess;
   if (!runs) return hipErrorInvalidValue;
   if (nt)
     hipLaunchKernelGGL((k_batch_staged<P, E, true>), dim3((unsigned)n_tiles), dim3(WG), 0, s, rp,
-                       col, val, desc, tiles, runs, n_tiles, x, y);
+                       col, val, tiles, runs, n_tiles, x, y);
   else
     hipLaunchKernelGGL((k_batch_staged<P, E, false>), dim3((unsigned)n_tiles), dim3(WG), 0, s, rp,
-                       col, val, desc, tiles, runs, n_tiles, x, y);
+                       col, val, tiles, runs, n_tiles, x, y);
   return hipGetLastError();
 }
 
 template <int P>
 static hipError_t batch_staged_e(const int32_t *rp, const int32_t *col, const void *val,
-                                 const BatchDesc *desc, const BatchTile *tiles,
+                                 const BatchTile *tiles,
                                  const int32_t *runs, int64_t n_tiles, int tile_items, int nt,
                                  const void *x, void *y, hipStream_t s) {
   switch (tile_items) {
-    case 8: return run_batch_staged<P, 8>(rp, col, val, desc, tiles, runs, n_tiles, nt, x, y, s);
-    case 16: return run_batch_staged<P, 16>(rp, col, val, desc, tiles, runs, n_tiles, nt, x, y, s);
+    case 8: return run_batch_staged<P, 8>(rp, col, val, tiles, runs, n_tiles, nt, x, y, s);
+    case 16: return run_batch_staged<P, 16>(rp, col, val, tiles, runs, n_tiles, nt, x, y, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 hipError_t launch_batch_staged(int prec, const int32_t *rp, const int32_t *col, const void *val,
-                               const BatchDesc *desc, const BatchTile *tiles, const int32_t *runs,
+                               const BatchTile *tiles, const int32_t *runs,
                                int64_t n_tiles, int tile_items, int nontemporal, const void *x,
                                void *y, hipStream_t s) {
-  SPMV_PREC_SWITCH(prec, (batch_staged_e<PP>(rp, col, val, desc, tiles, runs, n_tiles, tile_items,
+  SPMV_PREC_SWITCH(prec, (batch_staged_e<PP>(rp, col, val, tiles, runs, n_tiles, tile_items,
                                              nontemporal, x, y, s)))
 }
 
 hipError_t launch_batch_flat(int prec, const int32_t *rp, const int32_t *col, const void *val,
-                             const BatchDesc *desc, const BatchTile *tiles, int64_t n_tiles,
+                             const BatchTile *tiles, int64_t n_tiles,
                              int tile_items, int nontemporal, const void *x, void *y,
                              hipStream_t s) {
-  SPMV_PREC_SWITCH(prec, (flat_e<PP>(rp, col, val, desc, tiles, n_tiles, tile_items, nontemporal,
+  SPMV_PREC_SWITCH(prec, (flat_e<PP>(rp, col, val, tiles, n_tiles, tile_items, nontemporal,
                                      x, y, s)))
 }
 

@@ -98,9 +98,7 @@ extern "C" spmv_status_t spmv_create_batch(int32_t count, const int64_t *n_rows,
       upload(M.row_ptr, M.h_row_ptr.data(), M.h_row_ptr.size() * 4, "batch row_ptr", up.s);
       upload(M.col, col_all.data(), col_all.size() * 4, "batch col_idx", up.s);
       upload(M.val, val_all.data(), val_all.size(), "batch val", up.s);
-      upload(h->b_desc, h->h_desc.data(), h->h_desc.size() * sizeof(BatchDesc), "batch descriptors",
-             up.s);
-      h->b_counter.alloc(8 * sizeof(int32_t), "batch queue counters", up.s);
+      h->b_counter.alloc(NXCD_QUEUES * QUEUE_STRIDE * sizeof(int32_t), "batch queue counters", up.s);
       up.sync();
     }
     choose_plan(h.get(), M, "batch");
@@ -129,7 +127,10 @@ void batch_prepare(spmv_handle_s *h) {
     const BatchDesc &d = h->h_desc[size_t(m)];
     std::vector<int32_t> t =
         make_tiles(h->main.h_row_ptr.data() + d.rp_off, h->m_rows[size_t(m)], int64_t(kWG) * items);
-    for (size_t i = 0; i + 1 < t.size(); ++i) tl.push_back(BatchTile{m, t[i], t[i + 1], 0});
+    const int32_t *mrp = h->main.h_row_ptr.data() + d.rp_off;
+    for (size_t i = 0; i + 1 < t.size(); ++i)
+      tl.push_back(BatchTile{m, t[i], t[i + 1], mrp[t[i]], mrp[t[i + 1]], 0, d.rp_off, d.nz_off,
+                             d.x_off, d.y_off});
   }
   if (int64_t(tl.size()) >= int64_t(INT32_MAX) - (int64_t(1) << 20))
     fail(SPMV_ERR_UNSUPPORTED, "too many tiles");
@@ -160,11 +161,8 @@ void batch_runs(spmv_handle_s *h) {
         std::vector<int32_t> cs;
         for (int64_t t = b; t < e; ++t) {
           const BatchTile &T = h->h_btiles[size_t(t)];
-          const BatchDesc &D = h->h_desc[size_t(T.member)];
-          const int64_t p0 = M.h_row_ptr[size_t(D.rp_off + T.r0)];
-          const int64_t p1 = M.h_row_ptr[size_t(D.rp_off + T.r1)];
-          run_row(hc.data() + D.nz_off + p0, p1 - p0, int64_t(kWG) * items - 4, budget, cs,
-                  table.data() + size_t(t) * RUN_WORDS);
+          run_row(hc.data() + T.nz_off + T.p0, int64_t(T.p1) - T.p0, int64_t(kWG) * items - 4,
+                  budget, cs, table.data() + size_t(t) * RUN_WORDS);
         }
       },
       64);
@@ -180,18 +178,17 @@ void batch_runs(spmv_handle_s *h) {
 hipError_t batch_launch_direct(spmv_handle_s *h, const void *B, void *C, hipStream_t s) {
   if (h->main.plan.kernel == SPMV_KERNEL_STAGED)
     return launch_batch_staged(h->prec, h->main.row_ptr.as<int32_t>(), h->main.col.as<int32_t>(),
-                               h->main.val.p, h->b_desc.as<BatchDesc>(), h->b_tiles.as<BatchTile>(),
+                               h->main.val.p, h->b_tiles.as<BatchTile>(),
                                h->b_runs.as<int32_t>(), h->b_ntiles, h->b_tiles_items,
                                h->main.plan.nontemporal, B, C, s);
   if (h->main.plan.kernel == SPMV_KERNEL_TILE_GRID)
     return launch_batch_flat(h->prec, h->main.row_ptr.as<int32_t>(), h->main.col.as<int32_t>(),
-                             h->main.val.p, h->b_desc.as<BatchDesc>(), h->b_tiles.as<BatchTile>(),
+                             h->main.val.p, h->b_tiles.as<BatchTile>(),
                              h->b_ntiles, h->b_tiles_items, h->main.plan.nontemporal, B, C, s);
   hipError_t e = launch_batch_reset(h->b_counter.as<int32_t>(), s);
   if (e != hipSuccess) return e;
   return launch_batch_persistent(h->prec, h->main.row_ptr.as<int32_t>(), h->main.col.as<int32_t>(),
-                                 h->main.val.p, h->b_desc.as<BatchDesc>(),
-                                 h->b_tiles.as<BatchTile>(), h->b_ntiles, h->b_tiles_items,
+                                 h->main.val.p, h->b_tiles.as<BatchTile>(), h->b_ntiles, h->b_tiles_items,
                                  h->main.plan.nontemporal, h->b_counter.as<int32_t>(), h->b_grid,
                                  B, C, s);
 }
@@ -205,7 +202,7 @@ void batch_run(spmv_handle_s *h, const void *B, void *C, hipStream_t s) {
   }
   if (h->schedule == SPMV_SCHEDULE_BATCH_FLAT) {
     hip_ok(launch_batch_flat(h->prec, h->main.row_ptr.as<int32_t>(), h->main.col.as<int32_t>(),
-                             h->main.val.p, h->b_desc.as<BatchDesc>(), h->b_tiles.as<BatchTile>(),
+                             h->main.val.p, h->b_tiles.as<BatchTile>(),
                              h->b_ntiles, h->b_tiles_items, h->main.plan.nontemporal, B, C, s),
            "batch flat launch");
     return;

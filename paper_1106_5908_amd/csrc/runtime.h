@@ -250,7 +250,7 @@ struct spmv_handle_s {
   // batch
   int32_t count = 0;
   std::vector<int64_t> m_rows, m_cols;
-  spmv::rt::DevBuf b_desc, b_tiles, b_counter;
+  spmv::rt::DevBuf b_tiles, b_counter;
   int64_t b_ntiles = 0;
   int b_tiles_items = 0;
   int b_grid = 0;

@@ -50,7 +50,8 @@ struct TileRP {
   int32_t p;
 };
 
-// Per-member descriptor of a batch: offsets into the pooled arrays.
+// Per-member offsets of a batch into the pooled arrays (host side; each tile
+// carries a copy of its member's).
 struct BatchDesc {
   int64_t rp_off;   // first row_ptr entry of the member (local row_ptr values)
   int64_t nz_off;   // first col / val entry
@@ -58,12 +59,21 @@ struct BatchDesc {
   int64_t y_off;    // first element of the member's C
 };
 
-// Tile of a batch: member and row range [r0, r1) of that member.
+// Tile of a batch: member, row range [r0, r1) of that member and its entries
+// [p0, p1) (the member's row_ptr at r0 and r1), with the member's
+// descriptor copied in, so a workgroup starts its tile's loads after one
+// load of the tile instead of a chain through the descriptor table.
 struct BatchTile {
   int32_t member;
   int32_t r0;
   int32_t r1;
+  int32_t p0;
+  int32_t p1;
   int32_t pad;
+  int64_t rp_off;
+  int64_t nz_off;
+  int64_t x_off;
+  int64_t y_off;
 };
 
 // ---- launchers (kernels.hip) -------------------------------------------------
@@ -87,21 +97,25 @@ hipError_t launch_spmv_block(int prec, const CsrDev &A, const TileRP *tiles, int
                              hipStream_t s);
 
 // counters: one int32 per XCD (8)
+// The persistent batch grid's eight queue counters, QUEUE_STRIDE int32s
+// apart (one 128-byte line each): a buffer of NXCD_QUEUES * QUEUE_STRIDE.
+constexpr int QUEUE_STRIDE = 32;
+constexpr int NXCD_QUEUES = 8;
 hipError_t launch_batch_reset(int32_t *counters, hipStream_t s);
 
 hipError_t launch_batch_persistent(int prec, const int32_t *rp, const int32_t *col, const void *val,
-                                   const BatchDesc *desc, const BatchTile *tiles, int64_t n_tiles,
+                                   const BatchTile *tiles, int64_t n_tiles,
                                    int tile_items, int nontemporal, int32_t *counter, int grid,
                                    const void *x, void *y, hipStream_t s);
 
 hipError_t launch_batch_flat(int prec, const int32_t *rp, const int32_t *col, const void *val,
-                             const BatchDesc *desc, const BatchTile *tiles, int64_t n_tiles,
+                             const BatchTile *tiles, int64_t n_tiles,
                              int tile_items, int nontemporal, const void *x, void *y, hipStream_t s);
 
 // The staged kernel over batch tiles (tile_items 8 or 16): one workgroup per
 // tile, `runs` the run table of the n_tiles batch tiles (member-local columns).
 hipError_t launch_batch_staged(int prec, const int32_t *rp, const int32_t *col, const void *val,
-                               const BatchDesc *desc, const BatchTile *tiles, const int32_t *runs,
+                               const BatchTile *tiles, const int32_t *runs,
                                int64_t n_tiles, int tile_items, int nontemporal, const void *x,
                                void *y, hipStream_t s);
 
