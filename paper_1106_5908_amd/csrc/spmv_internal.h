@@ -60,9 +60,9 @@ struct BatchDesc {
 };
 
 // Tile of a batch: member, row range [r0, r1) of that member and its entries
-// [p0, p1) (the member's row_ptr at r0 and r1), with the member's
-// descriptor copied in, so a workgroup starts its tile's loads after one
-// load of the tile instead of a chain through the descriptor table.
+// [p0, p1) (the member's row_ptr at r0 and r1), with the member's offsets
+// copied in, so a workgroup starts its tile's loads after one load of the
+// tile instead of a chain of dependent loads.
 struct BatchTile {
   int32_t member;
   int32_t r0;

@@ -812,6 +812,33 @@ def test_batch_matches_members(schedule, tile_items, kernel):
         off += A.n_rows
 
 
+@pytest.mark.parametrize("count", [1, 3, 8, 9, 17])
+@pytest.mark.parametrize("schedule", [spmv.SPMV_SCHEDULE_BATCH_GRAPH, spmv.SPMV_SCHEDULE_BATCH_DIRECT])
+def test_batch_queue_fewer_tiles_than_queues(count, schedule):
+    """The persistent queue with fewer tiles than XCD queues (some queues
+    empty) or a few more: every tile is claimed exactly once, on each of
+    three calls in a row (the counters are reset before every launch)."""
+    import torch
+
+    rng = gen.rng_for(19, count)
+    mem = [gen.random_crs(int(rng.integers(1, 400)), int(rng.integers(1, 300)), rng, max_len=6,
+                          integer_values=True) for _ in range(count)]
+    xs = [gen.integer_vector(A.n_cols, rng) for A in mem]
+    exact = np.concatenate([oracle.spmv(A.row_ptr, A.col_idx, A.val, x) for A, x in zip(mem, xs)])
+    h = spmv.spmv_create_batch([(A.row_ptr, A.col_idx, A.val, A.n_cols) for A in mem], flags=NOTUNE)
+    try:
+        spmv.spmv_set_schedule(h, schedule)
+        spmv.spmv_set_plan(h, kernel=spmv.SPMV_KERNEL_STREAM, tile_items=4)
+        B = to_dev(np.concatenate(xs), "f64")
+        C = torch.zeros(exact.size, dtype=torch.float64, device="cuda")
+        for r in range(1, 4):
+            spmv.spmv_run(h, B, C)
+            torch.cuda.synchronize()
+            assert np.array_equal(C.cpu().numpy(), r * exact), f"call {r}"
+    finally:
+        spmv.spmv_destroy(h)
+
+
 @pytest.mark.parametrize("kernel", [spmv.SPMV_KERNEL_STREAM, spmv.SPMV_KERNEL_TILE_GRID,
                                     spmv.SPMV_KERNEL_STAGED])
 def test_batch_graph_replays_and_recapture(kernel):
