@@ -392,7 +392,26 @@ spmv_status_t spmv_create_sym_crs(int64_t n, int64_t nnz, const int32_t *row_ptr
  *                that cover all rows; not for split nonlocal parts, batches or
  *                symmetric handles).  In a block plan (spmv_get_block_plan)
  *                the same walk with the block kernel's column layout.
- *   tile_items   4, 8 or 16 (stream and fused-panel kernels); 8 or 16 (staged)
+ *                SPMV_KERNEL_SORTED_BLOCKS: the rows are cut into blocks of
+ *                16384 rows (FP64 accumulation) or 32768 (FP32); a
+ *                1024-thread workgroup takes one block, whose entries the
+ *                library has sorted by column and dealt into chunks of
+ *                1024 * tile_items entries in which no row appears twice,
+ *                and adds each entry's product to its row's sum in LDS, chunk
+ *                after chunk; C is read and written once.  The lanes of one
+ *                load gather neighbouring columns of B, so matrices whose
+ *                rows gather from scattered columns (a wide band) gain.  The
+ *                row sums are formed in a fixed order: the same result on
+ *                every call.  The layout (column, value and a 2-byte row per
+ *                entry, empty slots padded) is built on the host when the
+ *                plan is set, from a copy of col_idx and val read back once.
+ *                For parts that cover all rows (not split nonlocal parts,
+ *                batches or symmetric handles); SPMV_ERR_UNSUPPORTED when a
+ *                block's longest row would make the layout more than about
+ *                four slots per entry.  Block products of a handle with this
+ *                plan use the block kernel.
+ *   tile_items   4, 8 or 16 (stream and fused-panel kernels); 8 or 16 (staged);
+ *                1, 2 or 4 (sorted-block kernel)
  *   lanes        2, 4, 8, 16, 32 or 64 (vector kernel)
  *   nontemporal  1: val and col_idx are loaded with the streaming hint so
  *                they do not displace B from the caches
@@ -408,13 +427,15 @@ spmv_status_t spmv_create_sym_crs(int64_t n, int64_t nnz, const int32_t *row_ptr
  *                grouped by their offset from the diagonal (col - row) into
  *                this many equal slices, each a CRS applied in turn, so the
  *                window of B one slice gathers from is that many times
- *                narrower and can stay in the L2 cache
+ *                narrower and can stay in the L2 cache (1 for the
+ *                sorted-block kernel)
  * ------------------------------------------------------------------------- */
 #define SPMV_KERNEL_STREAM 1
 #define SPMV_KERNEL_VECTOR 2
 #define SPMV_KERNEL_TILE_GRID 3
 #define SPMV_KERNEL_STAGED 4
 #define SPMV_KERNEL_FUSED_PANELS 5
+#define SPMV_KERNEL_SORTED_BLOCKS 6
 #define SPMV_PART_MAIN 0
 #define SPMV_PART_NONLOCAL 1
 
@@ -460,7 +481,8 @@ typedef struct spmv_info {
     int64_t halo_begin;    /* split: first halo column; else n_cols */
     int64_t nnz_local, nnz_nonlocal, n_nonlocal_rows;
     int32_t batch_count;   /* batch: members; else 1 */
-    int64_t n_tiles;       /* stream-kernel tiles of the main part */
+    int64_t n_tiles;       /* stream-kernel tiles of the main part (chunks
+                              for a sorted-block plan) */
     double row_len_mean, row_len_cv;
     int64_t row_len_max;
     int64_t n_send;        /* split: entries of the send list; else 0 */

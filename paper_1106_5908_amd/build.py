@@ -16,7 +16,7 @@ OUT = os.path.join(PKG, "libspmv.so")
 BUILD = os.path.join(PKG, "_build")
 SOURCES = ["kernels.hip", "split.hip", "probes.hip", "exchange.hip", "kpm.hip", "lanczos.hip",
            "rt_core.cpp", "rt_plan.cpp", "rt_split.cpp", "rt_batch.cpp", "rt_run.cpp",
-           "rt_exchange.cpp", "rt_solvers.hip"]
+           "rt_exchange.cpp", "rt_sorted.cpp", "rt_solvers.hip"]
 ARCH = os.environ.get("SPMV_OFFLOAD_ARCH", "gfx950")
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")

@@ -961,6 +961,95 @@ __global__ __launch_bounds__(WG) void k_block_fused(PanelSetDev S, int64_t n_blo
 }
 
 // ---------------------------------------------------------------------------
+// Sorted-block kernel.  On a matrix whose rows gather from scattered columns
+// (a wide band), every gather of the stream kernel touches its own cache
+// line.  Here one workgroup takes a block of R rows (R accumulators fill
+// 128 KB of LDS: 16384 rows in FP64, 32768 in FP32) whose entries the host
+// sorted by column: the lanes of one load then gather neighbouring columns,
+// several to a line.  The entries come in chunks of Q = 1024 * E slots in
+// which no row appears twice, so each lane adds its product to its row's
+// accumulator with a plain LDS read-add-write, and one barrier per chunk
+// orders the chunks; the sums are therefore the same on every call.  Chunk
+// c + 1's gathers and chunk c + 2's slot loads are in flight while chunk c
+// is added.  C is read and written once, after the last chunk.
+// ---------------------------------------------------------------------------
+template <int P, int E, bool NT>
+__global__ __launch_bounds__(SB_WG) void k_sorted(SortedDev S, int remap, const void *xv,
+                                                  void *yv) {
+  using V = typename Ty<P>::V;
+  using X = typename Ty<P>::X;
+  constexpr int R = SB_LDS_BYTES / (int)sizeof(X);
+  constexpr int Q = SB_WG * E;
+  __shared__ X acc[R];
+  const X *__restrict__ x = static_cast<const X *>(xv);
+  X *__restrict__ y = static_cast<X *>(yv);
+  const V *__restrict__ val = static_cast<const V *>(S.val);
+  const int tid = (int)threadIdx.x;
+  const int64_t b = xcd_tile(blockIdx.x, S.n_blocks, remap);
+  for (int i = tid; i < R; i += SB_WG) acc[i] = neg_zero<X>();
+  lds_barrier();
+  const int64_t c0 = S.cs[b], c1 = S.cs[b + 1];
+  // slots of chunk c (uniform test: past the last chunk, empty slots)
+  auto load = [&](int64_t c, int (&cc)[E], V (&vv)[E], int (&rr)[E]) {
+    if (c < c1) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        const int64_t j = c * Q + (int64_t)e * SB_WG + tid;
+        cc[e] = ld<int32_t, NT>(S.col + j);
+        vv[e] = ld<V, NT>(val + j);
+        rr[e] = (int)ld<uint16_t, NT>(S.row + j);
+      }
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) {
+        cc[e] = 0;
+        vv[e] = V(0);
+        rr[e] = SB_PAD_ROW;
+      }
+    }
+  };
+  auto gather = [&](int64_t c, const int (&cc)[E], X (&g)[E]) {
+    if (c < c1) {
+#pragma unroll
+      for (int e = 0; e < E; ++e) g[e] = x[cc[e]];
+    } else {
+#pragma unroll
+      for (int e = 0; e < E; ++e) g[e] = X(0);
+    }
+  };
+  int ca[E], ra[E], cb[E], rb[E];
+  V va[E], vb[E];
+  X ga[E], gb[E];
+  load(c0, ca, va, ra);
+  gather(c0, ca, ga);
+  load(c0 + 1, cb, vb, rb);
+  for (int64_t c = c0; c < c1; ++c) {
+    gather(c + 1, cb, gb);
+    int cn[E], rn[E];
+    V vn[E];
+    load(c + 2, cn, vn, rn);
+    // rows are distinct within a chunk: no two lanes touch one accumulator
+#pragma unroll
+    for (int e = 0; e < E; ++e)
+      if (ra[e] != SB_PAD_ROW) acc[ra[e]] += widen<X>(va[e]) * ga[e];
+    lds_barrier();
+#pragma unroll
+    for (int e = 0; e < E; ++e) {
+      ra[e] = rb[e];
+      va[e] = vb[e];
+      ga[e] = gb[e];
+      rb[e] = rn[e];
+      vb[e] = vn[e];
+      cb[e] = cn[e];
+    }
+  }
+  // (the last chunk's barrier has ordered every addition before this read)
+  const int64_t r0 = b * R;
+  const int nrow = (int)min((int64_t)R, S.n_rows - r0);
+  for (int i = tid; i < nrow; i += SB_WG) y[r0 + i] = y[r0 + i] + acc[i];
+}
+
+// ---------------------------------------------------------------------------
 // Batch kernels: tile t of the queue carries its member's row range, entry
 // range and array offsets.
 // ---------------------------------------------------------------------------
@@ -1368,6 +1457,30 @@ int block_fused_rows_p(int kt, int k, int64_t ldb, int64_t ldc, const void *B, c
   return ng * block_nr_for(ng, want_rows);
 }
 
+template <int P, int E>
+hipError_t run_sorted(const SortedDev &S, int nt, int remap, const void *x, void *y,
+                      hipStream_t s) {
+  if (S.n_blocks <= 0) return hipSuccess;
+  if (nt)
+    hipLaunchKernelGGL((k_sorted<P, E, true>), dim3((unsigned)S.n_blocks), dim3(SB_WG), 0, s, S,
+                       remap, x, y);
+  else
+    hipLaunchKernelGGL((k_sorted<P, E, false>), dim3((unsigned)S.n_blocks), dim3(SB_WG), 0, s, S,
+                       remap, x, y);
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t dispatch_sorted(const SortedDev &S, int items, int nt, int remap, const void *x,
+                           void *y, hipStream_t s) {
+  switch (items) {
+    case 1: return run_sorted<P, 1>(S, nt, remap, x, y, s);
+    case 2: return run_sorted<P, 2>(S, nt, remap, x, y, s);
+    case 4: return run_sorted<P, 4>(S, nt, remap, x, y, s);
+    default: return hipErrorInvalidValue;
+  }
+}
+
 }  // namespace
 
 #define SPMV_PREC_SWITCH(prec, CALL) \
@@ -1426,6 +1539,13 @@ hipError_t launch_spmv_fused(int prec, const PanelSetDev &S, int R, int tile_ite
                              int xcd_remap, const void *x, void *y, hipStream_t s) {
   if (R < 1 || R > 2 * WG || S.K < 1 || S.K > PANEL_MAX) return hipErrorInvalidValue;
   SPMV_PREC_SWITCH(prec, (dispatch_fused<PP>(S, R, tile_items, nontemporal, xcd_remap, x, y, s)))
+}
+
+hipError_t launch_spmv_sorted(int prec, const SortedDev &S, int tile_items, int nontemporal,
+                              int xcd_remap, const void *x, void *y, hipStream_t s) {
+  const int R = sorted_block_rows(prec);
+  if (R <= 0 || S.n_blocks != (S.n_rows + R - 1) / R) return hipErrorInvalidValue;
+  SPMV_PREC_SWITCH(prec, (dispatch_sorted<PP>(S, tile_items, nontemporal, xcd_remap, x, y, s)))
 }
 
 int block_fused_rows(int prec, int kt, int k, int64_t ldb, int64_t ldc, const void *B, const void *C,
@@ -1530,6 +1650,14 @@ static int grid_e(int tile_items, int device) {
     case 4: return persistent_grid_for<P, 4>(device);
     case 8: return persistent_grid_for<P, 8>(device);
     default: return persistent_grid_for<P, 16>(device);
+  }
+}
+
+int sorted_block_rows(int prec) {
+  switch (prec) {
+    case P_F64: case P_F32_F64: return SB_LDS_BYTES / 8;
+    case P_F32: case P_BF16: return SB_LDS_BYTES / 4;
+    default: return 0;
   }
 }
 

@@ -144,11 +144,16 @@ spmv_plan_t default_plan() {
 void check_plan(const spmv_plan_t &p) {
   if (p.kernel != SPMV_KERNEL_STREAM && p.kernel != SPMV_KERNEL_VECTOR &&
       p.kernel != SPMV_KERNEL_TILE_GRID && p.kernel != SPMV_KERNEL_STAGED &&
-      p.kernel != SPMV_KERNEL_FUSED_PANELS)
-    fail(SPMV_ERR_INVALID_ARG,
-         "plan.kernel must be SPMV_KERNEL_STREAM, _VECTOR, _TILE_GRID, _STAGED or _FUSED_PANELS");
-  if (p.tile_items != 4 && p.tile_items != 8 && p.tile_items != 16)
+      p.kernel != SPMV_KERNEL_FUSED_PANELS && p.kernel != SPMV_KERNEL_SORTED_BLOCKS)
+    fail(SPMV_ERR_INVALID_ARG, "plan.kernel must be SPMV_KERNEL_STREAM, _VECTOR, _TILE_GRID, "
+                               "_STAGED, _FUSED_PANELS or _SORTED_BLOCKS");
+  if (p.kernel == SPMV_KERNEL_SORTED_BLOCKS) {
+    if (p.tile_items != 1 && p.tile_items != 2 && p.tile_items != 4)
+      fail(SPMV_ERR_INVALID_ARG, "the sorted-block kernel takes tile_items 1, 2 or 4");
+    if (p.panels != 1) fail(SPMV_ERR_INVALID_ARG, "the sorted-block kernel takes panels 1");
+  } else if (p.tile_items != 4 && p.tile_items != 8 && p.tile_items != 16) {
     fail(SPMV_ERR_INVALID_ARG, "plan.tile_items must be 4, 8 or 16");
+  }
   if (p.kernel == SPMV_KERNEL_STAGED && p.tile_items == 4)
     fail(SPMV_ERR_INVALID_ARG, "the staged kernel takes tile_items 8 or 16");
   if (p.lanes < 2 || p.lanes > 64 || (p.lanes & (p.lanes - 1)))
@@ -370,6 +375,8 @@ void choose_plan(spmv_handle_s *h, Part &p, const char *part_name) {
   if (p.plan.panels > 1 && (p.row_ids.p || h->kind == SPMV_KIND_BATCH)) p.plan.panels = 1;
   if (p.plan.kernel == SPMV_KERNEL_FUSED_PANELS && (p.row_ids.p || h->kind == SPMV_KIND_BATCH))
     p.plan.kernel = SPMV_KERNEL_STREAM;
+  if (p.plan.kernel == SPMV_KERNEL_SORTED_BLOCKS && (p.row_ids.p || h->kind == SPMV_KIND_BATCH))
+    p.plan = default_plan();
   if (p.plan.panels > 1) build_panels(h, p, p.plan.panels);
   if (h->kind != SPMV_KIND_BATCH) prepare_part(h, p);
   if (std::getenv("SPMV_LOG"))
@@ -391,6 +398,10 @@ void prepare_part(spmv_handle_s *h, Part &p) {
     (void)fused_rows_for(h, p, p.plan.panels, kWG * items - 4);
     return;
   }
+  if (p.plan.kernel == SPMV_KERNEL_SORTED_BLOCKS) {
+    if (p.n_rows > 0 && p.nnz > 0) (void)sorted_for(h, p, items);
+    return;
+  }
   if (p.plan.panels > 1) {
     for (auto &q : build_panels(h, p, p.plan.panels)) {
       (void)q->tiles_for(items);
@@ -406,6 +417,8 @@ void prepare_part(spmv_handle_s *h, Part &p) {
 bool part_prepared(const Part &p, int x_bytes) {
   (void)x_bytes;
   const int items = p.plan.tile_items;
+  if (p.plan.kernel == SPMV_KERNEL_SORTED_BLOCKS)
+    return p.n_rows == 0 || p.nnz == 0 || p.sorted.find(items) != p.sorted.end();
   if (p.plan.kernel == SPMV_KERNEL_FUSED_PANELS) {
     if (p.plan.panels > 1 && p.panel_sets.find(p.plan.panels) == p.panel_sets.end()) return false;
     return p.fused_rows.find(std::make_pair(p.plan.panels, kWG * items - 4)) != p.fused_rows.end();
@@ -507,6 +520,13 @@ void run_part_half(spmv_handle_s *h, Part &p, int half, const void *B, void *C, 
 
 void run_part(spmv_handle_s *h, Part &p, const void *B, void *C, hipStream_t s) {
   if (p.n_rows == 0 || p.nnz == 0) return;
+  if (p.plan.kernel == SPMV_KERNEL_SORTED_BLOCKS) {
+    const SortedDev S = sorted_dev(h, p, p.plan.tile_items);
+    hip_ok(launch_spmv_sorted(h->prec, S, p.plan.tile_items, p.plan.nontemporal, p.plan.xcd_remap,
+                              B, C, s),
+           "kernel launch");
+    return;
+  }
   if (p.plan.kernel == SPMV_KERNEL_FUSED_PANELS) {
     const PanelSetDev S = panel_set_dev(h, p, p.plan.panels);
     const int R = fused_rows_for(h, p, p.plan.panels, kWG * p.plan.tile_items - 4);
@@ -688,19 +708,39 @@ void tune_part(spmv_handle_s *h, Part &p, const char *name, void *x, void *y, hi
   if (!p.row_ids.p) {
     const std::vector<spmv_plan_t> pc = panel_candidates();
     cands.insert(cands.end(), pc.begin(), pc.end());
+    // sorted blocks: one 1024-thread workgroup per block, so only for parts
+    // of at least one block per two CUs
+    const int R = sorted_block_rows(h->prec);
+    int n_cu = 256;
+    (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
+    if (R > 0 && 2 * p.n_rows >= int64_t(R) * std::max(n_cu, 1))
+      for (int e : {1, 2, 4}) {
+        spmv_plan_t c = default_plan();
+        c.kernel = SPMV_KERNEL_SORTED_BLOCKS;
+        c.tile_items = e;
+        cands.push_back(c);
+      }
   }
+  std::vector<spmv_plan_t> ran;
   std::vector<float> times;
   for (const spmv_plan_t &c : cands) {
     p.plan = c;
-    prepare_part(h, p);
+    try {
+      prepare_part(h, p);
+    } catch (const Failure &f) {
+      // a part whose rows are too long for the sorted-block layout
+      if (c.kernel == SPMV_KERNEL_SORTED_BLOCKS && f.status == SPMV_ERR_UNSUPPORTED) continue;
+      throw;
+    }
+    ran.push_back(c);
     times.push_back(tm.median_ms([&] { run_part(h, p, x, y, s); }, s));
     best = std::min(best, times.back());
   }
   // the earliest candidate within 1% of the fastest: near-ties resolve the
   // same way from run to run
-  for (size_t i = 0; i < cands.size(); ++i)
+  for (size_t i = 0; i < ran.size(); ++i)
     if (times[i] <= best * 1.01f) {
-      best_p = cands[i];
+      best_p = ran[i];
       best = times[i];
       break;
     }
@@ -711,6 +751,7 @@ void tune_part(spmv_handle_s *h, Part &p, const char *name, void *x, void *y, hi
   std::vector<int> keep{p.plan.panels};
   for (auto &bp : h->block_plans) keep.push_back(bp.second.panels);
   prune_panels(p, keep);
+  prune_sorted(p, p.plan.kernel == SPMV_KERNEL_SORTED_BLOCKS ? p.plan.tile_items : 0);
   if (std::getenv("SPMV_LOG"))
     std::fprintf(stderr, "libspmv: tuned %s part: kernel=%d tile_items=%d lanes=%d nt=%d remap=%d "
                          "(%.1f us)\n",
@@ -754,6 +795,9 @@ extern "C" spmv_status_t spmv_set_plan(spmv_handle_t h_, int32_t part, const spm
     if (plan->kernel == SPMV_KERNEL_FUSED_PANELS && (p.row_ids.p || h->kind == SPMV_KIND_BATCH ||
                                                      h->kind == SPMV_KIND_SYMMETRIC))
       fail(SPMV_ERR_UNSUPPORTED, "the fused-panel kernel needs a part that covers all rows");
+    if (plan->kernel == SPMV_KERNEL_SORTED_BLOCKS && (p.row_ids.p || h->kind == SPMV_KIND_BATCH ||
+                                                      h->kind == SPMV_KIND_SYMMETRIC))
+      fail(SPMV_ERR_UNSUPPORTED, "the sorted-block kernel needs a part that covers all rows");
     DeviceGuard dg(h->device);
     p.plan = *plan;
     if (h->kind == SPMV_KIND_BATCH)

@@ -56,6 +56,10 @@ spmv_plan_t block_plan(spmv_handle_s *h, int k) {
   auto it = h->block_plans.find(k);
   if (it != h->block_plans.end()) return it->second;
   spmv_plan_t c = p.plan;
+  if (c.kernel == SPMV_KERNEL_SORTED_BLOCKS) {  // one-vector only: blocks use the block kernel
+    c.kernel = SPMV_KERNEL_STREAM;
+    c.tile_items = 4;
+  }
   if (p.plan.block_kt != 0) return c;  // set through spmv_set_plan
   c.block_kt = default_kt(k);
   // the cache file is read once per k and handle, not on every product

@@ -179,6 +179,12 @@ const char *prec_name(int p);
 
 // ---- one CRS part on the device ------------------------------------------------------------
 
+// Sorted-block layout of a part for one chunk size (see SortedDev).
+struct SortedSet {
+  DevBuf cs, col, val, row;
+  int64_t n_blocks = 0, n_chunks = 0;
+};
+
 struct Part {
   int64_t n_rows = 0, nnz = 0;
   DevBuf row_ptr, col, val, row_ids;
@@ -190,6 +196,7 @@ struct Part {
   int64_t d_min = 0, d_max = 0;
   std::map<int, std::pair<DevBuf, int64_t>> tiles;  // tile_items -> (tile starts, count)
   std::map<int, std::pair<DevBuf, int64_t>> runs;   // tile_items -> (run table, staged tiles)
+  std::map<int, SortedSet> sorted;                   // tile_items -> sorted-block layout
   // (panel count, entry capacity) -> rows per workgroup of the fused-panel kernels
   std::map<std::pair<int, int>, int> fused_rows;
   // Rows [0, cut_row) and [cut_row, n_rows) are tiled separately, so each
@@ -341,6 +348,15 @@ int fused_rows_for(spmv_handle_s *h, Part &p, int K, int cap);
 std::vector<std::unique_ptr<Part>> &build_panels(spmv_handle_s *h, Part &p, int K);
 // Drops panel sets no chosen plan uses (each is a full copy of the part).
 void prune_panels(Part &p, const std::vector<int> &keep);
+
+// ---- sorted-block layout (rt_sorted.cpp) ------------------------------------------------------
+
+// The layout of the part for chunks of SB_WG * items slots, built on first
+// use (synchronous: col_idx and val are read back once).
+const SortedSet &sorted_for(spmv_handle_s *h, Part &p, int items);
+SortedDev sorted_dev(spmv_handle_s *h, Part &p, int items);
+// Frees the layouts of every other chunk size.
+void prune_sorted(Part &p, int keep_items);
 
 // ---- batch (rt_batch.cpp) --------------------------------------------------------------------
 

@@ -175,6 +175,28 @@ struct PanelSetDev {
   int K;
   int64_t n_rows;
 };
+// Sorted-block layout of a part (SPMV_KERNEL_SORTED_BLOCKS).  The rows are
+// cut into blocks of sorted_block_rows(prec) rows; block b's entries, sorted
+// by column, fill chunks [cs[b], cs[b+1]) of SB_WG * tile_items slots in
+// which no row appears twice.  Slot s of the layout holds col[s], val[s] and
+// the entry's row within its block, row[s]; an empty slot has row
+// SB_PAD_ROW, val zero and a column some entry of its chunk has.
+constexpr int SB_WG = 1024;
+constexpr int SB_LDS_BYTES = 128 * 1024;
+constexpr uint16_t SB_PAD_ROW = 0xFFFF;
+struct SortedDev {
+  const int64_t *cs;
+  const int32_t *col;
+  const void *val;
+  const uint16_t *row;
+  int64_t n_rows;
+  int64_t n_blocks;
+};
+// Rows per block: the accumulators of a block fill SB_LDS_BYTES of LDS.
+int sorted_block_rows(int prec);
+// tile_items 1, 2 or 4 (chunks of 1024, 2048 or 4096 slots).
+hipError_t launch_spmv_sorted(int prec, const SortedDev &S, int tile_items, int nontemporal,
+                              int xcd_remap, const void *x, void *y, hipStream_t s);
 // Plain product over a panel set: R <= 512 rows per workgroup, tile_items
 // (4, 8, 16) entries per lane for the entries one panel holds in a row block
 // (blocks holding more are summed row by row from global memory).

@@ -48,6 +48,7 @@ SPMV_KERNEL_VECTOR = 2
 SPMV_KERNEL_TILE_GRID = 3
 SPMV_KERNEL_STAGED = 4
 SPMV_KERNEL_FUSED_PANELS = 5
+SPMV_KERNEL_SORTED_BLOCKS = 6
 SPMV_PART_MAIN = 0
 SPMV_PART_NONLOCAL = 1
 

@@ -95,6 +95,32 @@ def test_irregular8M_fp64(c3):
     assert_close(got, ref, den, FP64_TOL, f"irregular 8M FP64, plan {plan}")
 
 
+@pytest.mark.parametrize("items", [1, 2, 4])
+def test_irregular8M_sorted_blocks(c3, items):
+    """The sorted-block kernel at the full size whatever the tuner picks:
+    every row against the oracle, the same bits on two calls, and a layout
+    of about one slot per entry."""
+    import torch
+
+    A, x, ref, den = c3
+    h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, flags=NOTUNE)
+    try:
+        spmv.spmv_set_plan(h, kernel=spmv.SPMV_KERNEL_SORTED_BLOCKS, tile_items=items)
+        chunks = spmv.spmv_get_info(h)["n_tiles"]
+        assert A.nnz <= chunks * 1024 * items <= 1.05 * A.nnz + 489 * 1024 * items, chunks
+        B = to_dev(x, "f64")
+        C1 = torch.zeros(A.n_rows, dtype=B.dtype, device="cuda")
+        C2 = torch.zeros_like(C1)
+        spmv.spmv_run(h, B, C1)
+        spmv.spmv_run(h, B, C2)
+        torch.cuda.synchronize()
+        assert torch.equal(C1, C2)
+        got = C1.cpu().numpy()
+    finally:
+        spmv.spmv_destroy(h)
+    assert_close(got, ref, den, FP64_TOL, f"irregular 8M FP64, sorted blocks, {items} per lane")
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16", "f32f64"])
 @pytest.mark.parametrize("which", ["27pt160", "irregular8M"])
 def test_precision_modes_fullsize(prec, which, c2, c3):
@@ -125,7 +151,16 @@ def test_irregular8M_split_overlap(c3):
         C = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
         spmv.spmv_run(s, B, C, halo)
         torch.cuda.synchronize()
-        assert_close(C.cpu().numpy(), ref, den, FP64_TOL, "split with overlapped halo copy")
+        assert_close(C.cpu().numpy(), ref, den, FP64_TOL,
+                     f"split with overlapped halo copy, local plan {spmv.spmv_get_plan(s)}")
+        # the local part in sorted blocks, whatever the tuner picked
+        spmv.spmv_set_plan(s, spmv.SPMV_PART_MAIN, kernel=spmv.SPMV_KERNEL_SORTED_BLOCKS,
+                           tile_items=2)
+        B = to_dev(Bh, "f64")
+        C.zero_()
+        spmv.spmv_run(s, B, C, halo)
+        torch.cuda.synchronize()
+        assert_close(C.cpu().numpy(), ref, den, FP64_TOL, "split, local part in sorted blocks")
         info = spmv.spmv_get_info(s)
         parts = oracle.split(A.row_ptr, A.col_idx, A.val, hb)
         assert info["nnz_nonlocal"] == parts["nl_col"].size

@@ -45,7 +45,24 @@ PLANS = ([dict(kernel=1, tile_items=e, nontemporal=nt, xcd_remap=rm)
          [dict(kernel=4, tile_items=e, nontemporal=nt) for e in (8, 16) for nt in (0, 1)] +
          [dict(kernel=5, tile_items=e, panels=k, xcd_remap=rm)
           for e in (4, 8, 16) for k in (1, 2, 4, 8) for rm in (0, 1)] +
-         [dict(kernel=5, tile_items=8, panels=4, nontemporal=0)])
+         [dict(kernel=5, tile_items=8, panels=4, nontemporal=0)] +
+         [dict(kernel=6, tile_items=e, xcd_remap=rm) for e in (1, 2, 4) for rm in (0, 1)] +
+         [dict(kernel=6, tile_items=2, nontemporal=0)])
+
+
+def _sorted_refused(A, items, prec="f64"):
+    """Whether the sorted-block layout refuses A: its slots, at least
+    max(ceil(m / Q), longest row) chunks of Q per block of R rows, would
+    exceed four per entry plus one chunk per block plus 2^20."""
+    R = 16384 if prec in ("f64", "f32f64") else 32768
+    Q = 1024 * items
+    lens = np.diff(A.row_ptr).astype(np.int64)
+    bound, nb = 0, 0
+    for r0 in range(0, A.n_rows, R):
+        seg = lens[r0:r0 + R]
+        bound += max(-(-int(seg.sum()) // Q), int(seg.max()) if seg.size else 0) * Q
+        nb += 1
+    return bound > 4 * int(lens.sum()) + nb * Q + (1 << 20)
 
 
 def _pid(p):
@@ -99,12 +116,18 @@ def _long_row_matrix(long_len, n_short=300, n_cols=20000, seed=3):
                          [dict(kernel=1, tile_items=8, panels=k) for k in (2, 8)] +
                          [dict(kernel=2, lanes=64)] +
                          [dict(kernel=4, tile_items=e) for e in (8, 16)] +
-                         [dict(kernel=5, tile_items=e, panels=k) for e in (4, 16) for k in (1, 4)],
+                         [dict(kernel=5, tile_items=e, panels=k) for e in (4, 16) for k in (1, 4)] +
+                         [dict(kernel=6, tile_items=e) for e in (1, 4)],
                          ids=_pid)
 def test_long_rows(long_len, plan):
     A = _long_row_matrix(long_len)
     x = gen.uniform_vector(A.n_cols, gen.rng_for(10, 5))
     ref, den = oracle_ref(A, x)
+    if plan["kernel"] == 6 and _sorted_refused(A, plan["tile_items"]):
+        with pytest.raises(spmv.SpmvError) as ei:
+            gpu_spmv(A, x, plan=plan)
+        assert ei.value.status == spmv.SPMV_ERR_UNSUPPORTED
+        return
     assert_close(gpu_spmv(A, x, plan=plan), ref, den, FP64_TOL, f"long row {long_len}")
 
 
@@ -136,6 +159,15 @@ def test_edge_shapes():
             assert_close(gpu_spmv(A, x, c0, plan=dict(panels=k)), ref, den, FP64_TOL, f"{m}x{n} panels")
             assert_close(gpu_spmv(A, x, c0, plan=dict(kernel=5, panels=k)), ref, den, FP64_TOL,
                          f"{m}x{n} fused panels")
+    # sorted blocks: ragged last block, one row, one column, few columns, empty
+    for (m, n) in ((1000, 3000), (3000, 10), (1, 70000), (70000, 1), (40000, 5), (0, 5)):
+        A = gen.random_crs(m, n, rng, max_len=12)
+        x = gen.uniform_vector(n, rng)
+        c0 = gen.uniform_vector(m, rng)
+        ref, den = oracle_ref(A, x, c0)
+        for e in (1, 4):
+            assert_close(gpu_spmv(A, x, c0, plan=dict(kernel=6, tile_items=e)), ref, den, FP64_TOL,
+                         f"{m}x{n} sorted blocks")
     # 1-based input gives the same product
     A = gen.random_crs(2000, 2000, rng, max_len=20)
     x = gen.uniform_vector(2000, rng)
@@ -175,6 +207,10 @@ def test_determinism():
     A27, x27 = mats()["27pt"]
     st = dict(kernel=spmv.SPMV_KERNEL_STAGED, tile_items=16)
     assert np.array_equal(gpu_spmv(A27, x27, plan=st, runs=2), gpu_spmv(A27, x27, plan=st, runs=2))
+    # sorted blocks: row sums in a fixed chunk order, the same on every call
+    for e in (1, 2, 4):
+        sb = dict(kernel=spmv.SPMV_KERNEL_SORTED_BLOCKS, tile_items=e)
+        assert np.array_equal(gpu_spmv(A, x, plan=sb, runs=3), gpu_spmv(A, x, plan=sb, runs=3))
 
 
 @pytest.mark.parametrize("kernel", [spmv.SPMV_KERNEL_STREAM, spmv.SPMV_KERNEL_TILE_GRID,
@@ -406,9 +442,10 @@ def test_split_run_matches_oracle(schedule):
 @pytest.mark.parametrize("plan", [None, dict(kernel=1, tile_items=8, panels=4),
                                   dict(kernel=2, lanes=8), dict(kernel=1, tile_items=16, tiles_per_group=4),
                                   dict(kernel=4, tile_items=8), dict(kernel=5, tile_items=8, panels=2),
-                                  dict(kernel=5, tile_items=16, panels=1)],
+                                  dict(kernel=5, tile_items=16, panels=1),
+                                  dict(kernel=6, tile_items=2)],
                          ids=["default", "panels4", "vector8", "pipelined", "staged8", "fused2",
-                              "fused1"])
+                              "fused1", "sorted2"])
 def test_local_part_never_reads_halo(plan):
     """The receive area B[h:] holds NaN and no halo is copied: rows without a
     halo entry are computed by the local part alone and must be finite and
@@ -611,6 +648,28 @@ def test_precision_modes(prec, name):
     ref2 = oracle.spmv(A.row_ptr, A.col_idx, v, xr)
     den2 = oracle.abs_spmv(A.row_ptr, A.col_idx, v, xr)
     assert_close(got, ref2, den2, b_same, f"{prec} vs oracle on rounded inputs")
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16", "f32f64"])
+@pytest.mark.parametrize("items", [1, 4])
+def test_precision_modes_sorted_blocks(prec, items):
+    plan = dict(kernel=spmv.SPMV_KERNEL_SORTED_BLOCKS, tile_items=items)
+    for name in ("27pt", "irregular"):
+        A, x = mats()[name]
+        n = int(np.diff(A.row_ptr).max())
+        b_orig, b_same = prec_bounds(prec, n)
+        got = gpu_spmv(A, x, prec=prec, plan=plan)
+        ref, den = oracle_ref(A, x)
+        assert_close(got, ref, den, b_orig, f"{name} {prec} sorted vs FP64 oracle")
+        v, xr = rounded_inputs(A, x, prec)
+        ref2 = oracle.spmv(A.row_ptr, A.col_idx, v, xr)
+        den2 = oracle.abs_spmv(A.row_ptr, A.col_idx, v, xr)
+        assert_close(got, ref2, den2, b_same, f"{name} {prec} sorted vs oracle on rounded inputs")
+    rng = gen.rng_for(16, 1)
+    A = gen.random_crs(70000, 6000, rng, max_len=30, integer_values=True, vmax=8)
+    x = gen.integer_vector(A.n_cols, rng, vmax=8)
+    assert np.array_equal(gpu_spmv(A, x, prec=prec, plan=plan),
+                          oracle.spmv(A.row_ptr, A.col_idx, A.val, x))
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16", "f32f64"])
@@ -942,9 +1001,10 @@ def test_set_plan_validation():
     A, _ = mats()["irregular"]
     h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, flags=NOTUNE)
     try:
-        for bad in (dict(kernel=6), dict(kernel=0), dict(kernel=3), dict(kernel=4, tile_items=4),
+        for bad in (dict(kernel=7), dict(kernel=0), dict(kernel=3), dict(kernel=4, tile_items=4),
                     dict(tile_items=5), dict(lanes=3), dict(block_kt=2),
-                    dict(tiles_per_group=0), dict(tiles_per_group=65), dict(panels=3)):
+                    dict(tiles_per_group=0), dict(tiles_per_group=65), dict(panels=3),
+                    dict(kernel=6, tile_items=8), dict(kernel=6, tile_items=1, panels=2)):
             with pytest.raises(spmv.SpmvError):
                 spmv.spmv_set_plan(h, **bad)
         with pytest.raises(spmv.SpmvError):
@@ -953,6 +1013,28 @@ def test_set_plan_validation():
         spmv.spmv_destroy(h)
     # a destroyed handle is refused without being dereferenced
     assert spmv.load().spmv_run(spmv.ctypes.c_void_p(1), None, None, None, None) == spmv.SPMV_ERR_STATE
+
+
+def test_sorted_blocks_need_a_part_covering_all_rows():
+    A, x = mats()["irregular"]
+    sb = dict(kernel=spmv.SPMV_KERNEL_SORTED_BLOCKS, tile_items=2)
+    a, s = _split_handles(A, gen.halo_begin(A.n_cols))
+    try:
+        with pytest.raises(spmv.SpmvError) as ei:
+            spmv.spmv_set_plan(s, spmv.SPMV_PART_NONLOCAL, **sb)
+        assert ei.value.status == spmv.SPMV_ERR_UNSUPPORTED
+        spmv.spmv_set_plan(s, spmv.SPMV_PART_MAIN, **sb)  # the local part covers all rows
+    finally:
+        spmv.spmv_destroy(s)
+        spmv.spmv_destroy(a)
+    mem = _batch(count=3, seed_extra=4)
+    hb = spmv.spmv_create_batch([(M.row_ptr, M.col_idx, M.val, M.n_cols) for M, _ in mem], flags=NOTUNE)
+    try:
+        with pytest.raises(spmv.SpmvError) as ei:
+            spmv.spmv_set_plan(hb, **sb)
+        assert ei.value.status == spmv.SPMV_ERR_UNSUPPORTED
+    finally:
+        spmv.spmv_destroy(hb)
 
 
 # ---------------------------------------------------------------------------- probes
