@@ -632,14 +632,21 @@ def block_paths(A, steps, warmup, fp64_ms):
     return out
 
 
-def _plan_index_stream(A, plan, fused_rows: int = 512):
+def _plan_index_stream(A, plan, fused_rows: int = 512, sorted_rows: int = 16384):
     """The order in which a plan's launches gather B, as (col_idx order,
     launch cuts): the matrix order without panels; with K diagonal panels
     (the library's slices of col - row) panel after panel, one launch each;
     for the fused-panel kernel row block after row block (fused_rows rows),
-    each block's panels in turn, in one launch."""
+    each block's panels in turn, in one launch; for the sorted-block kernel
+    block after block (sorted_rows rows, FP64), each block's entries by
+    column (the library further deals them into chunks with distinct rows,
+    which moves a few entries by a chunk)."""
     K = int(plan.get("panels", 1))
     n = A.nnz
+    if plan.get("kernel") == 6:
+        rows = np.repeat(np.arange(A.n_rows, dtype=np.int64), np.diff(A.row_ptr))
+        key = (rows // sorted_rows) * (A.n_cols + 1) + A.col_idx
+        return A.col_idx[np.argsort(key, kind="stable")], [0, n]
     if K <= 1:
         return A.col_idx, [0, n]
     rows = np.repeat(np.arange(A.n_rows, dtype=np.int64), np.diff(A.row_ptr))
@@ -1306,7 +1313,7 @@ def summarize_pmc(fetch_dir, write_dir, out_path, plan_json, workload="27pt160",
                 continue
             name = r["Kernel_Name"]
             spmv_kernel = "spmv::" in name and any(
-                k in name for k in ("k_stream", "k_staged", "k_vector", "k_block", "k_fused"))
+                k in name for k in ("k_stream", "k_staged", "k_vector", "k_block", "k_fused", "k_sorted"))
             key = "spmv" if spmv_kernel else ("copy" if "k_copy" in name else None)
             if key is None:
                 continue
@@ -1375,7 +1382,7 @@ def summarize_counters(out_path, command, *dirs):
         for r in _counter_rows(d):
             name = r["Kernel_Name"]
             spmv_kernel = "spmv::" in name and any(
-                k in name for k in ("k_stream", "k_staged", "k_vector", "k_block", "k_fused"))
+                k in name for k in ("k_stream", "k_staged", "k_vector", "k_block", "k_fused", "k_sorted"))
             key = "spmv" if spmv_kernel else ("copy" if "k_copy" in name else None)
             if key is None:
                 continue
