@@ -393,7 +393,9 @@ spmv_status_t spmv_create_sym_crs(int64_t n, int64_t nnz, const int32_t *row_ptr
  *                symmetric handles).  In a block plan (spmv_get_block_plan)
  *                the same walk with the block kernel's column layout.
  *                SPMV_KERNEL_SORTED_BLOCKS: the rows are cut into blocks of
- *                16384 rows (FP64 accumulation) or 32768 (FP32); a
+ *                up to 16384 rows (FP64 accumulation) or 32768 (FP32),
+ *                sized so that a part of about a full round or more (one
+ *                block per CU) comes in whole rounds; a
  *                1024-thread workgroup takes one block, whose entries the
  *                library has sorted by column and dealt into chunks of
  *                1024 * tile_items entries in which no row appears twice,
@@ -575,8 +577,12 @@ spmv_status_t spmv_probe_atomic(double *C, int64_t n, int32_t scattered, int32_t
  *                               rows above the first row that has a nonlocal
  *                               entry, as soon as the halo is in; the
  *                               remaining local rows follow on `stream` (local
- *                               plans of the stream or staged kernel; others
- *                               run as OVERLAP)
+ *                               plans of the stream or staged kernel).  With a
+ *                               sorted-block local plan the blocks that hold
+ *                               nonlocal rows run first, on the nonlocal
+ *                               stream, followed there by the nonlocal kernel,
+ *                               while the other blocks run on `stream` beside
+ *                               them.  Other local plans run as OVERLAP
  *   SPMV_SCHEDULE_SERIAL        halo copy, local and nonlocal kernels in order
  *                               on `stream` (split without asynchrony)
  * Batch handles:

@@ -963,8 +963,8 @@ __global__ __launch_bounds__(WG) void k_block_fused(PanelSetDev S, int64_t n_blo
 // ---------------------------------------------------------------------------
 // Sorted-block kernel.  On a matrix whose rows gather from scattered columns
 // (a wide band), every gather of the stream kernel touches its own cache
-// line.  Here one workgroup takes a block of R rows (R accumulators fill
-// 128 KB of LDS: 16384 rows in FP64, 32768 in FP32) whose entries the host
+// line.  Here one workgroup takes a block of R rows (R accumulators in at
+// most 128 KB of LDS: up to 16384 rows in FP64, 32768 in FP32) whose entries the host
 // sorted by column: the lanes of one load then gather neighbouring columns,
 // several to a line.  The entries come in chunks of Q = 1024 * E slots in
 // which no row appears twice, so each lane adds its product to its row's
@@ -978,14 +978,15 @@ __global__ __launch_bounds__(SB_WG) void k_sorted(SortedDev S, int remap, const 
                                                   void *yv) {
   using V = typename Ty<P>::V;
   using X = typename Ty<P>::X;
-  constexpr int R = SB_LDS_BYTES / (int)sizeof(X);
+  constexpr int RMAX = SB_LDS_BYTES / (int)sizeof(X);
   constexpr int Q = SB_WG * E;
-  __shared__ X acc[R];
+  __shared__ X acc[RMAX];
+  const int R = S.R;  // rows per block, at most RMAX (checked by the launcher)
   const X *__restrict__ x = static_cast<const X *>(xv);
   X *__restrict__ y = static_cast<X *>(yv);
   const V *__restrict__ val = static_cast<const V *>(S.val);
   const int tid = (int)threadIdx.x;
-  const int64_t b = xcd_tile(blockIdx.x, S.n_blocks, remap);
+  const int64_t b = S.b0 + xcd_tile(blockIdx.x, S.b1 - S.b0, remap);
   for (int i = tid; i < R; i += SB_WG) acc[i] = neg_zero<X>();
   lds_barrier();
   const int64_t c0 = S.cs[b], c1 = S.cs[b + 1];
@@ -1460,13 +1461,12 @@ int block_fused_rows_p(int kt, int k, int64_t ldb, int64_t ldc, const void *B, c
 template <int P, int E>
 hipError_t run_sorted(const SortedDev &S, int nt, int remap, const void *x, void *y,
                       hipStream_t s) {
-  if (S.n_blocks <= 0) return hipSuccess;
+  if (S.b1 <= S.b0) return hipSuccess;
+  const dim3 grid((unsigned)(S.b1 - S.b0));
   if (nt)
-    hipLaunchKernelGGL((k_sorted<P, E, true>), dim3((unsigned)S.n_blocks), dim3(SB_WG), 0, s, S,
-                       remap, x, y);
+    hipLaunchKernelGGL((k_sorted<P, E, true>), grid, dim3(SB_WG), 0, s, S, remap, x, y);
   else
-    hipLaunchKernelGGL((k_sorted<P, E, false>), dim3((unsigned)S.n_blocks), dim3(SB_WG), 0, s, S,
-                       remap, x, y);
+    hipLaunchKernelGGL((k_sorted<P, E, false>), grid, dim3(SB_WG), 0, s, S, remap, x, y);
   return hipGetLastError();
 }
 
@@ -1543,8 +1543,10 @@ hipError_t launch_spmv_fused(int prec, const PanelSetDev &S, int R, int tile_ite
 
 hipError_t launch_spmv_sorted(int prec, const SortedDev &S, int tile_items, int nontemporal,
                               int xcd_remap, const void *x, void *y, hipStream_t s) {
-  const int R = sorted_block_rows(prec);
-  if (R <= 0 || S.n_blocks != (S.n_rows + R - 1) / R) return hipErrorInvalidValue;
+  const int rmax = sorted_block_rows(prec);
+  if (S.R < 1 || S.R > rmax || S.n_blocks != (S.n_rows + S.R - 1) / S.R || S.b0 < 0 ||
+      S.b1 > S.n_blocks || S.b0 > S.b1)
+    return hipErrorInvalidValue;
   SPMV_PREC_SWITCH(prec, (dispatch_sorted<PP>(S, tile_items, nontemporal, xcd_remap, x, y, s)))
 }
 

@@ -489,11 +489,26 @@ int fused_rows_for(spmv_handle_s *h, Part &p, int K, int cap) {
 
 bool part_runs_halves(const Part &p) {
   return p.cut_row > 0 && p.cut_row < p.n_rows &&
-         (p.plan.kernel == SPMV_KERNEL_STREAM || p.plan.kernel == SPMV_KERNEL_STAGED);
+         (p.plan.kernel == SPMV_KERNEL_STREAM || p.plan.kernel == SPMV_KERNEL_STAGED ||
+          p.plan.kernel == SPMV_KERNEL_SORTED_BLOCKS);
 }
 
 void run_part_half(spmv_handle_s *h, Part &p, int half, const void *B, void *C, hipStream_t s) {
   if (p.n_rows == 0 || p.nnz == 0) return;
+  if (p.plan.kernel == SPMV_KERNEL_SORTED_BLOCKS) {
+    // halves at block granularity: the blocks wholly above the cut row, and
+    // the rest (the block that holds the cut row goes with the second half)
+    SortedDev S = sorted_dev(h, p, p.plan.tile_items);
+    const int64_t cb = std::min<int64_t>(S.n_blocks, p.cut_row / S.R);
+    if (half == 0)
+      S.b1 = cb;
+    else
+      S.b0 = cb;
+    hip_ok(launch_spmv_sorted(h->prec, S, p.plan.tile_items, p.plan.nontemporal, p.plan.xcd_remap,
+                              B, C, s),
+           "kernel launch");
+    return;
+  }
   const bool staged = p.plan.kernel == SPMV_KERNEL_STAGED;
   const int xb = vec_bytes(h->prec);
   const int items = p.plan.tile_items;

@@ -84,6 +84,26 @@ void block_product(spmv_handle_s *h, int k, const void *B, int64_t ldb, void *C,
 
 void split_compute(spmv_handle_s *h, const void *B, void *C, hipEvent_t nl_after, bool beside,
                    hipStream_t s) {
+  if (beside && part_runs_halves(h->main) && h->nl.n_rows > 0 && h->nl.nnz > 0 &&
+      h->main.plan.kernel == SPMV_KERNEL_SORTED_BLOCKS) {
+    // Sorted blocks run one workgroup per CU, in rounds: the blocks that hold
+    // nonlocal rows go first, on the nonlocal stream, followed there by the
+    // nonlocal part once the halo is in; the other blocks run on s beside
+    // them, so the nonlocal part fills the CUs those blocks leave free.
+    hip_ok(hipStreamWaitEvent(h->nl_stream, h->ev_start, 0), "stream wait");
+    mark(h, T_LOCAL, h->nl_stream);
+    run_part_half(h, h->main, 1, B, C, h->nl_stream);
+    run_part_half(h, h->main, 0, B, C, s);
+    if (nl_after && nl_after != h->ev_start)
+      hip_ok(hipStreamWaitEvent(h->nl_stream, nl_after, 0), "stream wait");
+    mark(h, T_NONLOCAL, h->nl_stream);
+    run_part(h, h->nl, B, C, h->nl_stream);
+    mark(h, T_NONLOCAL + 1, h->nl_stream);
+    hip_ok(hipEventRecord(h->ev_nl_done, h->nl_stream), "event record");
+    hip_ok(hipStreamWaitEvent(s, h->ev_nl_done, 0), "stream wait");
+    mark(h, T_LOCAL + 1, s);
+    return;
+  }
   if (beside && part_runs_halves(h->main) && h->nl.n_rows > 0 && h->nl.nnz > 0) {
     // rows above the first nonlocal row on s, the nonlocal part beside them
     // on its own stream once the halo is in, then the remaining local rows

@@ -21,11 +21,26 @@ const SortedSet &sorted_for(spmv_handle_s *h, Part &p, int items) {
   auto it = p.sorted.find(items);
   if (it != p.sorted.end()) return it->second;
   if (p.row_ids.p) fail(SPMV_ERR_UNSUPPORTED, "the sorted-block kernel needs a part that covers all rows");
-  const int R = sorted_block_rows(h->prec);
+  const int rmax = sorted_block_rows(h->prec);
   const int Q = SB_WG * items;
-  if (R <= 0 || R > int(SB_PAD_ROW)) fail(SPMV_ERR_UNSUPPORTED, "no sorted-block layout for this precision");
+  if (rmax <= 0 || rmax > int(SB_PAD_ROW)) fail(SPMV_ERR_UNSUPPORTED, "no sorted-block layout for this precision");
   const int vb = val_bytes(h->prec);
   const int64_t n = p.n_rows, nnz = p.nnz;
+  // One workgroup per CU at a time.  A part of at least three quarters of
+  // a round (rmax rows on every CU) gets blocks sized to come in whole
+  // rounds of one per CU, the fewest rounds blocks of at most rmax rows
+  // allow, so that no CU idles in the last round; a smaller part gets
+  // blocks of rmax rows.
+  int n_cu = 256;
+  if (hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device) != hipSuccess ||
+      n_cu < 1)
+    n_cu = 256;
+  const int64_t full = int64_t(rmax) * n_cu;
+  int R = rmax;
+  if (4 * n >= 3 * full) {
+    const int64_t rounds = (n + full - 1) / full;
+    R = int(std::min<int64_t>(rmax, (n + rounds * n_cu - 1) / (rounds * n_cu)));
+  }
   const int64_t nb = (n + R - 1) / R;
   std::vector<int32_t> hc(size_t(std::max<int64_t>(nnz, 1)));
   std::vector<unsigned char> hv(size_t(std::max<int64_t>(nnz, 1)) * size_t(vb));
@@ -109,6 +124,7 @@ const SortedSet &sorted_for(spmv_handle_s *h, Part &p, int items) {
       },
       2);
   SortedSet S;
+  S.R = R;
   S.n_blocks = nb;
   S.n_chunks = cs[size_t(nb)];
   upload(S.cs, cs.data(), cs.size() * 8, "sorted-block chunk starts");
@@ -129,6 +145,9 @@ SortedDev sorted_dev(spmv_handle_s *h, Part &p, int items) {
   d.row = S.row.as<const uint16_t>();
   d.n_rows = p.n_rows;
   d.n_blocks = S.n_blocks;
+  d.R = S.R;
+  d.b0 = 0;
+  d.b1 = S.n_blocks;
   return d;
 }
 

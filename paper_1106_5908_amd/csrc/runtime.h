@@ -183,6 +183,7 @@ const char *prec_name(int p);
 struct SortedSet {
   DevBuf cs, col, val, row;
   int64_t n_blocks = 0, n_chunks = 0;
+  int R = 0;  // rows per block
 };
 
 struct Part {

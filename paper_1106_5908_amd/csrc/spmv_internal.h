@@ -176,7 +176,7 @@ struct PanelSetDev {
   int64_t n_rows;
 };
 // Sorted-block layout of a part (SPMV_KERNEL_SORTED_BLOCKS).  The rows are
-// cut into blocks of sorted_block_rows(prec) rows; block b's entries, sorted
+// cut into blocks of R rows (at most sorted_block_rows(prec)); block b's entries, sorted
 // by column, fill chunks [cs[b], cs[b+1]) of SB_WG * tile_items slots in
 // which no row appears twice.  Slot s of the layout holds col[s], val[s] and
 // the entry's row within its block, row[s]; an empty slot has row
@@ -191,8 +191,10 @@ struct SortedDev {
   const uint16_t *row;
   int64_t n_rows;
   int64_t n_blocks;
+  int R;
+  int64_t b0, b1;  // the launch covers blocks [b0, b1) of the n_blocks
 };
-// Rows per block: the accumulators of a block fill SB_LDS_BYTES of LDS.
+// Most rows per block: their accumulators fill SB_LDS_BYTES of LDS.
 int sorted_block_rows(int prec);
 // tile_items 1, 2 or 4 (chunks of 1024, 2048 or 4096 slots).
 hipError_t launch_spmv_sorted(int prec, const SortedDev &S, int tile_items, int nontemporal,

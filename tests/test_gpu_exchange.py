@@ -45,12 +45,16 @@ def _exchange(s, x, hb, prec, n_send, c0=None, pinned=True):
     return C.cpu().numpy().astype(np.float64), send.numpy().copy(), B[hb:].cpu().numpy()
 
 
+@pytest.mark.parametrize("local_plan", [None, dict(kernel=spmv.SPMV_KERNEL_SORTED_BLOCKS, tile_items=2)],
+                         ids=["default", "sorted"])
 @pytest.mark.parametrize("schedule", MODES)
-def test_symmetric_send_list_and_cycle(schedule):
+def test_symmetric_send_list_and_cycle(schedule, local_plan):
     A, x = _irregular()
     hb = gen.halo_begin(A.n_cols)
     a, s = _handles(A, hb)
     try:
+        if local_plan:
+            spmv.spmv_set_plan(s, spmv.SPMV_PART_MAIN, **local_plan)
         n = spmv.spmv_send_list_symmetric(s)
         want = oracle.send_list_symmetric(A.row_ptr, A.col_idx, hb)
         assert n == want.size > 0
@@ -239,9 +243,12 @@ def test_p_shares_exchange_cycle(P):
         assert np.array_equal(sent[q], wanted)
 
 
-def test_phase_timing():
-    """Per-phase events: ordering under both schedules (the nonlocal part after
-    the halo copy, everything after the call's start), and the error cases."""
+@pytest.mark.parametrize("local_plan", [None, dict(kernel=spmv.SPMV_KERNEL_SORTED_BLOCKS, tile_items=2)],
+                         ids=["default", "sorted"])
+def test_phase_timing(local_plan):
+    """Per-phase events: ordering under every schedule (the nonlocal part after
+    the halo copy, everything after the call's start), and the error cases;
+    with the local part in the default plan and in sorted blocks."""
     import torch
 
     A, x = _irregular()
@@ -249,6 +256,8 @@ def test_phase_timing():
     a, s = _handles(A, hb)
     eps = 0.01  # ms of event-timestamp slack
     try:
+        if local_plan:
+            spmv.spmv_set_plan(s, spmv.SPMV_PART_MAIN, **local_plan)
         with pytest.raises(spmv.SpmvError) as ei:
             spmv.spmv_phase_times(s)
         assert ei.value.status == spmv.SPMV_ERR_STATE

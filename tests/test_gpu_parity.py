@@ -540,8 +540,10 @@ def test_split_integer_bit_exact_and_edges():
 @pytest.mark.parametrize("plan", [dict(kernel=1, tile_items=8), dict(kernel=1, tile_items=8, panels=4),
                                   dict(kernel=1, tile_items=4, tiles_per_group=4),
                                   dict(kernel=4, tile_items=8), dict(kernel=2, lanes=8),
-                                  dict(kernel=5, tile_items=8, panels=2)],
-                         ids=["stream", "panels4", "pipelined", "staged", "vector", "fused"])
+                                  dict(kernel=5, tile_items=8, panels=2),
+                                  dict(kernel=6, tile_items=2), dict(kernel=6, tile_items=1)],
+                         ids=["stream", "panels4", "pipelined", "staged", "vector", "fused",
+                              "sorted2", "sorted1"])
 def test_split_local_halves_beside_nonlocal(plan):
     """The banded irregular matrix's nonlocal rows are a tail of the rows, so
     the local part is tiled in two halves cut at the first nonlocal row: the
