@@ -1094,8 +1094,9 @@ def trace_pass(steps: int):
 def phases_pass(steps: int, out_path: str, command: str):
     """Per-call phase events of the split product of the irregular 8M matrix
     (the library's own hipEvents on the GPU clock, spmv_phase_times): `steps`
-    calls of schedule (c) (halo copy overlapped with the local part) and of
-    the exchange cycle (d), each call alone; writes one line per call with
+    calls of schedule (c) (halo copy overlapped with the local part), of (c)
+    with the nonlocal part beside the local part, and of the exchange cycle
+    (d), each call alone; writes one line per call with
     the halo copy, local, nonlocal and send intervals (us from the call's
     start), the share of the copy (and of the send side) that ran while the
     local part ran, and whether the copy ended before the local part and the
@@ -1124,8 +1125,14 @@ def phases_pass(steps: int, out_path: str, command: str):
     summary = {}
     try:
         spmv.spmv_set_phase_timing(s, True)
-        for name, call in (("c_split_overlap", lambda: spmv.spmv_run(s, B, C, halo)),
-                           ("d_exchange_overlap", lambda: spmv.spmv_run_exchange(s, B, C, halo, send))):
+        for name, sched, call in (
+                ("c_split_overlap", spmv.SPMV_SCHEDULE_OVERLAP, lambda: spmv.spmv_run(s, B, C, halo)),
+                ("c_split_beside", spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL,
+                 lambda: spmv.spmv_run(s, B, C, halo)),
+                ("d_exchange_overlap", spmv.SPMV_SCHEDULE_OVERLAP,
+                 lambda: spmv.spmv_run_exchange(s, B, C, halo, send))):
+            spmv.spmv_set_schedule(s, sched)
+            beside = sched == spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL
             for _ in range(3):
                 call()
             torch.cuda.synchronize()
@@ -1142,7 +1149,9 @@ def phases_pass(steps: int, out_path: str, command: str):
                 us = {k: (v[0] * 1e3, v[1] * 1e3) for k, v in t.items() if v}
                 c, lo, nl = us["copy"], us["local"], us["nonlocal"]
                 ok_end = c[1] <= lo[1]
-                ok_after = nl[0] >= max(c[1], lo[1])
+                # beside: the nonlocal part within the local part's span, after the copy
+                ok_after = (nl[0] >= c[1] and lo[0] <= nl[0] and nl[1] <= lo[1]) if beside else \
+                    nl[0] >= max(c[1], lo[1])
                 ends_first += ok_end
                 after += ok_after
                 shares.append(share(c, lo))
@@ -1153,13 +1162,17 @@ def phases_pass(steps: int, out_path: str, command: str):
                              f"nonlocal [{nl[0]:7.1f}, {nl[1]:7.1f}]" +
                              (f"  send [{snd[0]:7.1f}, {snd[1]:7.1f}] {send_shares[-1] * 100:5.1f}%" if snd else "") +
                              f"  copy under local {shares[-1] * 100:5.1f}%")
+            where = ("runs inside the local part's span, after the copy" if beside
+                     else "starts after both")
             lines.append(f"  copy under the local part: median {np.median(shares) * 100:.1f}%, min "
                          f"{min(shares) * 100:.1f}%; the copy ends before the local part in {ends_first} of "
-                         f"{steps} calls; the nonlocal part starts after both in {after} of {steps}" +
+                         f"{steps} calls; the nonlocal part {where} in {after} of {steps}" +
                          (f"; send side under the local part: median {np.median(send_shares) * 100:.1f}%"
                           if send_shares else ""))
             summary[name] = {"calls": steps, "copy_share_under_local_median": float(np.median(shares)),
-                             "copy_ends_before_local": ends_first, "nonlocal_after_both": after}
+                             "copy_ends_before_local": ends_first,
+                             ("nonlocal_inside_local" if beside else "nonlocal_after_both"): after}
+        spmv.spmv_set_schedule(s, spmv.SPMV_SCHEDULE_OVERLAP)
         spmv.spmv_set_phase_timing(s, False)
     finally:
         torch.cuda.synchronize()
