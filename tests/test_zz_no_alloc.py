@@ -109,3 +109,17 @@ def test_noalloc_validation():
         assert ei.value.status == spmv.SPMV_ERR_UNSUPPORTED
     finally:
         spmv.spmv_destroy(h32)
+
+
+def test_noalloc_sorted_block_plan():
+    """The same with the product in sorted blocks: its layout is built when
+    the plan is set, so the noalloc call finds it ready, and its fixed
+    summation order makes the two loops agree bit for bit."""
+    A, _ = gen.workload_c3(N=300_000)
+    q = gen.uniform_vector(A.n_rows, gen.rng_for(44, 3))
+    got, ref = run_both(A, q, 20, plan=dict(kernel=spmv.SPMV_KERNEL_SORTED_BLOCKS, tile_items=2))
+    for g, r in zip(got, ref):
+        assert np.array_equal(g.view(np.uint64), r.view(np.uint64))
+    oa, ob = oracle.lanczos(A.row_ptr, A.col_idx, A.val, q, 20)
+    tol = bound(A.row_ptr, A.val, A.n_rows, 20)
+    assert np.all(np.abs(got[0] - oa) <= tol) and np.all(np.abs(got[1] - ob) <= tol)
