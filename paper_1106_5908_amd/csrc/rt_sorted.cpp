@@ -42,13 +42,6 @@ const SortedSet &sorted_for(spmv_handle_s *h, Part &p, int items) {
     R = int(std::min<int64_t>(rmax, (n + rounds * n_cu - 1) / (rounds * n_cu)));
   }
   const int64_t nb = (n + R - 1) / R;
-  std::vector<int32_t> hc(size_t(std::max<int64_t>(nnz, 1)));
-  std::vector<unsigned char> hv(size_t(std::max<int64_t>(nnz, 1)) * size_t(vb));
-  if (nnz > 0) {
-    hip_ok(hipMemcpy(hc.data(), p.col.p, size_t(nnz) * 4, hipMemcpyDeviceToHost), "col readback");
-    hip_ok(hipMemcpy(hv.data(), p.val.p, size_t(nnz) * size_t(vb), hipMemcpyDeviceToHost),
-           "val readback");
-  }
   const int32_t *rp = p.h_row_ptr.data();
   // A block needs at least max(ceil(m / Q), longest row) chunks: a row of
   // many entries makes the layout mostly empty slots.  Such parts are
@@ -65,6 +58,13 @@ const SortedSet &sorted_for(spmv_handle_s *h, Part &p, int items) {
     if (bound > 4 * nnz + nb * int64_t(Q) + (int64_t(1) << 20))
       fail(SPMV_ERR_UNSUPPORTED, "rows too long for the sorted-block kernel: " + std::to_string(bound) +
                                      " slots for " + std::to_string(nnz) + " entries");
+  }
+  std::vector<int32_t> hc(size_t(std::max<int64_t>(nnz, 1)));
+  std::vector<unsigned char> hv(size_t(std::max<int64_t>(nnz, 1)) * size_t(vb));
+  if (nnz > 0) {
+    hip_ok(hipMemcpy(hc.data(), p.col.p, size_t(nnz) * 4, hipMemcpyDeviceToHost), "col readback");
+    hip_ok(hipMemcpy(hv.data(), p.val.p, size_t(nnz) * size_t(vb), hipMemcpyDeviceToHost),
+           "val readback");
   }
   std::vector<std::vector<int32_t>> placed(static_cast<size_t>(nb));
   parallel_for(
