@@ -465,7 +465,11 @@ spmv_status_t spmv_get_block_plan(spmv_handle_t h, int32_t k, spmv_plan_t *plan)
 /* Times candidate plans for every part of `h` (block products when k > 1)
  * on scratch vectors, keeps the fastest, and records it in the persistent
  * cache (file named by SPMV_TUNE_CACHE, default $HOME/.cache/libspmv_tune.json)
- * keyed by device, precision, k and the row-length statistics.  Synchronous. */
+ * keyed by device, precision, k and the row-length statistics.  On a split
+ * handle whose schedule the caller has not set (spmv_set_schedule), it also
+ * times SPMV_SCHEDULE_OVERLAP against SPMV_SCHEDULE_OVERLAP_NONLOCAL with
+ * the plans chosen (halo resident) and keeps the second if it is at least 1%
+ * faster; the schedule is not cached.  Synchronous. */
 spmv_status_t spmv_tune(spmv_handle_t h, int32_t k, void *stream);
 
 /* ---------------------------------------------------------------------------

@@ -498,6 +498,7 @@ extern "C" spmv_status_t spmv_set_schedule(spmv_handle_t h_, int32_t schedule) {
                            schedule == SPMV_SCHEDULE_BATCH_FLAT);
     if (!ok_split && !ok_batch) fail(SPMV_ERR_INVALID_ARG, "schedule not valid for this handle");
     h->schedule = schedule;
+    h->schedule_set = true;
   });
 }
 

@@ -888,7 +888,25 @@ extern "C" spmv_status_t spmv_tune(spmv_handle_t h_, int32_t k, void *stream) {
     }
     if (k == 1) {
       tune_part(h, h->main, h->kind == SPMV_KIND_SPLIT ? "local" : "main", x.p, y.p, s, tm);
-      if (h->kind == SPMV_KIND_SPLIT) tune_part(h, h->nl, "nonlocal", x.p, y.p, s, tm);
+      if (h->kind == SPMV_KIND_SPLIT) {
+        tune_part(h, h->nl, "nonlocal", x.p, y.p, s, tm);
+        if (!h->schedule_set && part_runs_halves(h->main) && h->nl.nnz > 0) {
+          // the ordered schedule, or the nonlocal part beside the local
+          // part, whichever runs faster with the plans just chosen (the
+          // halo resident); the second must win by 1%
+          auto timed = [&](bool beside) {
+            return tm.median_ms(
+                [&] {
+                  hip_ok(hipEventRecord(h->ev_start, s), "event record");
+                  split_compute(h, x.p, y.p, h->ev_start, beside, s);
+                },
+                s);
+          };
+          const float ordered = timed(false), beside = timed(true);
+          h->schedule = beside < 0.99f * ordered ? SPMV_SCHEDULE_OVERLAP_NONLOCAL
+                                                 : SPMV_SCHEDULE_OVERLAP;
+        }
+      }
       return;
     }
     if (h->kind != SPMV_KIND_PLAIN) fail(SPMV_ERR_UNSUPPORTED, "block tuning needs a plain handle");

@@ -240,6 +240,7 @@ struct spmv_handle_s {
   spmv::rt::Part nl;    // split: nonlocal part
   int64_t halo_begin = 0;
   int schedule = SPMV_SCHEDULE_OVERLAP;
+  bool schedule_set = false;  // set by spmv_set_schedule: spmv_tune then keeps it
   hipStream_t copy_stream = nullptr;
   hipEvent_t ev_start = nullptr, ev_copied = nullptr;
   // split: timing events of the last call's phases (see spmv_set_phase_timing)

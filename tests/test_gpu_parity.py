@@ -425,6 +425,40 @@ def _run_split(A, x, h_begin, schedule, prec="f64", halo="pinned", c0=None, flag
         spmv.spmv_destroy(a)
 
 
+def test_split_tune_schedule_unless_set():
+    """spmv_tune on a split handle may switch it to the nonlocal-beside
+    schedule (the product stays the oracle's); once the caller has set a
+    schedule, tuning keeps it (serial: the copy ends before the local part)."""
+    import torch
+
+    A, x = mats()["irregular"]
+    hb = gen.halo_begin(A.n_cols)
+    ref, den = oracle_ref(A, x)
+    halo = torch.from_numpy(np.ascontiguousarray(x[hb:])).pin_memory()
+    for preset in (None, spmv.SPMV_SCHEDULE_SERIAL):
+        a, s = _split_handles(A, hb)
+        try:
+            spmv.spmv_set_plan(s, spmv.SPMV_PART_MAIN, kernel=spmv.SPMV_KERNEL_SORTED_BLOCKS,
+                               tile_items=2)
+            if preset is not None:
+                spmv.spmv_set_schedule(s, preset)
+            spmv.spmv_tune(s, 1)
+            spmv.spmv_set_phase_timing(s, True)
+            Bh = x.copy()
+            Bh[hb:] = np.nan
+            B = to_dev(Bh, "f64")
+            C = to_dev(np.zeros(A.n_rows), "f64")
+            spmv.spmv_run(s, B, C, halo)
+            torch.cuda.synchronize()
+            assert_close(C.cpu().numpy(), ref, den, FP64_TOL, f"tuned split, preset {preset}")
+            t = spmv.spmv_phase_times(s)
+            if preset == spmv.SPMV_SCHEDULE_SERIAL:
+                assert t["copy"][1] <= t["local"][0] + 0.01
+        finally:
+            spmv.spmv_destroy(s)
+            spmv.spmv_destroy(a)
+
+
 @pytest.mark.parametrize("schedule", [spmv.SPMV_SCHEDULE_OVERLAP, spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL,
                                       spmv.SPMV_SCHEDULE_SERIAL])
 def test_split_run_matches_oracle(schedule):
