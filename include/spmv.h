@@ -397,8 +397,10 @@ spmv_status_t spmv_create_sym_crs(int64_t n, int64_t nnz, const int32_t *row_ptr
  *                sized so that a part of about a full round or more (one
  *                block per CU) comes in whole rounds; a
  *                1024-thread workgroup takes one block, whose entries the
- *                library has sorted by column and dealt into chunks of
- *                1024 * tile_items entries in which no row appears twice,
+ *                library has sorted by column (each block's sweep starting at
+ *                a column common to the blocks that run together) and dealt
+ *                into chunks of 1024 * tile_items entries in which no row
+ *                appears twice,
  *                and adds each entry's product to its row's sum in LDS, chunk
  *                after chunk; C is read and written once.  The lanes of one
  *                load gather neighbouring columns of B, so matrices whose

@@ -6,6 +6,7 @@
 #include <hip/hip_runtime_api.h>
 
 #include <algorithm>
+#include <climits>
 #include <cstring>
 #include <numeric>
 #include <string>
@@ -66,6 +67,23 @@ const SortedSet &sorted_for(spmv_handle_s *h, Part &p, int items) {
     hip_ok(hipMemcpy(hv.data(), p.val.p, size_t(nnz) * size_t(vb), hipMemcpyDeviceToHost),
            "val readback");
   }
+  // The sweeps' common period: the widest column range of a block.
+  std::vector<int64_t> span(static_cast<size_t>(nb), 0);
+  parallel_for(
+      nb,
+      [&](int64_t b0, int64_t b1) {
+        for (int64_t b = b0; b < b1; ++b) {
+          const int64_t p0 = rp[b * R], p1 = rp[std::min<int64_t>(n, b * R + R)];
+          int32_t lo = INT32_MAX, hi = -1;
+          for (int64_t j = p0; j < p1; ++j) {
+            lo = std::min(lo, hc[size_t(j)]);
+            hi = std::max(hi, hc[size_t(j)]);
+          }
+          span[size_t(b)] = p1 > p0 ? int64_t(hi) - lo + 1 : 0;
+        }
+      },
+      2);
+  const int64_t period = span.empty() ? 0 : *std::max_element(span.begin(), span.end());
   std::vector<std::vector<int32_t>> placed(static_cast<size_t>(nb));
   parallel_for(
       nb,
@@ -80,7 +98,8 @@ const SortedSet &sorted_for(spmv_handle_s *h, Part &p, int items) {
             len[size_t(r - r0)] = rp[r + 1] - rp[r];
             for (int64_t j = rp[r]; j < rp[r + 1]; ++j) lrow[size_t(j - p0)] = int32_t(r - r0);
           }
-          placed[size_t(b)] = sorted_place_block(hc.data() + p0, lrow.data(), len.data(), p1 - p0, R, Q);
+          placed[size_t(b)] =
+              sorted_place_block(hc.data() + p0, lrow.data(), len.data(), p1 - p0, R, Q, period);
         }
       },
       2);

@@ -21,7 +21,8 @@ constexpr int64_t kSwapSearch = 64;
 // entries of row r.  Returns the slots of the block's chunks, chunk after
 // chunk, Q per chunk: a block-local entry index, or -1 for an empty slot.
 //
-// N = max(ceil(m / Q), longest row) chunks.  The entries, in column order,
+// N = max(ceil(m / Q), longest row) chunks.  The entries, in column order
+// (rotated to start at a multiple of `period`, see below),
 // go to the first chunk, searching cyclically from the chunk proportional to
 // their rank, that has room and does not yet hold their row.  If every chunk
 // with room holds the row, an entry of a full chunk without it moves to a
@@ -29,7 +30,8 @@ constexpr int64_t kSwapSearch = 64;
 // gets one more chunk.  Each chunk's entries are then laid out in column
 // order, so neighbouring lanes gather neighbouring columns.
 inline std::vector<int32_t> sorted_place_block(const int32_t *col, const int32_t *lrow,
-                                               const int32_t *len, int64_t m, int R, int Q) {
+                                               const int32_t *len, int64_t m, int R, int Q,
+                                               int64_t period = 0) {
   std::vector<int32_t> slots;
   if (m == 0) return slots;
   // entries by column, ties by position (a total order: the layout is the
@@ -39,6 +41,19 @@ inline std::vector<int32_t> sorted_place_block(const int32_t *col, const int32_t
   std::sort(by_col.begin(), by_col.end(), [&](int32_t a, int32_t b) {
     return col[a] != col[b] ? col[a] < col[b] : a < b;
   });
+  // With period > 0 the sweep starts at the first multiple of `period` above
+  // the block's lowest column (when the block reaches that far) and wraps
+  // round: blocks that run at the same time and cover that column then read
+  // the same columns of B at the same time, and share them in L2.
+  if (period > 0) {
+    const int64_t lo = col[by_col[0]], hi = col[by_col[size_t(m - 1)]];
+    const int64_t s0 = (lo + period - 1) / period * period;
+    if (s0 > lo && s0 <= hi) {
+      const auto it = std::lower_bound(by_col.begin(), by_col.end(), s0,
+                                       [&](int32_t a, int64_t v) { return col[a] < v; });
+      std::rotate(by_col.begin(), it, by_col.end());
+    }
+  }
   int64_t maxl = 0;
   for (int r = 0; r < R; ++r) maxl = std::max<int64_t>(maxl, len[r]);
   int64_t N = std::max<int64_t>((m + Q - 1) / Q, maxl);

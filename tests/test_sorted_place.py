@@ -1,8 +1,9 @@
 """Chunk placement of the sorted-block layout (csrc/sorted_place.h), built
 on its own with g++ and checked on the host: every entry of a block lands in
 exactly one slot, no row appears twice in a chunk, each chunk's entries come
-first and in column order, and the chunk count stays at its lower bound
-max(ceil(m / Q), longest row) up to a small slack.  Runs without a GPU."""
+first and in column order (rotated to the sweep's start when a period is
+given), and the chunk count stays at its lower bound max(ceil(m / Q),
+longest row) up to a small slack.  Runs without a GPU."""
 import os
 import shutil
 import subprocess
@@ -19,17 +20,17 @@ HARNESS = r"""
 #include "sorted_place.h"
 int main(int argc, char **argv) {
   FILE *f = std::fopen(argv[1], "rb");
-  int64_t hdr[3];
-  if (std::fread(hdr, 8, 3, f) != 3) return 2;
+  int64_t hdr[4];
+  if (std::fread(hdr, 8, 4, f) != 4) return 2;
   const int R = int(hdr[0]), Q = int(hdr[1]);
-  const int64_t m = hdr[2];
+  const int64_t m = hdr[2], period = hdr[3];
   std::vector<int32_t> col(size_t(m) + 1), lrow(size_t(m) + 1), len(size_t(R), 0);
   if (m > 0 && (std::fread(col.data(), 4, size_t(m), f) != size_t(m) ||
                 std::fread(lrow.data(), 4, size_t(m), f) != size_t(m))) return 3;
   std::fclose(f);
   for (int64_t i = 0; i < m; ++i) len[size_t(lrow[size_t(i)])]++;
   const std::vector<int32_t> s =
-      spmv::rt::sorted_place_block(col.data(), lrow.data(), len.data(), m, R, Q);
+      spmv::rt::sorted_place_block(col.data(), lrow.data(), len.data(), m, R, Q, period);
   FILE *o = std::fopen(argv[2], "wb");
   const int64_t n = int64_t(s.size());
   std::fwrite(&n, 8, 1, o);
@@ -52,11 +53,11 @@ def harness(tmp_path_factory):
     return d, exe
 
 
-def _place(harness, R, Q, col, lrow):
+def _place(harness, R, Q, col, lrow, period=0):
     d, exe = harness
     inp, out = d / "in.bin", d / "out.bin"
     with open(inp, "wb") as f:
-        np.array([R, Q, col.size], dtype=np.int64).tofile(f)
+        np.array([R, Q, col.size, period], dtype=np.int64).tofile(f)
         col.astype(np.int32).tofile(f)
         lrow.astype(np.int32).tofile(f)
     subprocess.check_call([str(exe), str(inp), str(out)])
@@ -65,7 +66,8 @@ def _place(harness, R, Q, col, lrow):
         return np.fromfile(f, dtype=np.int32, count=n)
 
 
-def _check(slots, R, Q, col, lrow, slack):
+def _check(slots, R, Q, col, lrow, slack, start=None):
+    """start: the column the sweep begins at (columns below it come last)."""
     m = col.size
     assert slots.size % Q == 0
     used = slots[slots >= 0]
@@ -80,7 +82,10 @@ def _check(slots, R, Q, col, lrow, slack):
         assert (c[:k] >= 0).all() and (c[k:] < 0).all(), "entries first, then empty slots"
         e = c[:k]
         assert np.unique(lrow[e]).size == k, "no row twice in a chunk"
-        key = col[e].astype(np.int64) * (m + 1) + e
+        c = col[e].astype(np.int64)
+        if start is not None:
+            c = np.where(c >= start, c, c + (1 << 40))
+        key = c * (m + 1) + e
         assert (np.diff(key) > 0).all(), "column order inside a chunk"
     return len(chunks), bound
 
@@ -135,3 +140,24 @@ def test_degenerate_blocks(harness):
     one = np.array([5]), np.array([0])
     s = _place(harness, R, Q, *one)
     assert s.size == Q and s[0] == 0 and (s[1:] < 0).all()
+
+
+def test_sweep_rotated_to_the_period(harness):
+    """With a period, a block's sweep starts at the first multiple of it
+    above the block's lowest column and wraps round; the placement stays
+    valid and at its bound, and the first chunk begins at that column."""
+    rng = np.random.default_rng(11)
+    R, Q = 4096, 2048
+    col, lrow = _band_block(rng, R, 13, 200000)
+    col = col + 1000
+    lo, hi = int(col.min()), int(col.max())
+    for period in (150000, 300000, 10 ** 9):
+        s0 = -(-lo // period) * period
+        rotated = lo < s0 <= hi
+        slots = _place(harness, R, Q, col, lrow, period)
+        _check(slots, R, Q, col, lrow, slack=1, start=s0 if rotated else None)
+        first = slots[0]
+        if rotated:
+            assert col[first] == col[col >= s0].min()
+        else:
+            assert col[first] == lo
