@@ -632,21 +632,47 @@ def block_paths(A, steps, warmup, fp64_ms):
     return out
 
 
-def _plan_index_stream(A, plan, fused_rows: int = 512, sorted_rows: int = 16384):
+def _sorted_block_rows(n_rows: int, n_cu: int, rmax: int = 16384) -> int:
+    """Rows per block of the library's sorted-block layout (FP64 sums): rmax,
+    or for a part of at least three quarters of a round (rmax rows on every
+    CU) the size that makes whole rounds of one block per CU."""
+    full = rmax * n_cu
+    if 4 * n_rows < 3 * full:
+        return rmax
+    rounds = -(-n_rows // full)
+    return min(rmax, -(-n_rows // (rounds * n_cu)))
+
+
+def _plan_index_stream(A, plan, fused_rows: int = 512, n_cu: int = 256):
     """The order in which a plan's launches gather B, as (col_idx order,
     launch cuts): the matrix order without panels; with K diagonal panels
     (the library's slices of col - row) panel after panel, one launch each;
     for the fused-panel kernel row block after row block (fused_rows rows),
     each block's panels in turn, in one launch; for the sorted-block kernel
-    block after block (sorted_rows rows, FP64), each block's entries by
-    column (the library further deals them into chunks with distinct rows,
-    which moves a few entries by a chunk)."""
+    block after block (the library's FP64 block size), each block's entries
+    by column from the first multiple of the widest block span above the
+    block's lowest column, wrapping round (the library further deals them
+    into chunks with distinct rows, which moves a few entries by a chunk)."""
     K = int(plan.get("panels", 1))
     n = A.nnz
     if plan.get("kernel") == 6:
+        R = _sorted_block_rows(A.n_rows, n_cu)
         rows = np.repeat(np.arange(A.n_rows, dtype=np.int64), np.diff(A.row_ptr))
-        key = (rows // sorted_rows) * (A.n_cols + 1) + A.col_idx
-        return A.col_idx[np.argsort(key, kind="stable")], [0, n]
+        blk = rows // R
+        col = A.col_idx.astype(np.int64)
+        nb = int(blk.max()) + 1 if n else 0
+        lo = np.full(nb, np.iinfo(np.int64).max)
+        hi = np.full(nb, -1)
+        np.minimum.at(lo, blk, col)
+        np.maximum.at(hi, blk, col)
+        period = int((hi - lo + 1).max()) if nb else 1
+        s0 = -(-lo // period) * period
+        rot = (s0 > lo) & (s0 <= hi)
+        start = np.where(rot, s0, lo)[blk]
+        # columns at or above the start first, then the wrapped ones
+        key_col = np.where(col >= start, col - start, col - start + (1 << 40))
+        order = np.lexsort((np.arange(n), key_col, blk))
+        return A.col_idx[order], [0, n]
     if K <= 1:
         return A.col_idx, [0, n]
     rows = np.repeat(np.arange(A.n_rows, dtype=np.int64), np.diff(A.row_ptr))
@@ -688,8 +714,10 @@ def gather_ceiling(A, plan, kernel_ms, block_rows, reps: int = 10):
         del idx
     del src
 
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+
     def own(width, pl):
-        order, cuts = _plan_index_stream(A, pl)
+        order, cuts = _plan_index_stream(A, pl, n_cu=n_cu)
         idx = torch.from_numpy(np.ascontiguousarray(order)).cuda()
         Bw = torch.rand(A.n_cols * width, dtype=torch.float64, device="cuda")
         rm = bool(pl.get("xcd_remap", 1))
