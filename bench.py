@@ -656,23 +656,23 @@ def _plan_index_stream(A, plan, fused_rows: int = 512, n_cu: int = 256):
     K = int(plan.get("panels", 1))
     n = A.nnz
     if plan.get("kernel") == 6:
+        if n == 0:
+            return A.col_idx, [0, 0]
         R = _sorted_block_rows(A.n_rows, n_cu)
-        rows = np.repeat(np.arange(A.n_rows, dtype=np.int64), np.diff(A.row_ptr))
-        blk = rows // R
+        bounds = A.row_ptr[np.arange(0, A.n_rows, R)].astype(np.int64)  # first entry per block
+        counts = np.diff(np.append(bounds, n))
+        keep = counts > 0
         col = A.col_idx.astype(np.int64)
-        nb = int(blk.max()) + 1 if n else 0
-        lo = np.full(nb, np.iinfo(np.int64).max)
-        hi = np.full(nb, -1)
-        np.minimum.at(lo, blk, col)
-        np.maximum.at(hi, blk, col)
-        period = int((hi - lo + 1).max()) if nb else 1
+        lo = np.minimum.reduceat(col, bounds[keep])
+        hi = np.maximum.reduceat(col, bounds[keep])
+        period = int((hi - lo + 1).max())
         s0 = -(-lo // period) * period
-        rot = (s0 > lo) & (s0 <= hi)
-        start = np.where(rot, s0, lo)[blk]
-        # columns at or above the start first, then the wrapped ones
-        key_col = np.where(col >= start, col - start, col - start + (1 << 40))
-        order = np.lexsort((np.arange(n), key_col, blk))
-        return A.col_idx[order], [0, n]
+        start = np.where((s0 > lo) & (s0 <= hi), s0, lo)
+        blk = np.repeat(np.arange(keep.sum(), dtype=np.int64), counts[keep])
+        st = start[blk]
+        # per block: columns at or above the start first, then the wrapped ones
+        key = (blk << 42) + np.where(col >= st, col - st, col - st + (1 << 41))
+        return A.col_idx[np.argsort(key, kind="stable")], [0, n]
     if K <= 1:
         return A.col_idx, [0, n]
     rows = np.repeat(np.arange(A.n_rows, dtype=np.int64), np.diff(A.row_ptr))
