@@ -584,11 +584,12 @@ spmv_status_t spmv_probe_atomic(double *C, int64_t n, int32_t scattered, int32_t
  *                               entry, as soon as the halo is in; the
  *                               remaining local rows follow on `stream` (local
  *                               plans of the stream or staged kernel).  With a
- *                               sorted-block local plan the blocks that hold
- *                               nonlocal rows run first, on the nonlocal
- *                               stream, followed there by the nonlocal kernel,
- *                               while the other blocks run on `stream` beside
- *                               them.  Other local plans run as OVERLAP
+ *                               sorted-block local plan the blocks above the
+ *                               first nonlocal row run on `stream`, and on the
+ *                               nonlocal stream the nonlocal kernel runs beside
+ *                               them once the halo is in, followed there by
+ *                               the blocks that hold nonlocal rows.  Other
+ *                               local plans run as OVERLAP
  *   SPMV_SCHEDULE_SERIAL        halo copy, local and nonlocal kernels in order
  *                               on `stream` (split without asynchrony)
  * Batch handles:

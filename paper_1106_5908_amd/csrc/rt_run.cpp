@@ -86,19 +86,20 @@ void split_compute(spmv_handle_s *h, const void *B, void *C, hipEvent_t nl_after
                    hipStream_t s) {
   if (beside && part_runs_halves(h->main) && h->nl.n_rows > 0 && h->nl.nnz > 0 &&
       h->main.plan.kernel == SPMV_KERNEL_SORTED_BLOCKS) {
-    // Sorted blocks run one workgroup per CU, in rounds: the blocks that hold
-    // nonlocal rows go first, on the nonlocal stream, followed there by the
-    // nonlocal part once the halo is in; the other blocks run on s beside
-    // them, so the nonlocal part fills the CUs those blocks leave free.
-    hip_ok(hipStreamWaitEvent(h->nl_stream, h->ev_start, 0), "stream wait");
-    mark(h, T_LOCAL, h->nl_stream);
-    run_part_half(h, h->main, 1, B, C, h->nl_stream);
+    // Sorted blocks run one workgroup per CU, in rounds.  The blocks above
+    // the first nonlocal row start on s; on the nonlocal stream the
+    // nonlocal part runs beside them as soon as the halo is in, and then
+    // the blocks that hold nonlocal rows, which take the CUs the first
+    // blocks leave free in their last round.
+    mark(h, T_LOCAL, s);
     run_part_half(h, h->main, 0, B, C, s);
+    hip_ok(hipStreamWaitEvent(h->nl_stream, h->ev_start, 0), "stream wait");
     if (nl_after && nl_after != h->ev_start)
       hip_ok(hipStreamWaitEvent(h->nl_stream, nl_after, 0), "stream wait");
     mark(h, T_NONLOCAL, h->nl_stream);
     run_part(h, h->nl, B, C, h->nl_stream);
     mark(h, T_NONLOCAL + 1, h->nl_stream);
+    run_part_half(h, h->main, 1, B, C, h->nl_stream);
     hip_ok(hipEventRecord(h->ev_nl_done, h->nl_stream), "event record");
     hip_ok(hipStreamWaitEvent(s, h->ev_nl_done, 0), "stream wait");
     mark(h, T_LOCAL + 1, s);
