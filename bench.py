@@ -487,8 +487,14 @@ def split_paths(A, x, steps, warmup):
     def mode_b():
         spmv.spmv_run(s, B, C, halo)
 
+    # the schedule spmv_tune chose, then each schedule set explicitly
+    tct = time_launches(mode_b, steps, warmup)
+    tkt = time_launches(lambda: spmv.spmv_run(s, B, C), steps, warmup)
     spmv.spmv_set_schedule(s, spmv.SPMV_SCHEDULE_SERIAL)
     tb = time_launches(mode_b, steps, warmup)
+    spmv.spmv_set_schedule(s, spmv.SPMV_SCHEDULE_OVERLAP_MERGED)
+    tc2 = time_launches(mode_b, steps, warmup)
+    tk2 = time_launches(lambda: spmv.spmv_run(s, B, C), steps, warmup)  # merged tail, resident
     spmv.spmv_set_schedule(s, spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL)
     tc1 = time_launches(mode_b, steps, warmup)
     tk1 = time_launches(lambda: spmv.spmv_run(s, B, C), steps, warmup)  # nonlocal beside local, resident
@@ -504,14 +510,21 @@ def split_paths(A, x, steps, warmup):
         "b_split_serial_copy_ms": tb["p50_ms"],
         "c_split_overlap_copy_ms": tc["p50_ms"],
         "c_nonlocal_beside_local_ms": tc1["p50_ms"],
+        "c_merged_tail_ms": tc2["p50_ms"],
+        "c_tuned_schedule_ms": tct["p50_ms"],
         "split_kernels_only_ms": tk["p50_ms"],
         "split_kernels_nonlocal_beside_local_ms": tk1["p50_ms"],
+        "split_kernels_merged_tail_ms": tk2["p50_ms"],
+        "split_kernels_tuned_schedule_ms": tkt["p50_ms"],
         "unsplit_kernel_only_ms": tu["p50_ms"],
         "c_gflops": flops / (tc["p50_ms"] * 1e6),
         "split_model_bytes": mb + split_extra_bytes(info["n_nonlocal_rows"]),
         "split_model_penalty": split_extra_bytes(info["n_nonlocal_rows"]) / mb,
         "split_kernel_penalty": tk["p50_ms"] / tu["p50_ms"] - 1.0,
         "split_kernel_penalty_nonlocal_beside_local": tk1["p50_ms"] / tu["p50_ms"] - 1.0,
+        "split_kernel_penalty_merged_tail": tk2["p50_ms"] / tu["p50_ms"] - 1.0,
+        "split_kernel_penalty_tuned_schedule": tkt["p50_ms"] / tu["p50_ms"] - 1.0,
+        "c_tuned_gflops": flops / (tct["p50_ms"] * 1e6),
         "overlap_speedup_vs_a": ta["p50_ms"] / tc["p50_ms"],
         "overlap_speedup_vs_b": tb["p50_ms"] / tc["p50_ms"],
         "plans": {"local": spmv.spmv_get_plan(s, spmv.SPMV_PART_MAIN),
@@ -520,9 +533,10 @@ def split_paths(A, x, steps, warmup):
     res.update(traffic_report(read_traffic(res["plans"], "irregular8M-split"),
                               res["split_model_bytes"], flops))
     log(f"split: (a) {ta['p50_ms']*1e3:.0f} us, (b) {tb['p50_ms']*1e3:.0f} us, "
-        f"(c) {tc['p50_ms']*1e3:.0f} us (nonlocal beside local {tc1['p50_ms']*1e3:.0f} us), kernels only "
-        f"{tk['p50_ms']*1e3:.0f} us (nonlocal beside local {tk1['p50_ms']*1e3:.0f} us), "
-        f"unsplit {tu['p50_ms']*1e3:.0f} us")
+        f"(c) {tc['p50_ms']*1e3:.0f} us (nonlocal beside local {tc1['p50_ms']*1e3:.0f} us, merged tail "
+        f"{tc2['p50_ms']*1e3:.0f} us, tuned {tct['p50_ms']*1e3:.0f} us), kernels only "
+        f"{tk['p50_ms']*1e3:.0f} us (nonlocal beside local {tk1['p50_ms']*1e3:.0f} us, merged tail "
+        f"{tk2['p50_ms']*1e3:.0f} us, tuned {tkt['p50_ms']*1e3:.0f} us), unsplit {tu['p50_ms']*1e3:.0f} us")
 
     # (d) / (e): the whole exchange cycle of task mode (Sect. 3.5): the send
     # list of the symmetric matrix is packed and copied to pinned host memory
@@ -1123,8 +1137,10 @@ def phases_pass(steps: int, out_path: str, command: str):
     """Per-call phase events of the split product of the irregular 8M matrix
     (the library's own hipEvents on the GPU clock, spmv_phase_times): `steps`
     calls of schedule (c) (halo copy overlapped with the local part), of (c)
-    with the nonlocal part beside the local part, and of the exchange cycle
-    (d), each call alone; writes one line per call with
+    with the nonlocal part beside the local part, of (c) with the last
+    blocks run over local and nonlocal entries together (their interval is
+    reported as the nonlocal one), and of the exchange cycle (d), each call
+    alone; writes one line per call with
     the halo copy, local, nonlocal and send intervals (us from the call's
     start), the share of the copy (and of the send side) that ran while the
     local part ran, and whether the copy ended before the local part and the
@@ -1157,10 +1173,15 @@ def phases_pass(steps: int, out_path: str, command: str):
                 ("c_split_overlap", spmv.SPMV_SCHEDULE_OVERLAP, lambda: spmv.spmv_run(s, B, C, halo)),
                 ("c_split_beside", spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL,
                  lambda: spmv.spmv_run(s, B, C, halo)),
+                ("c_split_merged", spmv.SPMV_SCHEDULE_OVERLAP_MERGED,
+                 lambda: spmv.spmv_run(s, B, C, halo)),
                 ("d_exchange_overlap", spmv.SPMV_SCHEDULE_OVERLAP,
                  lambda: spmv.spmv_run_exchange(s, B, C, halo, send))):
             spmv.spmv_set_schedule(s, sched)
-            beside = sched == spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL
+            sorted_local = spmv.spmv_get_plan(s, spmv.SPMV_PART_MAIN)["kernel"] == \
+                spmv.SPMV_KERNEL_SORTED_BLOCKS
+            beside = sched == spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL or \
+                (sched == spmv.SPMV_SCHEDULE_OVERLAP_MERGED and sorted_local)
             for _ in range(3):
                 call()
             torch.cuda.synchronize()

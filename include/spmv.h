@@ -469,9 +469,10 @@ spmv_status_t spmv_get_block_plan(spmv_handle_t h, int32_t k, spmv_plan_t *plan)
  * cache (file named by SPMV_TUNE_CACHE, default $HOME/.cache/libspmv_tune.json)
  * keyed by device, precision, k and the row-length statistics.  On a split
  * handle whose schedule the caller has not set (spmv_set_schedule), it also
- * times SPMV_SCHEDULE_OVERLAP against SPMV_SCHEDULE_OVERLAP_NONLOCAL with
- * the plans chosen (halo resident) and keeps the second if it is at least 1%
- * faster; the schedule is not cached.  Synchronous. */
+ * times SPMV_SCHEDULE_OVERLAP against SPMV_SCHEDULE_OVERLAP_NONLOCAL and,
+ * with a sorted-block local plan, SPMV_SCHEDULE_OVERLAP_MERGED, with the
+ * plans chosen (halo resident), and keeps the fastest other schedule if it is
+ * at least 1% faster than OVERLAP; the schedule is not cached.  Synchronous. */
 spmv_status_t spmv_tune(spmv_handle_t h, int32_t k, void *stream);
 
 /* ---------------------------------------------------------------------------
@@ -590,6 +591,19 @@ spmv_status_t spmv_probe_atomic(double *C, int64_t n, int32_t scattered, int32_t
  *                               them once the halo is in, followed there by
  *                               the blocks that hold nonlocal rows.  Other
  *                               local plans run as OVERLAP
+ *   SPMV_SCHEDULE_OVERLAP_MERGED  sorted-block local plans: the blocks above
+ *                               the first row that has a nonlocal entry run
+ *                               on `stream` beside the halo copy; the blocks
+ *                               from that row on run, as soon as the halo is
+ *                               in, on the nonlocal stream over their rows'
+ *                               local and nonlocal entries together (a second
+ *                               layout of those blocks, built when the
+ *                               schedule or the plan is set), and no separate
+ *                               nonlocal kernel runs.  Each row's sum still
+ *                               holds its local and nonlocal products, in the
+ *                               merged layout's chunk order (deterministic).
+ *                               Other local plans, or a merged layout refused
+ *                               for rows too long, run as OVERLAP
  *   SPMV_SCHEDULE_SERIAL        halo copy, local and nonlocal kernels in order
  *                               on `stream` (split without asynchrony)
  * Batch handles:
@@ -603,6 +617,7 @@ spmv_status_t spmv_probe_atomic(double *C, int64_t n, int32_t scattered, int32_t
 #define SPMV_SCHEDULE_BATCH_DIRECT 2
 #define SPMV_SCHEDULE_BATCH_FLAT 3
 #define SPMV_SCHEDULE_OVERLAP_NONLOCAL 4
+#define SPMV_SCHEDULE_OVERLAP_MERGED 5
 spmv_status_t spmv_set_schedule(spmv_handle_t h, int32_t schedule);
 
 #ifdef __cplusplus

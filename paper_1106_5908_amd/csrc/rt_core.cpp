@@ -491,12 +491,20 @@ extern "C" spmv_status_t spmv_set_schedule(spmv_handle_t h_, int32_t schedule) {
     spmv_handle_s *h = live(h_);
     const bool ok_split = h->kind == SPMV_KIND_SPLIT &&
                           (schedule == SPMV_SCHEDULE_OVERLAP || schedule == SPMV_SCHEDULE_SERIAL ||
-                           schedule == SPMV_SCHEDULE_OVERLAP_NONLOCAL);
+                           schedule == SPMV_SCHEDULE_OVERLAP_NONLOCAL ||
+                           schedule == SPMV_SCHEDULE_OVERLAP_MERGED);
     const bool ok_batch = h->kind == SPMV_KIND_BATCH &&
                           (schedule == SPMV_SCHEDULE_BATCH_GRAPH ||
                            schedule == SPMV_SCHEDULE_BATCH_DIRECT ||
                            schedule == SPMV_SCHEDULE_BATCH_FLAT);
     if (!ok_split && !ok_batch) fail(SPMV_ERR_INVALID_ARG, "schedule not valid for this handle");
+    if (schedule == SPMV_SCHEDULE_OVERLAP_MERGED &&
+        h->main.plan.kernel == SPMV_KERNEL_SORTED_BLOCKS && h->main.n_rows > 0 &&
+        h->main.nnz > 0) {
+      // built here, so that the products only enqueue work
+      DeviceGuard dg(h->device);
+      (void)merged_tail_for(h, h->main.plan.tile_items);
+    }
     h->schedule = schedule;
     h->schedule_set = true;
   });

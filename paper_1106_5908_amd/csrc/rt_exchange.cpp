@@ -151,7 +151,7 @@ extern "C" spmv_status_t spmv_run_exchange(spmv_handle_t h_, const void *B, void
                "halo copy");
         mark(h, T_COPY + 1, s);
       }
-      split_compute(h, B, C, nullptr, false, s);
+      split_compute(h, B, C, nullptr, SPMV_SCHEDULE_SERIAL, s);
       return;
     }
     hip_ok(hipEventRecord(h->ev_start, s), "event record");
@@ -175,8 +175,7 @@ extern "C" spmv_status_t spmv_run_exchange(spmv_handle_t h_, const void *B, void
       mark(h, T_COPY + 1, h->copy_stream);
       hip_ok(hipEventRecord(h->ev_copied, h->copy_stream), "event record");
     }
-    split_compute(h, B, C, copy ? h->ev_copied : h->ev_start,
-                  h->schedule == SPMV_SCHEDULE_OVERLAP_NONLOCAL, s);
+    split_compute(h, B, C, copy ? h->ev_copied : h->ev_start, h->schedule, s);
     if (ns > 0) hip_ok(hipStreamWaitEvent(s, h->ev_sent, 0), "stream wait");
   });
 }

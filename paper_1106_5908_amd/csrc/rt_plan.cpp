@@ -10,6 +10,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <cstring>
 #include <fstream>
 #include <map>
 #include <mutex>
@@ -819,6 +820,13 @@ extern "C" spmv_status_t spmv_set_plan(spmv_handle_t h_, int32_t part, const spm
       batch_prepare(h);
     else if (h->kind != SPMV_KIND_SYMMETRIC)
       prepare_part(h, p);
+    if (h->kind == SPMV_KIND_SPLIT && &p == &h->main) {
+      // the merged layout of SPMV_SCHEDULE_OVERLAP_MERGED follows the local plan
+      const bool sorted = plan->kernel == SPMV_KERNEL_SORTED_BLOCKS;
+      prune_merged(h, sorted ? plan->tile_items : 0);
+      if (sorted && h->schedule == SPMV_SCHEDULE_OVERLAP_MERGED && p.n_rows > 0 && p.nnz > 0)
+        (void)merged_tail_for(h, plan->tile_items);
+    }
   });
 }
 
@@ -890,22 +898,54 @@ extern "C" spmv_status_t spmv_tune(spmv_handle_t h_, int32_t k, void *stream) {
       tune_part(h, h->main, h->kind == SPMV_KIND_SPLIT ? "local" : "main", x.p, y.p, s, tm);
       if (h->kind == SPMV_KIND_SPLIT) {
         tune_part(h, h->nl, "nonlocal", x.p, y.p, s, tm);
+        const bool sorted = h->main.plan.kernel == SPMV_KERNEL_SORTED_BLOCKS;
+        if (!sorted) prune_merged(h, 0);
         if (!h->schedule_set && part_runs_halves(h->main) && h->nl.nnz > 0) {
-          // the ordered schedule, or the nonlocal part beside the local
-          // part, whichever runs faster with the plans just chosen (the
-          // halo resident); the second must win by 1%
-          auto timed = [&](bool beside) {
-            return tm.median_ms(
-                [&] {
-                  hip_ok(hipEventRecord(h->ev_start, s), "event record");
-                  split_compute(h, x.p, y.p, h->ev_start, beside, s);
-                },
-                s);
+          // the ordered schedule, the nonlocal part beside the local part,
+          // or (sorted-block local plans) the last blocks over local and
+          // nonlocal entries together, whichever runs fastest with the
+          // plans just chosen, the halo copied in from a pinned buffer of
+          // the tuner's own (a schedule that waits for the halo longer
+          // shows it); another than the ordered one must win by 1%
+          const int64_t n_halo = h->n_cols - h->halo_begin;
+          const size_t hb = size_t(std::max<int64_t>(n_halo, 1)) * size_t(vec_bytes(h->prec));
+          void *pin = nullptr;
+          hip_ok(hipHostMalloc(&pin, hb, hipHostMallocDefault), "pinned tune halo");
+          struct PinFree {
+            void *p;
+            ~PinFree() { (void)hipHostFree(p); }
+          } pin_free{pin};
+          std::memset(pin, 0, hb);
+          struct Restore {  // the caller's schedule again if a trial fails
+            spmv_handle_s *h;
+            int saved;
+            bool done;
+            ~Restore() {
+              if (!done) h->schedule = saved;
+            }
+          } restore{h, h->schedule, false};
+          auto timed = [&](int schedule) {
+            h->schedule = schedule;
+            return tm.median_ms([&] { split_run(h, x.p, y.p, n_halo > 0 ? pin : nullptr, s); }, s);
           };
-          const float ordered = timed(false), beside = timed(true);
-          h->schedule = beside < 0.99f * ordered ? SPMV_SCHEDULE_OVERLAP_NONLOCAL
-                                                 : SPMV_SCHEDULE_OVERLAP;
+          const float ordered = timed(SPMV_SCHEDULE_OVERLAP);
+          float best = 0.99f * ordered;
+          int chosen = SPMV_SCHEDULE_OVERLAP;
+          std::vector<int> others{SPMV_SCHEDULE_OVERLAP_NONLOCAL};
+          if (sorted && merged_tail_for(h, h->main.plan.tile_items))
+            others.push_back(SPMV_SCHEDULE_OVERLAP_MERGED);
+          for (int sc : others) {
+            const float t = timed(sc);
+            if (t < best) {
+              best = t;
+              chosen = sc;
+            }
+          }
+          h->schedule = chosen;
+          restore.done = true;
+          if (chosen != SPMV_SCHEDULE_OVERLAP_MERGED) prune_merged(h, 0);
         }
+        if (sorted) prune_merged(h, h->main.plan.tile_items);
       }
       return;
     }

@@ -82,8 +82,54 @@ void block_product(spmv_handle_s *h, int k, const void *B, int64_t ldb, void *C,
                  s, scale, c.kernel == SPMV_KERNEL_FUSED_PANELS);
 }
 
-void split_compute(spmv_handle_s *h, const void *B, void *C, hipEvent_t nl_after, bool beside,
+void split_compute(spmv_handle_s *h, const void *B, void *C, hipEvent_t nl_after, int schedule,
                    hipStream_t s) {
+  const SortedSet *T = nullptr;
+  if (schedule == SPMV_SCHEDULE_OVERLAP_MERGED && h->main.plan.kernel == SPMV_KERNEL_SORTED_BLOCKS &&
+      h->main.n_rows > 0 && h->main.nnz > 0)
+    T = merged_tail_for(h, h->main.plan.tile_items);
+  if (T) {
+    // The first blocks run from the local layout; the rest, from the merged
+    // layout over their rows' local and nonlocal entries, once the halo is
+    // in.  No separate nonlocal kernel runs.  When the first blocks are
+    // whole rounds (one block per CU), the rest follow on s as one launch,
+    // so that every round sweeps B as in the unsplit product; otherwise
+    // they run on the nonlocal stream, on the CUs the first blocks leave
+    // free.
+    mark(h, T_LOCAL, s);
+    SortedDev u = sorted_dev(h, h->main, h->main.plan.tile_items);
+    u.b1 = T->b_first;
+    hip_ok(launch_spmv_sorted(h->prec, u, h->main.plan.tile_items, h->main.plan.nontemporal,
+                              h->main.plan.xcd_remap, B, C, s),
+           "kernel launch");
+    const bool ordered = T->after_rounds;
+    hipStream_t t = ordered ? s : h->nl_stream;
+    if (!ordered) hip_ok(hipStreamWaitEvent(t, h->ev_start, 0), "stream wait");
+    if (nl_after && nl_after != h->ev_start)
+      hip_ok(hipStreamWaitEvent(t, nl_after, 0), "stream wait");
+    mark(h, T_NONLOCAL, t);
+    SortedDev d;
+    d.cs = T->cs.as<const int64_t>();
+    d.col = T->col.as<const int32_t>();
+    d.val = T->val.p;
+    d.row = T->row.as<const uint16_t>();
+    d.n_rows = h->main.n_rows;
+    d.n_blocks = T->n_blocks;
+    d.R = T->R;
+    d.b0 = T->b_first;
+    d.b1 = T->n_blocks;
+    hip_ok(launch_spmv_sorted(h->prec, d, h->main.plan.tile_items, h->main.plan.nontemporal,
+                              h->main.plan.xcd_remap, B, C, t),
+           "kernel launch");
+    mark(h, T_NONLOCAL + 1, t);
+    if (!ordered) {
+      hip_ok(hipEventRecord(h->ev_nl_done, t), "event record");
+      hip_ok(hipStreamWaitEvent(s, h->ev_nl_done, 0), "stream wait");
+    }
+    mark(h, T_LOCAL + 1, s);
+    return;
+  }
+  const bool beside = schedule == SPMV_SCHEDULE_OVERLAP_NONLOCAL;
   if (beside && part_runs_halves(h->main) && h->nl.n_rows > 0 && h->nl.nnz > 0 &&
       h->main.plan.kernel == SPMV_KERNEL_SORTED_BLOCKS) {
     // Sorted blocks run one workgroup per CU, in rounds.  The blocks above
@@ -129,6 +175,41 @@ void split_compute(spmv_handle_s *h, const void *B, void *C, hipEvent_t nl_after
   mark(h, T_NONLOCAL + 1, s);
 }
 
+void split_run(spmv_handle_s *h, const void *B, void *C, const void *B_halo_host, hipStream_t s) {
+  const int64_t n_halo = h->n_cols - h->halo_begin;
+  const size_t vb = size_t(vec_bytes(h->prec));
+  void *recv = static_cast<char *>(const_cast<void *>(B)) + size_t(h->halo_begin) * vb;
+  const bool copy = B_halo_host && n_halo > 0;
+  if (copy) require_pinned(h, B_halo_host, "B_halo_host");
+  begin_timed_call(h, s);
+  if (h->schedule == SPMV_SCHEDULE_SERIAL) {
+    if (copy) {
+      mark(h, T_COPY, s);
+      hip_ok(hipMemcpyAsync(recv, B_halo_host, size_t(n_halo) * vb, hipMemcpyHostToDevice, s),
+             "halo copy");
+      mark(h, T_COPY + 1, s);
+    }
+    split_compute(h, B, C, nullptr, SPMV_SCHEDULE_SERIAL, s);
+  } else {
+    hip_ok(hipEventRecord(h->ev_start, s), "event record");
+    hipEvent_t after = h->ev_start;
+    if (copy) {
+      hip_ok(hipStreamWaitEvent(h->copy_stream, h->ev_start, 0), "stream wait");
+      mark(h, T_COPY, h->copy_stream);
+      hip_ok(hipMemcpyAsync(recv, B_halo_host, size_t(n_halo) * vb, hipMemcpyHostToDevice,
+                            h->copy_stream),
+             "halo copy");
+      mark(h, T_COPY + 1, h->copy_stream);
+      hip_ok(hipEventRecord(h->ev_copied, h->copy_stream), "event record");
+      after = h->ev_copied;
+    }
+    split_compute(h, B, C, after, h->schedule, s);
+  }
+  h->tran[0] = copy;
+  h->tran[1] = h->tran[2] = true;
+  h->tran[3] = false;
+}
+
 }  // namespace rt
 }  // namespace spmv
 
@@ -155,38 +236,7 @@ extern "C" spmv_status_t spmv_run(spmv_handle_t h_, const void *B, void *C,
       return;
     }
     // split handle: local part, halo arrival, nonlocal part (Sect. 3.4 / 3.5)
-    const int64_t n_halo = h->n_cols - h->halo_begin;
-    const size_t vb = size_t(vec_bytes(h->prec));
-    void *recv = static_cast<char *>(const_cast<void *>(B)) + size_t(h->halo_begin) * vb;
-    const bool copy = B_halo_host && n_halo > 0;
-    if (copy) require_pinned(h, B_halo_host, "B_halo_host");
-    begin_timed_call(h, s);
-    if (h->schedule == SPMV_SCHEDULE_SERIAL) {
-      if (copy) {
-        mark(h, T_COPY, s);
-        hip_ok(hipMemcpyAsync(recv, B_halo_host, size_t(n_halo) * vb, hipMemcpyHostToDevice, s),
-               "halo copy");
-        mark(h, T_COPY + 1, s);
-      }
-      split_compute(h, B, C, nullptr, false, s);
-    } else {
-      hip_ok(hipEventRecord(h->ev_start, s), "event record");
-      hipEvent_t after = h->ev_start;
-      if (copy) {
-        hip_ok(hipStreamWaitEvent(h->copy_stream, h->ev_start, 0), "stream wait");
-        mark(h, T_COPY, h->copy_stream);
-        hip_ok(hipMemcpyAsync(recv, B_halo_host, size_t(n_halo) * vb, hipMemcpyHostToDevice,
-                              h->copy_stream),
-               "halo copy");
-        mark(h, T_COPY + 1, h->copy_stream);
-        hip_ok(hipEventRecord(h->ev_copied, h->copy_stream), "event record");
-        after = h->ev_copied;
-      }
-      split_compute(h, B, C, after, h->schedule == SPMV_SCHEDULE_OVERLAP_NONLOCAL, s);
-    }
-    h->tran[0] = copy;
-    h->tran[1] = h->tran[2] = true;
-    h->tran[3] = false;
+    split_run(h, B, C, B_halo_host, s);
   });
 }
 

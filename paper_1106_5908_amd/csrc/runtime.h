@@ -183,7 +183,10 @@ const char *prec_name(int p);
 struct SortedSet {
   DevBuf cs, col, val, row;
   int64_t n_blocks = 0, n_chunks = 0;
-  int R = 0;  // rows per block
+  int R = 0;           // rows per block
+  int64_t period = 0;  // the sweeps start at multiples of it
+  int64_t b_first = 0; // blocks before it hold no chunk (a layout of the last blocks only)
+  bool after_rounds = false;  // merged layout: b_first ends whole rounds of one block per CU
 };
 
 struct Part {
@@ -256,6 +259,10 @@ struct spmv_handle_s {
   // rows that have no nonlocal entry) and its completion event
   hipStream_t nl_stream = nullptr;
   hipEvent_t ev_nl_done = nullptr;
+  // split, SPMV_SCHEDULE_OVERLAP_MERGED: chunk multiplier -> layout of the
+  // local part's last blocks over local and nonlocal entries (see
+  // merged_tail_for); a refused layout is kept as one with no blocks
+  std::map<int, spmv::rt::SortedSet> merged;
   // batch
   int32_t count = 0;
   std::vector<int64_t> m_rows, m_cols;
@@ -359,6 +366,17 @@ const SortedSet &sorted_for(spmv_handle_s *h, Part &p, int items);
 SortedDev sorted_dev(spmv_handle_s *h, Part &p, int items);
 // Frees the layouts of every other chunk size.
 void prune_sorted(Part &p, int keep_items);
+// Split handle with a sorted-block local plan: the layout of the local
+// part's last blocks over their rows' local and nonlocal entries together
+// (same block size and sweep period as the local layout).  It starts at the
+// last round boundary (a multiple of the CU count, one block per CU) at or
+// above the block that holds the first nonlocal row (after_rounds), or at
+// that block if fewer than one round precedes it.  Built on first use; null
+// if the layout is refused (rows too long) or the handle has no nonlocal
+// rows.
+const SortedSet *merged_tail_for(spmv_handle_s *h, int items);
+// Frees the merged layouts of every other chunk size (all with keep 0).
+void prune_merged(spmv_handle_s *h, int keep_items);
 
 // ---- batch (rt_batch.cpp) --------------------------------------------------------------------
 
@@ -394,16 +412,24 @@ void begin_timed_call(spmv_handle_s *h, hipStream_t s);
 // pageable memory (a pageable copy is staged by the runtime and does not
 // proceed beside the kernels; nonblocking is not asynchronous, Sect. 3.1).
 void require_pinned(const spmv_handle_s *h, const void *p, const char *what);
-// The local and nonlocal parts of a split handle on stream s.  With `beside`
-// and a local plan that can run its halves (part_runs_halves), the local
-// rows above the first nonlocal row run on s while the nonlocal part runs on
-// the handle's nonlocal stream after `nl_after` (the halo copy's event, or
-// the call's start event), and the remaining local rows follow on s once
-// the nonlocal part is done; otherwise the local part, then (after
-// `nl_after` unless it is null or the start event) the nonlocal part, in
-// order on s.  Either way every row gets its local and nonlocal sums.
-void split_compute(spmv_handle_s *h, const void *B, void *C, hipEvent_t nl_after, bool beside,
+// The local and nonlocal parts of a split handle on stream s.  Under
+// SPMV_SCHEDULE_OVERLAP_NONLOCAL with a local plan that can run its halves
+// (part_runs_halves), the local rows above the first nonlocal row run on s
+// while the nonlocal part runs on the handle's nonlocal stream after
+// `nl_after` (the halo copy's event, or the call's start event), and the
+// remaining local rows follow once the nonlocal part is done.  Under
+// SPMV_SCHEDULE_OVERLAP_MERGED with a sorted-block local plan, the blocks
+// above the first nonlocal row run on s and the blocks from there on run
+// over their local and nonlocal entries together on the nonlocal stream
+// after `nl_after`, with no separate nonlocal kernel.  Otherwise the local
+// part, then (after `nl_after` unless it is null or the start event) the
+// nonlocal part, in order on s.  Either way every row gets its local and
+// nonlocal sums.
+void split_compute(spmv_handle_s *h, const void *B, void *C, hipEvent_t nl_after, int schedule,
                    hipStream_t s);
+// One product of a split handle under its schedule: the halo copy from
+// B_halo_host (pinned; null: the halo is resident) and split_compute.
+void split_run(spmv_handle_s *h, const void *B, void *C, const void *B_halo_host, hipStream_t s);
 
 }  // namespace rt
 }  // namespace spmv

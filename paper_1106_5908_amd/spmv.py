@@ -74,6 +74,7 @@ SPMV_SCHEDULE_BATCH_GRAPH = 0
 SPMV_SCHEDULE_BATCH_DIRECT = 2
 SPMV_SCHEDULE_BATCH_FLAT = 3
 SPMV_SCHEDULE_OVERLAP_NONLOCAL = 4
+SPMV_SCHEDULE_OVERLAP_MERGED = 5
 
 EXPORTED = [
     "spmv_create_crs", "spmv_create_sym_crs", "spmv_split_local_nonlocal", "spmv_run",

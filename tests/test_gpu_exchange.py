@@ -14,7 +14,8 @@ from workloads import gen
 pytestmark = pytest.mark.gpu
 
 NOTUNE = spmv.SPMV_FLAG_NO_TUNE_CACHE
-MODES = [spmv.SPMV_SCHEDULE_OVERLAP, spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL, spmv.SPMV_SCHEDULE_SERIAL]
+MODES = [spmv.SPMV_SCHEDULE_OVERLAP, spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL,
+         spmv.SPMV_SCHEDULE_OVERLAP_MERGED, spmv.SPMV_SCHEDULE_SERIAL]
 
 
 def _irregular():
@@ -286,8 +287,11 @@ def test_phase_timing(local_plan):
                     if ph:
                         assert -eps <= ph[0] <= ph[1] + eps
                 assert t["copy"][1] <= t["nonlocal"][0] + eps
-                if schedule == spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL:
-                    # the nonlocal part runs inside the local part's span, beside its upper rows
+                merged = (schedule == spmv.SPMV_SCHEDULE_OVERLAP_MERGED and local_plan is not None
+                          and local_plan["kernel"] == spmv.SPMV_KERNEL_SORTED_BLOCKS)
+                if schedule == spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL or merged:
+                    # the nonlocal part (merged: the last blocks over local and
+                    # nonlocal entries) runs inside the local part's span
                     assert t["local"][0] <= t["nonlocal"][0] + eps
                     assert t["nonlocal"][1] <= t["local"][1] + eps
                 else:

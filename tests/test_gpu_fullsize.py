@@ -161,6 +161,25 @@ def test_irregular8M_split_overlap(c3):
         spmv.spmv_run(s, B, C, halo)
         torch.cuda.synchronize()
         assert_close(C.cpu().numpy(), ref, den, FP64_TOL, "split, local part in sorted blocks")
+        # every schedule with the sorted local plan; the merged one here
+        # runs its last blocks as one launch after whole rounds (256 blocks
+        # of the local layout precede the first nonlocal row)
+        spmv.spmv_set_phase_timing(s, True)
+        for sch in (spmv.SPMV_SCHEDULE_OVERLAP_MERGED, spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL,
+                    spmv.SPMV_SCHEDULE_SERIAL, spmv.SPMV_SCHEDULE_OVERLAP):
+            spmv.spmv_set_schedule(s, sch)
+            for with_copy in (True, False):
+                B = to_dev(Bh if with_copy else x, "f64")
+                C.zero_()
+                spmv.spmv_run(s, B, C, halo if with_copy else None)
+                torch.cuda.synchronize()
+                assert_close(C.cpu().numpy(), ref, den, FP64_TOL,
+                             f"split, sorted local plan, schedule {sch}, copy {with_copy}")
+                t = spmv.spmv_phase_times(s)
+                if with_copy and sch == spmv.SPMV_SCHEDULE_OVERLAP_MERGED:
+                    assert t["copy"][1] <= t["nonlocal"][0] + 0.01
+                    assert t["local"][0] <= t["nonlocal"][0] and t["nonlocal"][1] <= t["local"][1] + 0.01
+        spmv.spmv_set_phase_timing(s, False)
         info = spmv.spmv_get_info(s)
         parts = oracle.split(A.row_ptr, A.col_idx, A.val, hb)
         assert info["nnz_nonlocal"] == parts["nl_col"].size

@@ -9,7 +9,7 @@ import pytest
 
 import oracle
 from gpu_util import (FP64_TOL, assert_close, gpu_spmv, oracle_ref, prec_bounds, rounded_inputs,
-                      to_dev)
+                      to_dev, torch_dtype)
 from paper_1106_5908_amd import spmv
 from workloads import gen
 
@@ -460,7 +460,7 @@ def test_split_tune_schedule_unless_set():
 
 
 @pytest.mark.parametrize("schedule", [spmv.SPMV_SCHEDULE_OVERLAP, spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL,
-                                      spmv.SPMV_SCHEDULE_SERIAL])
+                                      spmv.SPMV_SCHEDULE_OVERLAP_MERGED, spmv.SPMV_SCHEDULE_SERIAL])
 def test_split_run_matches_oracle(schedule):
     A, x = mats()["irregular"]
     h_begin = gen.halo_begin(A.n_cols)
@@ -566,7 +566,7 @@ def test_split_integer_bit_exact_and_edges():
     exact = oracle.spmv(A.row_ptr, A.col_idx, A.val, x)
     for h_begin in (0, 1, 18800, 19999, 20000):
         for sch in (spmv.SPMV_SCHEDULE_OVERLAP, spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL,
-                    spmv.SPMV_SCHEDULE_SERIAL):
+                    spmv.SPMV_SCHEDULE_OVERLAP_MERGED, spmv.SPMV_SCHEDULE_SERIAL):
             got, _ = _run_split(A, x, h_begin, sch)
             assert np.array_equal(got, exact), (h_begin, sch)
 
@@ -584,7 +584,8 @@ def test_split_local_halves_beside_nonlocal(plan):
     upper half runs while the nonlocal part runs on its own stream.  Its tile
     table has a tile starting exactly at that row, and on integer data every
     schedule gives the oracle's product bit for bit (with C0); plans that
-    cannot run halves (vector, fused) take the ordered path."""
+    cannot run halves (vector, fused) take the ordered path, and so do plans
+    other than sorted blocks under the merged schedule."""
     import torch
 
     A, _ = mats()["irregular"]
@@ -606,7 +607,7 @@ def test_split_local_halves_beside_nonlocal(plan):
             assert first_nl in set(tiles[:, 0].tolist())
         halo = torch.from_numpy(np.ascontiguousarray(x[h_begin:])).pin_memory()
         for sch in (spmv.SPMV_SCHEDULE_OVERLAP, spmv.SPMV_SCHEDULE_OVERLAP_NONLOCAL,
-                    spmv.SPMV_SCHEDULE_SERIAL):
+                    spmv.SPMV_SCHEDULE_OVERLAP_MERGED, spmv.SPMV_SCHEDULE_SERIAL):
             spmv.spmv_set_schedule(s, sch)
             for with_copy in (True, False):
                 Bh = x.copy()
@@ -617,6 +618,91 @@ def test_split_local_halves_beside_nonlocal(plan):
                 spmv.spmv_run(s, B, C, halo if with_copy else None)
                 torch.cuda.synchronize()
                 assert np.array_equal(C.cpu().numpy(), exact), (sch, with_copy)
+    finally:
+        spmv.spmv_destroy(s)
+        spmv.spmv_destroy(a)
+
+
+@pytest.mark.parametrize("prec", ["f64", "f32", "bf16", "f32f64"])
+@pytest.mark.parametrize("items", [1, 2, 4])
+def test_split_merged_tail(prec, items):
+    """SPMV_SCHEDULE_OVERLAP_MERGED with a sorted-block local plan: the
+    blocks from the one that holds the first nonlocal row run over their
+    rows' local and nonlocal entries together, after the halo copy and
+    inside the local part's span, with no nonlocal kernel.  Checked against
+    the oracle (to the precision's bound) with the band's halo, with halos
+    whose first nonlocal row falls in the second block and in the first
+    (every block merged), and with no halo and an all-halo B (the ordered
+    path); the same bits on a second call."""
+    import torch
+
+    A, x = mats()["irregular"]
+    n = int(np.diff(A.row_ptr).max())
+    b_orig, _ = prec_bounds(prec, n)
+    c0 = gen.uniform_vector(A.n_rows, gen.rng_for(14, 3))
+    ref, den = oracle_ref(A, x, c0)
+    for hb in (gen.halo_begin(A.n_cols), A.n_cols // 4, 10000, A.n_cols, 0):
+        a, s = _split_handles(A, hb, prec)
+        try:
+            spmv.spmv_set_plan(s, spmv.SPMV_PART_MAIN, kernel=spmv.SPMV_KERNEL_SORTED_BLOCKS,
+                               tile_items=items)
+            spmv.spmv_set_schedule(s, spmv.SPMV_SCHEDULE_OVERLAP_MERGED)
+            spmv.spmv_set_phase_timing(s, True)
+            info = spmv.spmv_get_info(s)
+            merged = 0 < hb < A.n_cols and info["nnz_local"] > 0
+            Bh = x.copy()
+            Bh[hb:] = np.nan
+            halo = torch.from_numpy(np.ascontiguousarray(x[hb:])).to(torch_dtype(prec))
+            halo = halo.pin_memory() if hb < A.n_cols else None
+            outs = []
+            for _ in range(2):
+                B = to_dev(Bh, prec)
+                C = to_dev(c0, prec)
+                spmv.spmv_run(s, B, C, halo)
+                torch.cuda.synchronize()
+                outs.append(C.cpu().numpy().astype(np.float64))
+                t = spmv.spmv_phase_times(s)
+                if merged:
+                    eps = 0.01
+                    assert t["copy"][1] <= t["nonlocal"][0] + eps
+                    assert t["local"][0] <= t["nonlocal"][0] + eps
+                    assert t["nonlocal"][1] <= t["local"][1] + eps
+            assert_close(outs[0], ref, den, b_orig, f"merged tail {prec} E={items} halo {hb}")
+            assert np.array_equal(outs[0], outs[1]), f"merged tail {prec} E={items} halo {hb}"
+        finally:
+            spmv.spmv_destroy(s)
+            spmv.spmv_destroy(a)
+
+
+def test_split_merged_tail_integer_exact():
+    """The merged layout on integer data: the oracle's product bit for bit,
+    with the copy and with the halo resident, for every chunk size."""
+    import torch
+
+    A, _ = mats()["irregular"]
+    rng = gen.rng_for(15, 2)
+    A = gen.CRS(A.n_rows, A.n_cols, A.row_ptr, A.col_idx,
+                rng.integers(-9, 10, size=A.nnz).astype(np.float64))
+    x = gen.integer_vector(A.n_cols, rng)
+    c0 = gen.integer_vector(A.n_rows, rng)
+    hb = gen.halo_begin(A.n_cols)
+    exact = oracle.spmv(A.row_ptr, A.col_idx, A.val, x, c0)
+    halo = torch.from_numpy(np.ascontiguousarray(x[hb:])).pin_memory()
+    a, s = _split_handles(A, hb)
+    try:
+        spmv.spmv_set_schedule(s, spmv.SPMV_SCHEDULE_OVERLAP_MERGED)
+        for e in (1, 2, 4):
+            spmv.spmv_set_plan(s, spmv.SPMV_PART_MAIN, kernel=spmv.SPMV_KERNEL_SORTED_BLOCKS,
+                               tile_items=e)
+            for with_copy in (True, False):
+                Bh = x.copy()
+                if with_copy:
+                    Bh[hb:] = np.nan
+                B = to_dev(Bh, "f64")
+                C = to_dev(c0, "f64")
+                spmv.spmv_run(s, B, C, halo if with_copy else None)
+                torch.cuda.synchronize()
+                assert np.array_equal(C.cpu().numpy(), exact), (e, with_copy)
     finally:
         spmv.spmv_destroy(s)
         spmv.spmv_destroy(a)
