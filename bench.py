@@ -149,10 +149,21 @@ def read_traffic(plan, workload: str = "27pt160"):
                 t = json.load(f)
         except (OSError, ValueError):
             continue
-        if (t.get("kernel_sha") == kernel_hash() and t.get("plan") == plan
+        if (t.get("kernel_sha") == kernel_hash() and _same_traffic_plan(t.get("plan"), plan)
                 and t.get("pmc_workload", "27pt160") == workload):
             return t.get("traffic_bytes")
     return None
+
+
+def _same_traffic_plan(a, b):
+    """Plans that launch the same kernels: equal, or, for the split under the
+    merged-tail schedule (which runs no nonlocal kernel), the same local plan."""
+    from paper_1106_5908_amd import spmv
+
+    merged = spmv.SPMV_SCHEDULE_OVERLAP_MERGED
+    if isinstance(a, dict) and isinstance(b, dict) and a.get("schedule") == b.get("schedule") == merged:
+        return a.get("local") == b.get("local")
+    return a == b
 
 
 def traffic_report(traffic, model_bytes: float, flops: float):
@@ -532,6 +543,9 @@ def split_paths(A, x, steps, warmup):
     })
     res.update(traffic_report(read_traffic(res["plans"], "irregular8M-split"),
                               res["split_model_bytes"], flops))
+    merged = traffic_report(read_traffic({**res["plans"], "schedule": spmv.SPMV_SCHEDULE_OVERLAP_MERGED},
+                                         "irregular8M-split"), mb, flops)
+    res.update({f"{k}_merged_tail": v for k, v in merged.items()})
     log(f"split: (a) {ta['p50_ms']*1e3:.0f} us, (b) {tb['p50_ms']*1e3:.0f} us, "
         f"(c) {tc['p50_ms']*1e3:.0f} us (nonlocal beside local {tc1['p50_ms']*1e3:.0f} us, merged tail "
         f"{tc2['p50_ms']*1e3:.0f} us, tuned {tct['p50_ms']*1e3:.0f} us), kernels only "
@@ -1027,8 +1041,9 @@ def pmc_pass(steps: int, plan_json: str | None, workload: str = "27pt160"):
     tuning, so the profile holds only these dispatches), then a copy of 2^27
     doubles (the calibration kernel of known size), each bracketed by
     synchronisation.  Block workloads take the block plan (block_kt set);
-    the split takes {"local": plan, "nonlocal": plan} and runs with the halo
-    resident (no copy)."""
+    the split takes {"local": plan, "nonlocal": plan} (and optionally
+    "schedule": a split schedule) and runs with the halo resident (no
+    copy)."""
     import torch
 
     from paper_1106_5908_amd import spmv
@@ -1045,11 +1060,15 @@ def pmc_pass(steps: int, plan_json: str | None, workload: str = "27pt160"):
         if plan:
             spmv.spmv_set_plan(s, spmv.SPMV_PART_MAIN, **plan["local"])
             spmv.spmv_set_plan(s, spmv.SPMV_PART_NONLOCAL, **plan["nonlocal"])
+            if "schedule" in plan:
+                spmv.spmv_set_schedule(s, plan["schedule"])
         B = dev_vec(x, "f64")
         C = torch.zeros(A.n_rows, dtype=torch.float64, device="cuda")
         call = lambda: spmv.spmv_run(s, B, C)  # noqa: E731
         got = {"local": spmv.spmv_get_plan(s, spmv.SPMV_PART_MAIN),
                "nonlocal": spmv.spmv_get_plan(s, spmv.SPMV_PART_NONLOCAL)}
+        if plan and "schedule" in plan:
+            got["schedule"] = plan["schedule"]
     else:
         if plan:
             spmv.spmv_set_plan(h, **plan)
@@ -1405,7 +1424,11 @@ def summarize_pmc(fetch_dir, write_dir, out_path, plan_json, workload="27pt160",
 
         A, _ = gen.workload_c3()
         n, nnz = A.n_rows, A.nnz
-        if k == 0:
+        from paper_1106_5908_amd import spmv
+
+        # the merged-tail schedule reads every row's entries once, as the
+        # unsplit product does: no row list and no second pass over C
+        if k == 0 and json.loads(plan_json).get("schedule") != spmv.SPMV_SCHEDULE_OVERLAP_MERGED:
             parts = oracle.split(A.row_ptr, A.col_idx, A.val, gen.halo_begin(A.n_cols))
             extra = split_extra_bytes(int(parts["nl_rows"].size))
     wl = "" if workload == "27pt160" else f" --pmc-workload {workload}"
