@@ -412,8 +412,15 @@ spmv_status_t spmv_create_sym_crs(int64_t n, int64_t nnz, const int32_t *row_ptr
  *                For parts that cover all rows (not split nonlocal parts,
  *                batches or symmetric handles); SPMV_ERR_UNSUPPORTED when a
  *                block's longest row would make the layout more than about
- *                four slots per entry.  Block products of a handle with this
- *                plan use the block kernel.
+ *                four slots per entry.  Block products use the block kernel,
+ *                unless block_kt is set: then they run a block form of this
+ *                kernel, with block_kt columns of B per pass, R * block_kt
+ *                sums per block in LDS (R at most 16384 / block_kt rows in
+ *                FP64 and F32/F64, 32768 / block_kt in F32 and BF16), and
+ *                block_kt lanes per slot, each gathering one column of the
+ *                slot's row of B; chunks of (1024 / block_kt) * tile_items
+ *                slots.  Its layout is built when the plan is set.  A plan
+ *                whose layout is refused is not kept.
  *   tile_items   4, 8 or 16 (stream and fused-panel kernels); 8 or 16 (staged);
  *                1, 2 or 4 (sorted-block kernel)
  *   lanes        2, 4, 8, 16, 32 or 64 (vector kernel)

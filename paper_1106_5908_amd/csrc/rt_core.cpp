@@ -411,7 +411,7 @@ extern "C" spmv_status_t spmv_get_info(spmv_handle_t h_, spmv_info_t *info) {
       batch_prepare(h);
       info->n_tiles = h->b_ntiles;
     } else if (h->main.plan.kernel == SPMV_KERNEL_SORTED_BLOCKS) {
-      auto it = h->main.sorted.find(h->main.plan.tile_items);
+      auto it = h->main.sorted.find(std::make_pair(h->main.plan.tile_items, 1));
       info->n_tiles = it == h->main.sorted.end() ? 0 : it->second.n_chunks;
     } else {
       auto it = h->main.tiles.find(h->main.plan.tile_items);

@@ -400,7 +400,11 @@ void prepare_part(spmv_handle_s *h, Part &p) {
     return;
   }
   if (p.plan.kernel == SPMV_KERNEL_SORTED_BLOCKS) {
-    if (p.n_rows > 0 && p.nnz > 0) (void)sorted_for(h, p, items);
+    if (p.n_rows > 0 && p.nnz > 0) {
+      (void)sorted_for(h, p, items);
+      // block products of this plan use the block form of the kernel
+      if (p.plan.block_kt != 0) (void)sorted_for(h, p, items, p.plan.block_kt);
+    }
     return;
   }
   if (p.plan.panels > 1) {
@@ -419,7 +423,7 @@ bool part_prepared(const Part &p, int x_bytes) {
   (void)x_bytes;
   const int items = p.plan.tile_items;
   if (p.plan.kernel == SPMV_KERNEL_SORTED_BLOCKS)
-    return p.n_rows == 0 || p.nnz == 0 || p.sorted.find(items) != p.sorted.end();
+    return p.n_rows == 0 || p.nnz == 0 || p.sorted.find(std::make_pair(items, 1)) != p.sorted.end();
   if (p.plan.kernel == SPMV_KERNEL_FUSED_PANELS) {
     if (p.plan.panels > 1 && p.panel_sets.find(p.plan.panels) == p.panel_sets.end()) return false;
     return p.fused_rows.find(std::make_pair(p.plan.panels, kWG * items - 4)) != p.fused_rows.end();
@@ -709,6 +713,21 @@ bool staged_promising(const spmv_handle_s *h, const Part &p, int items) {
   return 2 * fit > n_sample;
 }
 
+// The sorted-block layouts the part's plans use: (tile_items, 1) for the
+// one-vector plan, (tile_items, block_kt) for block plans of that kernel.
+std::vector<std::pair<int, int>> sorted_keys(spmv_handle_s *h, const Part &p) {
+  std::vector<std::pair<int, int>> keep;
+  if (p.plan.kernel == SPMV_KERNEL_SORTED_BLOCKS) {
+    keep.emplace_back(p.plan.tile_items, 1);
+    if (p.plan.block_kt != 0) keep.emplace_back(p.plan.tile_items, p.plan.block_kt);
+  }
+  if (&p == &h->main)
+    for (auto &bp : h->block_plans)
+      if (bp.second.kernel == SPMV_KERNEL_SORTED_BLOCKS)
+        keep.emplace_back(bp.second.tile_items, bp.second.block_kt);
+  return keep;
+}
+
 void tune_part(spmv_handle_s *h, Part &p, const char *name, void *x, void *y, hipStream_t s,
                Timer &tm) {
   if (p.n_rows == 0 || p.nnz == 0) return;
@@ -767,7 +786,7 @@ void tune_part(spmv_handle_s *h, Part &p, const char *name, void *x, void *y, hi
   std::vector<int> keep{p.plan.panels};
   for (auto &bp : h->block_plans) keep.push_back(bp.second.panels);
   prune_panels(p, keep);
-  prune_sorted(p, p.plan.kernel == SPMV_KERNEL_SORTED_BLOCKS ? p.plan.tile_items : 0);
+  prune_sorted(p, sorted_keys(h, p));
   if (std::getenv("SPMV_LOG"))
     std::fprintf(stderr, "libspmv: tuned %s part: kernel=%d tile_items=%d lanes=%d nt=%d remap=%d "
                          "(%.1f us)\n",
@@ -815,11 +834,17 @@ extern "C" spmv_status_t spmv_set_plan(spmv_handle_t h_, int32_t part, const spm
                                                       h->kind == SPMV_KIND_SYMMETRIC))
       fail(SPMV_ERR_UNSUPPORTED, "the sorted-block kernel needs a part that covers all rows");
     DeviceGuard dg(h->device);
+    const spmv_plan_t before = p.plan;
     p.plan = *plan;
-    if (h->kind == SPMV_KIND_BATCH)
-      batch_prepare(h);
-    else if (h->kind != SPMV_KIND_SYMMETRIC)
-      prepare_part(h, p);
+    try {
+      if (h->kind == SPMV_KIND_BATCH)
+        batch_prepare(h);
+      else if (h->kind != SPMV_KIND_SYMMETRIC)
+        prepare_part(h, p);
+    } catch (...) {
+      p.plan = before;  // a plan that cannot be prepared (a refused layout) is not kept
+      throw;
+    }
     if (h->kind == SPMV_KIND_SPLIT && &p == &h->main) {
       // the merged layout of SPMV_SCHEDULE_OVERLAP_MERGED follows the local plan
       const bool sorted = plan->kernel == SPMV_KERNEL_SORTED_BLOCKS;
@@ -979,20 +1004,58 @@ extern "C" spmv_status_t spmv_tune(spmv_handle_t h_, int32_t k, void *stream) {
               }
             }
           }
+    // the sorted-block kernel for blocks, for parts of at least half a round
+    // of its blocks (R * kt sums per block), its layout built when tried;
+    // 4 columns per pass only: with 8 or 16 its chunks of distinct rows
+    // shrink to 256-512 slots and it has not been competitive
+    int best_sorted = 0;
+    {
+      int n_cu = 256;
+      (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
+      for (int kt : {4}) {
+        const int R = sorted_block_rows(h->prec) / kt;
+        if (R <= 0 || 2 * p.n_rows < int64_t(R) * std::max(n_cu, 1)) continue;
+        for (int e : {2, 4}) {
+          try {
+            (void)sorted_for(h, p, e, kt);
+          } catch (const Failure &f) {
+            if (f.status == SPMV_ERR_UNSUPPORTED) continue;  // rows too long
+            throw;
+          }
+          const float ms = tm.median_ms(
+              [&] { run_block_part(h, p, kt, 1, 1, 1, k, x.p, k, y.p, k, s, 1.0, false, e); }, s);
+          if (ms < best * 0.99f) {
+            best = ms;
+            best_kt = kt;
+            best_nt = 1;
+            best_pn = 1;
+            best_rm = 1;
+            best_fused = false;
+            best_sorted = e;
+          }
+        }
+      }
+    }
     spmv_plan_t c = p.plan;
     c.block_kt = best_kt;
     c.nontemporal = best_nt;
     c.panels = best_pn;
     c.xcd_remap = best_rm;
-    c.kernel = best_fused ? SPMV_KERNEL_FUSED_PANELS : SPMV_KERNEL_STREAM;
+    c.kernel = best_sorted    ? SPMV_KERNEL_SORTED_BLOCKS
+               : best_fused ? SPMV_KERNEL_FUSED_PANELS
+                            : SPMV_KERNEL_STREAM;
+    if (best_sorted) c.tile_items = best_sorted;
     h->block_plans[k] = c;
     std::vector<int> keep{p.plan.panels};
     for (auto &bp : h->block_plans) keep.push_back(bp.second.panels);
     prune_panels(p, keep);
+    prune_sorted(p, sorted_keys(h, p));
     if (std::getenv("SPMV_LOG"))
       std::fprintf(stderr,
-                   "libspmv: tuned block k=%d: kt=%d nt=%d panels=%d remap=%d fused=%d (%.1f us)\n",
-                   k, best_kt, best_nt, best_pn, best_rm, int(best_fused), best * 1000.0f);
+                   "libspmv: tuned block k=%d: kt=%d nt=%d panels=%d remap=%d fused=%d sorted=%d "
+                   "(%.1f us)\n",
+                   k, best_kt, best_nt, best_pn, best_rm, int(best_fused), best_sorted,
+                   best * 1000.0f);
     if (!(h->flags & SPMV_FLAG_NO_TUNE_CACHE))
       cache_store(tune_key(h->device, h->prec, k, "block", p.n_rows, p.stats), c);
   });

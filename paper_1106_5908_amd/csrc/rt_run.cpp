@@ -3,6 +3,7 @@
 // right-hand sides.
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <string>
 
 #include "runtime.h"
@@ -29,8 +30,17 @@ int default_kt(int k) {
 // The panels are shared with the single-vector plan.
 void run_block_part(spmv_handle_s *h, Part &p, int kt, int nt, int remap, int panels, int k,
                     const void *B, int64_t ldb, void *C, int64_t ldc, hipStream_t s,
-                    double scale, bool fused) {
+                    double scale, bool fused, int sorted_items) {
   if (p.n_rows == 0 || p.nnz == 0) return;
+  if (sorted_items > 0) {
+    // one pass over the layout per kt columns of B and C
+    const SortedDev S = sorted_dev(h, p, sorted_items, kt);
+    for (int j0 = 0; j0 < k; j0 += kt)
+      hip_ok(launch_spmv_sorted_block(h->prec, S, sorted_items, kt, nt, remap, B, ldb, j0,
+                                      std::min(kt, k - j0), C, ldc, scale, s),
+             "block kernel launch");
+    return;
+  }
   if (fused) {
     // 8 entries per lane are staged per panel: rows per workgroup sized so a
     // panel's entries in a block fit them
@@ -56,7 +66,9 @@ spmv_plan_t block_plan(spmv_handle_s *h, int k) {
   auto it = h->block_plans.find(k);
   if (it != h->block_plans.end()) return it->second;
   spmv_plan_t c = p.plan;
-  if (c.kernel == SPMV_KERNEL_SORTED_BLOCKS) {  // one-vector only: blocks use the block kernel
+  // a sorted-block plan serves blocks only with block_kt set; otherwise
+  // blocks use the block kernel
+  if (c.kernel == SPMV_KERNEL_SORTED_BLOCKS && c.block_kt == 0) {
     c.kernel = SPMV_KERNEL_STREAM;
     c.tile_items = 4;
   }
@@ -79,7 +91,8 @@ void block_product(spmv_handle_s *h, int k, const void *B, int64_t ldb, void *C,
                    hipStream_t s, double scale) {
   const spmv_plan_t c = block_plan(h, k);
   run_block_part(h, h->main, c.block_kt, c.nontemporal, c.xcd_remap, c.panels, k, B, ldb, C, ldc,
-                 s, scale, c.kernel == SPMV_KERNEL_FUSED_PANELS);
+                 s, scale, c.kernel == SPMV_KERNEL_FUSED_PANELS,
+                 c.kernel == SPMV_KERNEL_SORTED_BLOCKS ? c.tile_items : 0);
 }
 
 void split_compute(spmv_handle_s *h, const void *B, void *C, hipEvent_t nl_after, int schedule,

@@ -174,12 +174,15 @@ int checked_rmax(spmv_handle_s *h) {
 
 }  // namespace
 
-const SortedSet &sorted_for(spmv_handle_s *h, Part &p, int items) {
-  auto it = p.sorted.find(items);
+const SortedSet &sorted_for(spmv_handle_s *h, Part &p, int items, int kt) {
+  const std::pair<int, int> key(items, kt);
+  auto it = p.sorted.find(key);
   if (it != p.sorted.end()) return it->second;
   if (p.row_ids.p) fail(SPMV_ERR_UNSUPPORTED, "the sorted-block kernel needs a part that covers all rows");
-  const int R = block_rows(h, p.n_rows, checked_rmax(h));
-  const int Q = SB_WG * items;
+  if (kt != 1 && kt != 4 && kt != 8 && kt != 16)
+    fail(SPMV_ERR_INVALID_ARG, "sorted-block layouts take 1, 4, 8 or 16 columns per pass");
+  const int R = block_rows(h, p.n_rows, checked_rmax(h) / kt);
+  const int Q = SB_WG / kt * items;
   const int vb = val_bytes(h->prec);
   const int64_t n = p.n_rows, nnz = p.nnz;
   check_slots(p.h_row_ptr.data(), n, R, Q, 0);
@@ -191,7 +194,7 @@ const SortedSet &sorted_for(spmv_handle_s *h, Part &p, int items) {
            "val readback");
   }
   SortedSet S = build_layout(p.h_row_ptr.data(), hc.data(), hv.data(), vb, n, R, Q, 0, 0);
-  return p.sorted.emplace(items, std::move(S)).first->second;
+  return p.sorted.emplace(key, std::move(S)).first->second;
 }
 
 const SortedSet *merged_tail_for(spmv_handle_s *h, int items) {
@@ -277,8 +280,8 @@ void prune_merged(spmv_handle_s *h, int keep_items) {
   }
 }
 
-SortedDev sorted_dev(spmv_handle_s *h, Part &p, int items) {
-  const SortedSet &S = sorted_for(h, p, items);
+SortedDev sorted_dev(spmv_handle_s *h, Part &p, int items, int kt) {
+  const SortedSet &S = sorted_for(h, p, items, kt);
   SortedDev d;
   d.cs = S.cs.as<const int64_t>();
   d.col = S.col.as<const int32_t>();
@@ -292,9 +295,9 @@ SortedDev sorted_dev(spmv_handle_s *h, Part &p, int items) {
   return d;
 }
 
-void prune_sorted(Part &p, int keep_items) {
+void prune_sorted(Part &p, const std::vector<std::pair<int, int>> &keep) {
   for (auto it = p.sorted.begin(); it != p.sorted.end();) {
-    if (it->first != keep_items)
+    if (std::find(keep.begin(), keep.end(), it->first) == keep.end())
       it = p.sorted.erase(it);
     else
       ++it;

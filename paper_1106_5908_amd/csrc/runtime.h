@@ -200,7 +200,9 @@ struct Part {
   int64_t d_min = 0, d_max = 0;
   std::map<int, std::pair<DevBuf, int64_t>> tiles;  // tile_items -> (tile starts, count)
   std::map<int, std::pair<DevBuf, int64_t>> runs;   // tile_items -> (run table, staged tiles)
-  std::map<int, SortedSet> sorted;                   // tile_items -> sorted-block layout
+  // (tile_items, kt) -> sorted-block layout; kt 1 for one right-hand side,
+  // else the columns of B per pass of the block kernel
+  std::map<std::pair<int, int>, SortedSet> sorted;
   // (panel count, entry capacity) -> rows per workgroup of the fused-panel kernels
   std::map<std::pair<int, int>, int> fused_rows;
   // Rows [0, cut_row) and [cut_row, n_rows) are tiled separately, so each
@@ -362,10 +364,13 @@ void prune_panels(Part &p, const std::vector<int> &keep);
 
 // The layout of the part for chunks of SB_WG * items slots, built on first
 // use (synchronous: col_idx and val are read back once).
-const SortedSet &sorted_for(spmv_handle_s *h, Part &p, int items);
-SortedDev sorted_dev(spmv_handle_s *h, Part &p, int items);
-// Frees the layouts of every other chunk size.
-void prune_sorted(Part &p, int keep_items);
+// For block products (kt = 4, 8 or 16 columns per pass) the chunks hold
+// (SB_WG / kt) * items slots and the blocks at most sorted_block_rows / kt
+// rows.
+const SortedSet &sorted_for(spmv_handle_s *h, Part &p, int items, int kt = 1);
+SortedDev sorted_dev(spmv_handle_s *h, Part &p, int items, int kt = 1);
+// Frees every layout but those listed as (items, kt).
+void prune_sorted(Part &p, const std::vector<std::pair<int, int>> &keep);
 // Split handle with a sorted-block local plan: the layout of the local
 // part's last blocks over their rows' local and nonlocal entries together
 // (same block size and sweep period as the local layout).  It starts at the
@@ -390,9 +395,11 @@ void run_sym(spmv_handle_s *h, const void *B, void *C, hipStream_t s);
 int default_kt(int k);
 // Block product C = C + scale*A*B over a part, or over its diagonal panels
 // in turn when `panels` > 1.  `scale` is 1 or a power of two (exact).
+// sorted_items > 0: the sorted-block kernel for blocks, with that many
+// slots per lane and load step (kt columns per pass; panels ignored).
 void run_block_part(spmv_handle_s *h, Part &p, int kt, int nt, int remap, int panels, int k,
                     const void *B, int64_t ldb, void *C, int64_t ldc, hipStream_t s,
-                    double scale = 1.0, bool fused = false);
+                    double scale = 1.0, bool fused = false, int sorted_items = 0);
 // The plan block products with k columns use on this handle: chosen by
 // spmv_tune, else read from the cache, else the defaults.
 spmv_plan_t block_plan(spmv_handle_s *h, int k);

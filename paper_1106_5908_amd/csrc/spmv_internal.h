@@ -199,6 +199,13 @@ int sorted_block_rows(int prec);
 // tile_items 1, 2 or 4 (chunks of 1024, 2048 or 4096 slots).
 hipError_t launch_spmv_sorted(int prec, const SortedDev &S, int tile_items, int nontemporal,
                               int xcd_remap, const void *x, void *y, hipStream_t s);
+// Columns [j0, j0 + kk) of C += scale * A * B (row-major, kk <= kt) over a
+// sorted-block layout whose chunks hold (1024 / kt) * tile_items slots and
+// whose blocks hold at most sorted_block_rows(prec) / kt rows.
+hipError_t launch_spmv_sorted_block(int prec, const SortedDev &S, int tile_items, int kt,
+                                    int nontemporal, int xcd_remap, const void *B, int64_t ldb,
+                                    int j0, int kk, void *C, int64_t ldc, double scale,
+                                    hipStream_t s);
 // Plain product over a panel set: R <= 512 rows per workgroup, tile_items
 // (4, 8, 16) entries per lane for the entries one panel holds in a row block
 // (blocks holding more are summed row by row from global memory).

@@ -88,6 +88,26 @@ def test_irregular_moments_and_determinism():
     check(A, val, V0, m3, M)
 
 
+@pytest.mark.parametrize("kt", [4, 8])
+def test_irregular_moments_sorted_block_plan(kt):
+    """The block products in sorted blocks (values scaled by +-2 as they are
+    loaded): the moments to the same bound."""
+    import torch
+
+    A, _ = gen.workload_c3(N=100_000)
+    val = scaled(A)
+    R, M = 8, 33
+    V0 = gen.uniform_vector(A.n_rows * R, gen.rng_for(18, 1)).reshape(A.n_rows, R)
+    h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, val, A.n_cols, flags=NOTUNE)
+    try:
+        spmv.spmv_set_plan(h, kernel=spmv.SPMV_KERNEL_SORTED_BLOCKS, tile_items=2, block_kt=kt)
+        assert spmv.spmv_get_block_plan(h, R)["kernel"] == spmv.SPMV_KERNEL_SORTED_BLOCKS
+        got = spmv.spmv_kpm_moments(h, torch.from_numpy(V0).to("cuda"), M).cpu().numpy()
+    finally:
+        spmv.spmv_destroy(h)
+    check(A, val, V0, got, M)
+
+
 def test_integer_first_moments_exact():
     """With integer data the first two moments are exact sums: mu_0 = |v0|^2,
     mu_1 = v0.A v0 (no rounding anywhere below 2^53)."""

@@ -935,6 +935,90 @@ def test_block_fused_integer_exact_long_rows(k, panels):
         assert np.array_equal(got, want), prec
 
 
+@pytest.mark.parametrize("items", [1, 2, 4])
+@pytest.mark.parametrize("kt", [4, 8, 16])
+@pytest.mark.parametrize("k", [1, 3, 4, 8, 16, 17])
+def test_block_sorted(k, kt, items):
+    """The sorted-block kernel for blocks (plan kernel 6 with block_kt: R * kt
+    sums per block in LDS, kt lanes per slot, one pass per kt columns)
+    against the oracle, with C0 and padded leading dimensions; a second call
+    adds the same bits again (C0 + 2 A X)."""
+    import torch
+
+    A, _ = mats()["irregular"]
+    X = gen.block_rhs(A.n_cols, k, extra=21)
+    c0 = gen.block_rhs(A.n_rows, k, extra=22)
+    plan = dict(kernel=6, tile_items=items, block_kt=kt)
+    got, pad = _gpu_block_plan(A, X, plan, c0, ldb_pad=1 if k % 2 else 2, ldc_pad=3)
+    assert np.all(pad == 0)
+    ref = oracle.spmv_block(A.row_ptr, A.col_idx, A.val, X, c0)
+    for t in range(k):
+        den = oracle.abs_spmv(A.row_ptr, A.col_idx, A.val, X[:, t], c0[:, t])
+        assert_close(got[:, t], ref[:, t], den, FP64_TOL, f"sorted block k={k} kt={kt} E={items} col {t}")
+    h = spmv.spmv_create_crs(A.row_ptr, A.col_idx, A.val, A.n_cols, flags=NOTUNE)
+    try:
+        spmv.spmv_set_plan(h, **plan)
+        B = torch.from_numpy(X).cuda()
+        C1 = torch.zeros((A.n_rows, k), dtype=torch.float64, device="cuda")
+        C2 = torch.zeros((A.n_rows, k), dtype=torch.float64, device="cuda")
+        spmv.spmv_run_block(h, B, C1)
+        spmv.spmv_run_block(h, B, C2)
+        spmv.spmv_run_block(h, B, C2)
+        torch.cuda.synchronize()
+        assert torch.equal(C2, C1 + C1), "two calls add the same bits twice"
+    finally:
+        spmv.spmv_destroy(h)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16", "f32f64"])
+def test_block_sorted_precision(prec):
+    A, _ = mats()["irregular"]
+    k = 8
+    X = gen.block_rhs(A.n_cols, k, extra=23)
+    got, _ = _gpu_block_plan(A, X, dict(kernel=6, tile_items=2, block_kt=4), prec=prec)
+    n = int(np.diff(A.row_ptr).max())
+    b_orig, _ = prec_bounds(prec, n)
+    ref = oracle.spmv_block(A.row_ptr, A.col_idx, A.val, X)
+    for t in range(k):
+        den = oracle.abs_spmv(A.row_ptr, A.col_idx, A.val, X[:, t])
+        assert_close(got[:, t], ref[:, t], den, b_orig, f"sorted block {prec} col {t}")
+
+
+def test_block_sorted_integer_exact_and_edges():
+    """Integer data: bit for bit for every width; a matrix with empty rows
+    and a ragged last block; and a part of rows too long for the layout is
+    refused when the plan is set."""
+    rng = gen.rng_for(17, 3)
+    A = gen.random_crs(70000, 6000, rng, max_len=30, integer_values=True, vmax=8)
+    for k in (1, 5, 16):
+        X = rng.integers(-5, 6, size=(A.n_cols, k)).astype(np.float64)
+        want = oracle.spmv_block(A.row_ptr, A.col_idx, A.val, X)
+        for kt in (4, 16):
+            got, _ = _gpu_block_plan(A, X, dict(kernel=6, tile_items=2, block_kt=kt))
+            assert np.array_equal(got, want), (k, kt)
+    L = _long_row_matrix(3000, n_short=2000, n_cols=5000)
+    if _sorted_refused(L, 2):
+        h = spmv.spmv_create_crs(L.row_ptr, L.col_idx, L.val, L.n_cols, flags=NOTUNE)
+        try:
+            before = spmv.spmv_get_plan(h)
+            with pytest.raises(spmv.SpmvError) as ei:
+                spmv.spmv_set_plan(h, kernel=6, tile_items=2, block_kt=4)
+            assert ei.value.status == spmv.SPMV_ERR_UNSUPPORTED
+            assert spmv.spmv_get_plan(h) == before, "a refused plan is not kept"
+            X = rng.integers(-5, 6, size=(L.n_cols, 3)).astype(np.float64)
+            import torch
+            C = torch.zeros((L.n_rows, 3), dtype=torch.float64, device="cuda")
+            spmv.spmv_run_block(h, torch.from_numpy(X).cuda(), C)
+            torch.cuda.synchronize()
+            Lr = gen.CRS(L.n_rows, L.n_cols, L.row_ptr, L.col_idx, L.val)
+            ref = oracle.spmv_block(Lr.row_ptr, Lr.col_idx, Lr.val, X)
+            for t in range(3):
+                den = oracle.abs_spmv(Lr.row_ptr, Lr.col_idx, Lr.val, X[:, t])
+                assert_close(C.cpu().numpy()[:, t], ref[:, t], den, FP64_TOL, "after a refused plan")
+        finally:
+            spmv.spmv_destroy(h)
+
+
 def test_block_rejects_split_and_bad_k():
     import torch
 
