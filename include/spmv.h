@@ -466,9 +466,11 @@ spmv_status_t spmv_set_plan(spmv_handle_t h, int32_t part, const spmv_plan_t *pl
 
 /* The plan spmv_run_block uses for blocks of k columns on plain handle h: the
  * one spmv_tune chose for this k, else the persistent cache's, else the main
- * part's plan with block_kt = 4, 8 or 16 by k.  Its block_kt, nontemporal,
- * xcd_remap and panels fields apply.  Errors: SPMV_ERR_UNSUPPORTED for other
- * handles, SPMV_ERR_INVALID_ARG for k outside [1, 64] or a NULL plan. */
+ * part's plan (with block_kt = 4, 8 or 16 by k if it has none).  Its kernel
+ * (the block kernel, the fused-panel walk, or the sorted-block kernel's block
+ * form with tile_items), block_kt, nontemporal, xcd_remap and panels fields
+ * apply.  Errors: SPMV_ERR_UNSUPPORTED for other handles, SPMV_ERR_INVALID_ARG
+ * for k outside [1, 64] or a NULL plan. */
 spmv_status_t spmv_get_block_plan(spmv_handle_t h, int32_t k, spmv_plan_t *plan);
 
 /* Times candidate plans for every part of `h` (block products when k > 1)
