@@ -1053,38 +1053,45 @@ __global__ __launch_bounds__(SB_WG) void k_sorted(SortedDev S, int remap, const 
 // ---------------------------------------------------------------------------
 // Sorted-block kernel for a block of right-hand sides: columns [j0, j0 + kk)
 // of row-major B and C per launch (kk <= K).  A block of R rows keeps R * K
-// sums in LDS; K lanes share a slot, lane j gathering B[col][j0 + j], so the
-// K values of one entry come from one contiguous stretch of B.  A chunk is
-// E * (1024 / K) slots with distinct rows, added with a plain LDS
-// read-add-write and closed by a barrier, as in k_sorted; every stored
-// value is multiplied by `scale` first (as in k_block).
+// sums in LDS; K / VW lanes share a slot, lane l gathering the VW columns
+// j0 + l*VW .. + VW - 1 of the slot's row of B (one 16-byte load when
+// VW > 1), so one entry's K values come from one contiguous stretch of B.
+// A chunk of distinct rows is walked in H pieces of E * (1024 * VW / K)
+// slots and closed by a barrier, as in k_sorted; the wide form (VW 2 in
+// FP64, 4 in FP32) takes a chunk in one piece, the one-column form in VW
+// pieces, so both read the same layout.  Every stored value is multiplied
+// by `scale` first (as in k_block).  The layout is streamed with the
+// nontemporal hint: it is read once per pass.
 // ---------------------------------------------------------------------------
-template <int P, int E, int K, bool NT>
+template <int P, int E, int K, int VW, int H>
 __global__ __launch_bounds__(SB_WG) void k_sorted_blk(SortedDev S, int remap, const void *xv,
                                                       int64_t ldb, void *yv, int64_t ldc, int j0,
                                                       int kk, typename Ty<P>::X scale) {
   using V = typename Ty<P>::V;
   using X = typename Ty<P>::X;
+  constexpr bool NT = true;
   constexpr int RMAX = SB_LDS_BYTES / (int)sizeof(X);
-  constexpr int SPW = SB_WG / K;  // slots per load step
-  constexpr int Q = SPW * E;      // slots per chunk
-  __shared__ X acc[RMAX];
+  constexpr int LPS = K / VW;          // lanes per slot
+  constexpr int SPW = SB_WG / LPS;     // slots per load step
+  constexpr int PQ = SPW * E;          // slots per piece; a chunk is H pieces
+  static_assert(K % VW == 0, "a lane's columns lie in one pass");
+  __shared__ __align__(16) X acc[RMAX];
   const int R = S.R;  // rows per block; R * K <= RMAX (checked by the launcher)
   const X *__restrict__ x = static_cast<const X *>(xv);
   X *__restrict__ y = static_cast<X *>(yv);
   const V *__restrict__ val = static_cast<const V *>(S.val);
   const int tid = (int)threadIdx.x;
-  const int j = tid % K, sl = tid / K;
-  const bool jin = j < kk;
+  const int jb = (tid % LPS) * VW, sl = tid / LPS;
+  const bool jin = jb < kk;  // kk is a multiple of VW
   const int64_t b = S.b0 + xcd_tile(blockIdx.x, S.b1 - S.b0, remap);
   for (int i = tid; i < R * K; i += SB_WG) acc[i] = neg_zero<X>();
   lds_barrier();
-  const int64_t c0 = S.cs[b], c1 = S.cs[b + 1];
-  auto load = [&](int64_t c, int (&cc)[E], V (&vv)[E], int (&rr)[E]) {
-    if (c < c1) {
+  const int64_t p0 = S.cs[b] * H, p1 = S.cs[b + 1] * H;
+  auto load = [&](int64_t p, int (&cc)[E], V (&vv)[E], int (&rr)[E]) {
+    if (p < p1) {
 #pragma unroll
       for (int e = 0; e < E; ++e) {
-        const int64_t q = c * Q + (int64_t)e * SPW + sl;
+        const int64_t q = p * PQ + (int64_t)e * SPW + sl;
         cc[e] = ld<int32_t, NT>(S.col + q);
         vv[e] = ld<V, NT>(val + q);
         rr[e] = (int)ld<uint16_t, NT>(S.row + q);
@@ -1098,38 +1105,51 @@ __global__ __launch_bounds__(SB_WG) void k_sorted_blk(SortedDev S, int remap, co
       }
     }
   };
-  auto gather = [&](int64_t c, const int (&cc)[E], X (&g)[E]) {
+  auto gather = [&](int64_t p, const int (&cc)[E], X (&g)[E][VW]) {
 #pragma unroll
-    for (int e = 0; e < E; ++e) g[e] = (c < c1 && jin) ? x[(int64_t)cc[e] * ldb + j0 + j] : X(0);
+    for (int e = 0; e < E; ++e) {
+      if (p < p1 && jin) {
+        load_vec<X, VW>(x + (int64_t)cc[e] * ldb + j0 + jb, g[e]);
+      } else {
+#pragma unroll
+        for (int v = 0; v < VW; ++v) g[e][v] = X(0);
+      }
+    }
   };
   int ca[E], ra[E], cb[E], rb[E];
   V va[E], vb[E];
-  X ga[E], gb[E];
-  load(c0, ca, va, ra);
-  gather(c0, ca, ga);
-  load(c0 + 1, cb, vb, rb);
-  for (int64_t c = c0; c < c1; ++c) {
-    gather(c + 1, cb, gb);
+  X ga[E][VW], gb[E][VW];
+  load(p0, ca, va, ra);
+  gather(p0, ca, ga);
+  load(p0 + 1, cb, vb, rb);
+  for (int64_t p = p0; p < p1; ++p) {
+    gather(p + 1, cb, gb);
     int cn[E], rn[E];
     V vn[E];
-    load(c + 2, cn, vn, rn);
+    load(p + 2, cn, vn, rn);
+    // rows are distinct within a chunk: no two slots touch one row's sums
+    // between the barriers that close the chunks
 #pragma unroll
     for (int e = 0; e < E; ++e)
       if (ra[e] != SB_PAD_ROW && jin) {
         const X a = widen<X>(va[e]) * scale;
-        acc[ra[e] * K + j] += a * ga[e];
+        X *ap = &acc[ra[e] * K + jb];
+#pragma unroll
+        for (int v = 0; v < VW; ++v) ap[v] += a * ga[e][v];
       }
-    lds_barrier();
+    if (H == 1 || (p - p0) % H == H - 1) lds_barrier();
 #pragma unroll
     for (int e = 0; e < E; ++e) {
       ra[e] = rb[e];
       va[e] = vb[e];
-      ga[e] = gb[e];
       rb[e] = rn[e];
       vb[e] = vn[e];
       cb[e] = cn[e];
+#pragma unroll
+      for (int v = 0; v < VW; ++v) ga[e][v] = gb[e][v];
     }
   }
+  // (the last chunk's barrier has ordered every addition before this read)
   const int64_t r0 = b * R;
   const int nrow = (int)min((int64_t)R, S.n_rows - r0);
   for (int i = tid; i < nrow * K; i += SB_WG) {
@@ -1550,42 +1570,45 @@ int block_fused_rows_p(int kt, int k, int64_t ldb, int64_t ldc, const void *B, c
 }
 
 template <int P, int E, int K>
-hipError_t run_sorted_blk(const SortedDev &S, int nt, int remap, const void *x, int64_t ldb,
-                          void *y, int64_t ldc, int j0, int kk, double scale, hipStream_t s) {
+hipError_t run_sorted_blk(const SortedDev &S, int remap, const void *x, int64_t ldb, void *y,
+                          int64_t ldc, int j0, int kk, double scale, hipStream_t s) {
   if (S.b1 <= S.b0) return hipSuccess;
   using X = typename Ty<P>::X;
+  constexpr int VWIDE = sizeof(X) == 8 ? 2 : 4;
   const X sc = static_cast<X>(scale);
   const dim3 grid((unsigned)(S.b1 - S.b0));
-  if (nt)
-    hipLaunchKernelGGL((k_sorted_blk<P, E, K, true>), grid, dim3(SB_WG), 0, s, S, remap, x, ldb,
-                       y, ldc, j0, kk, sc);
+  // wide column loads need every lane's first column aligned to VWIDE
+  const bool wide = kk % VWIDE == 0 && ldb % VWIDE == 0 && j0 % VWIDE == 0 &&
+                    reinterpret_cast<uintptr_t>(x) % (sizeof(X) * VWIDE) == 0;
+  if (wide)
+    hipLaunchKernelGGL((k_sorted_blk<P, E, K, VWIDE, 1>), grid, dim3(SB_WG), 0, s, S, remap, x,
+                       ldb, y, ldc, j0, kk, sc);
   else
-    hipLaunchKernelGGL((k_sorted_blk<P, E, K, false>), grid, dim3(SB_WG), 0, s, S, remap, x, ldb,
-                       y, ldc, j0, kk, sc);
+    hipLaunchKernelGGL((k_sorted_blk<P, E, K, 1, VWIDE>), grid, dim3(SB_WG), 0, s, S, remap, x,
+                       ldb, y, ldc, j0, kk, sc);
   return hipGetLastError();
 }
 
 template <int P, int K>
-hipError_t dispatch_sorted_blk_k(const SortedDev &S, int items, int nt, int remap, const void *x,
+hipError_t dispatch_sorted_blk_k(const SortedDev &S, int items, int remap, const void *x,
                                  int64_t ldb, void *y, int64_t ldc, int j0, int kk, double scale,
                                  hipStream_t s) {
   switch (items) {
-    case 1: return run_sorted_blk<P, 1, K>(S, nt, remap, x, ldb, y, ldc, j0, kk, scale, s);
-    case 2: return run_sorted_blk<P, 2, K>(S, nt, remap, x, ldb, y, ldc, j0, kk, scale, s);
-    case 4: return run_sorted_blk<P, 4, K>(S, nt, remap, x, ldb, y, ldc, j0, kk, scale, s);
+    case 1: return run_sorted_blk<P, 1, K>(S, remap, x, ldb, y, ldc, j0, kk, scale, s);
+    case 2: return run_sorted_blk<P, 2, K>(S, remap, x, ldb, y, ldc, j0, kk, scale, s);
+    case 4: return run_sorted_blk<P, 4, K>(S, remap, x, ldb, y, ldc, j0, kk, scale, s);
     default: return hipErrorInvalidValue;
   }
 }
 
 template <int P>
-hipError_t dispatch_sorted_blk(const SortedDev &S, int items, int kt, int nt, int remap,
-                               const void *x, int64_t ldb, void *y, int64_t ldc, int j0, int kk,
-                               double scale, hipStream_t s) {
+hipError_t dispatch_sorted_blk(const SortedDev &S, int items, int kt, int remap, const void *x,
+                               int64_t ldb, void *y, int64_t ldc, int j0, int kk, double scale,
+                               hipStream_t s) {
   switch (kt) {
-    case 4: return dispatch_sorted_blk_k<P, 4>(S, items, nt, remap, x, ldb, y, ldc, j0, kk, scale, s);
-    case 8: return dispatch_sorted_blk_k<P, 8>(S, items, nt, remap, x, ldb, y, ldc, j0, kk, scale, s);
-    case 16:
-      return dispatch_sorted_blk_k<P, 16>(S, items, nt, remap, x, ldb, y, ldc, j0, kk, scale, s);
+    case 4: return dispatch_sorted_blk_k<P, 4>(S, items, remap, x, ldb, y, ldc, j0, kk, scale, s);
+    case 8: return dispatch_sorted_blk_k<P, 8>(S, items, remap, x, ldb, y, ldc, j0, kk, scale, s);
+    case 16: return dispatch_sorted_blk_k<P, 16>(S, items, remap, x, ldb, y, ldc, j0, kk, scale, s);
     default: return hipErrorInvalidValue;
   }
 }
@@ -1677,23 +1700,22 @@ hipError_t launch_spmv_sorted(int prec, const SortedDev &S, int tile_items, int 
                               int xcd_remap, const void *x, void *y, hipStream_t s) {
   const int rmax = sorted_block_rows(prec);
   if (S.R < 1 || S.R > rmax || S.n_blocks != (S.n_rows + S.R - 1) / S.R || S.b0 < 0 ||
-      S.b1 > S.n_blocks || S.b0 > S.b1)
+      S.b1 > S.n_blocks || S.b0 > S.b1 || S.q != sorted_chunk_slots(prec, 1, tile_items))
     return hipErrorInvalidValue;
   SPMV_PREC_SWITCH(prec, (dispatch_sorted<PP>(S, tile_items, nontemporal, xcd_remap, x, y, s)))
 }
 
 hipError_t launch_spmv_sorted_block(int prec, const SortedDev &S, int tile_items, int kt,
-                                    int nontemporal, int xcd_remap, const void *B, int64_t ldb,
-                                    int j0, int kk, void *C, int64_t ldc, double scale,
-                                    hipStream_t s) {
+                                    int xcd_remap, const void *B, int64_t ldb, int j0, int kk,
+                                    void *C, int64_t ldc, double scale, hipStream_t s) {
   if (kt != 4 && kt != 8 && kt != 16) return hipErrorInvalidValue;
   const int rmax = sorted_block_rows(prec) / kt;
   if (S.R < 1 || S.R > rmax || S.n_blocks != (S.n_rows + S.R - 1) / S.R || S.b0 < 0 ||
-      S.b1 > S.n_blocks || S.b0 > S.b1 || j0 < 0 || kk < 1 || kk > kt || j0 + kk > ldb ||
-      j0 + kk > ldc)
+      S.b1 > S.n_blocks || S.b0 > S.b1 || S.q != sorted_chunk_slots(prec, kt, tile_items) ||
+      j0 < 0 || kk < 1 || kk > kt || j0 + kk > ldb || j0 + kk > ldc)
     return hipErrorInvalidValue;
-  SPMV_PREC_SWITCH(prec, (dispatch_sorted_blk<PP>(S, tile_items, kt, nontemporal, xcd_remap, B, ldb,
-                                                   C, ldc, j0, kk, scale, s)))
+  SPMV_PREC_SWITCH(prec, (dispatch_sorted_blk<PP>(S, tile_items, kt, xcd_remap, B, ldb, C, ldc, j0,
+                                                   kk, scale, s)))
 }
 
 int block_fused_rows(int prec, int kt, int k, int64_t ldb, int64_t ldc, const void *B, const void *C,
@@ -1799,6 +1821,12 @@ static int grid_e(int tile_items, int device) {
     case 8: return persistent_grid_for<P, 8>(device);
     default: return persistent_grid_for<P, 16>(device);
   }
+}
+
+int sorted_chunk_slots(int prec, int kt, int items) {
+  if (kt == 1) return SB_WG * items;
+  const int vwide = sorted_block_rows(prec) == SB_LDS_BYTES / 8 ? 2 : 4;  // 8- or 4-byte sums
+  return SB_WG / kt * items * vwide;
 }
 
 int sorted_block_rows(int prec) {

@@ -1006,13 +1006,14 @@ extern "C" spmv_status_t spmv_tune(spmv_handle_t h_, int32_t k, void *stream) {
           }
     // the sorted-block kernel for blocks, for parts of at least half a round
     // of its blocks (R * kt sums per block), its layout built when tried;
-    // 4 columns per pass only: with 8 or 16 its chunks of distinct rows
-    // shrink to 256-512 slots and it has not been competitive
+    // 4 or 8 columns per pass: with 16 its chunks of distinct rows shrink
+    // and it has not been competitive
     int best_sorted = 0;
     {
       int n_cu = 256;
       (void)hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, h->device);
-      for (int kt : {4}) {
+      for (int kt : {4, 8}) {
+        if (kt > 2 * k && kt != 4) continue;
         const int R = sorted_block_rows(h->prec) / kt;
         if (R <= 0 || 2 * p.n_rows < int64_t(R) * std::max(n_cu, 1)) continue;
         for (int e : {2, 4}) {

@@ -36,7 +36,7 @@ void run_block_part(spmv_handle_s *h, Part &p, int kt, int nt, int remap, int pa
     // one pass over the layout per kt columns of B and C
     const SortedDev S = sorted_dev(h, p, sorted_items, kt);
     for (int j0 = 0; j0 < k; j0 += kt)
-      hip_ok(launch_spmv_sorted_block(h->prec, S, sorted_items, kt, nt, remap, B, ldb, j0,
+      hip_ok(launch_spmv_sorted_block(h->prec, S, sorted_items, kt, remap, B, ldb, j0,
                                       std::min(kt, k - j0), C, ldc, scale, s),
              "block kernel launch");
     return;
@@ -129,6 +129,7 @@ void split_compute(spmv_handle_s *h, const void *B, void *C, hipEvent_t nl_after
     d.n_rows = h->main.n_rows;
     d.n_blocks = T->n_blocks;
     d.R = T->R;
+    d.q = T->Q;
     d.b0 = T->b_first;
     d.b1 = T->n_blocks;
     hip_ok(launch_spmv_sorted(h->prec, d, h->main.plan.tile_items, h->main.plan.nontemporal,

@@ -153,6 +153,7 @@ SortedSet build_layout(const int32_t *rp, const int32_t *hc, const unsigned char
       2);
   SortedSet S;
   S.R = R;
+  S.Q = Q;
   S.n_blocks = nb;
   S.n_chunks = cs[size_t(nb)];
   S.period = period;
@@ -182,7 +183,7 @@ const SortedSet &sorted_for(spmv_handle_s *h, Part &p, int items, int kt) {
   if (kt != 1 && kt != 4 && kt != 8 && kt != 16)
     fail(SPMV_ERR_INVALID_ARG, "sorted-block layouts take 1, 4, 8 or 16 columns per pass");
   const int R = block_rows(h, p.n_rows, checked_rmax(h) / kt);
-  const int Q = SB_WG / kt * items;
+  const int Q = sorted_chunk_slots(h->prec, kt, items);
   const int vb = val_bytes(h->prec);
   const int64_t n = p.n_rows, nnz = p.nnz;
   check_slots(p.h_row_ptr.data(), n, R, Q, 0);
@@ -290,6 +291,7 @@ SortedDev sorted_dev(spmv_handle_s *h, Part &p, int items, int kt) {
   d.n_rows = p.n_rows;
   d.n_blocks = S.n_blocks;
   d.R = S.R;
+  d.q = S.Q;
   d.b0 = 0;
   d.b1 = S.n_blocks;
   return d;

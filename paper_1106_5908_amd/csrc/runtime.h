@@ -184,6 +184,7 @@ struct SortedSet {
   DevBuf cs, col, val, row;
   int64_t n_blocks = 0, n_chunks = 0;
   int R = 0;           // rows per block
+  int Q = 0;           // slots per chunk
   int64_t period = 0;  // the sweeps start at multiples of it
   int64_t b_first = 0; // blocks before it hold no chunk (a layout of the last blocks only)
   bool after_rounds = false;  // merged layout: b_first ends whole rounds of one block per CU

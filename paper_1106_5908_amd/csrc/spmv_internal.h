@@ -192,6 +192,7 @@ struct SortedDev {
   int64_t n_rows;
   int64_t n_blocks;
   int R;
+  int q;           // slots per chunk (checked by the launchers)
   int64_t b0, b1;  // the launch covers blocks [b0, b1) of the n_blocks
 };
 // Most rows per block: their accumulators fill SB_LDS_BYTES of LDS.
@@ -200,12 +201,17 @@ int sorted_block_rows(int prec);
 hipError_t launch_spmv_sorted(int prec, const SortedDev &S, int tile_items, int nontemporal,
                               int xcd_remap, const void *x, void *y, hipStream_t s);
 // Columns [j0, j0 + kk) of C += scale * A * B (row-major, kk <= kt) over a
-// sorted-block layout whose chunks hold (1024 / kt) * tile_items slots and
-// whose blocks hold at most sorted_block_rows(prec) / kt rows.
+// sorted-block layout whose chunks hold sorted_chunk_slots(prec, kt,
+// tile_items) slots and whose blocks hold at most sorted_block_rows(prec) /
+// kt rows.
 hipError_t launch_spmv_sorted_block(int prec, const SortedDev &S, int tile_items, int kt,
-                                    int nontemporal, int xcd_remap, const void *B, int64_t ldb,
-                                    int j0, int kk, void *C, int64_t ldc, double scale,
-                                    hipStream_t s);
+                                    int xcd_remap, const void *B, int64_t ldb, int j0, int kk,
+                                    void *C, int64_t ldc, double scale, hipStream_t s);
+// Slots per chunk of a sorted-block layout: 1024 * items for one
+// right-hand side (kt = 1); for the block form with kt columns per pass,
+// the slots its wide form (2 FP64 or 4 FP32 columns per lane) takes in one
+// load step per item.
+int sorted_chunk_slots(int prec, int kt, int items);
 // Plain product over a panel set: R <= 512 rows per workgroup, tile_items
 // (4, 8, 16) entries per lane for the entries one panel holds in a row block
 // (blocks holding more are summed row by row from global memory).
