@@ -263,8 +263,10 @@ def run_spmv_path(A, x, prec, steps, warmup, label, ref=None, den=None, tune=Tru
     spmv.spmv_run(h, B, C)
     torch.cuda.synchronize()
     got = C.cpu().numpy().astype(np.float64)
-    err, ref, den = normalized_err(A, x, got, ref, den)
+    # the first call's output is checked against the oracle after the timed
+    # calls, so the device does not idle between them while the CPU works
     t = time_launches(lambda: spmv.spmv_run(h, B, C), steps, warmup)
+    err, ref, den = normalized_err(A, x, got, ref, den)
     plan = spmv.spmv_get_plan(h)
     spmv.spmv_destroy(h)
     del B, C
