@@ -1023,16 +1023,21 @@ extern "C" spmv_status_t spmv_tune(spmv_handle_t h_, int32_t k, void *stream) {
             if (f.status == SPMV_ERR_UNSUPPORTED) continue;  // rows too long
             throw;
           }
-          const float ms = tm.median_ms(
-              [&] { run_block_part(h, p, kt, 1, 1, 1, k, x.p, k, y.p, k, s, 1.0, false, e); }, s);
-          if (ms < best * 0.99f) {
-            best = ms;
-            best_kt = kt;
-            best_nt = 1;
-            best_pn = 1;
-            best_rm = 1;
-            best_fused = false;
-            best_sorted = e;
+          // remap 0 lets the XCDs share one window of B in the MALL, as
+          // for the fused walk; the layout is the same either way
+          for (int rm : {1, 0}) {
+            const float ms = tm.median_ms(
+                [&] { run_block_part(h, p, kt, 1, rm, 1, k, x.p, k, y.p, k, s, 1.0, false, e); },
+                s);
+            if (ms < best * 0.99f) {
+              best = ms;
+              best_kt = kt;
+              best_nt = 1;
+              best_pn = 1;
+              best_rm = rm;
+              best_fused = false;
+              best_sorted = e;
+            }
           }
         }
       }
