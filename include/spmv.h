@@ -417,10 +417,15 @@ spmv_status_t spmv_create_sym_crs(int64_t n, int64_t nnz, const int32_t *row_ptr
  *                kernel, with block_kt columns of B per pass, R * block_kt
  *                sums per block in LDS (R at most 16384 / block_kt rows in
  *                FP64 and F32/F64, 32768 / block_kt in F32 and BF16), and
- *                block_kt lanes per slot, each gathering one column of the
- *                slot's row of B; chunks of (1024 / block_kt) * tile_items
- *                slots.  Its layout is built when the plan is set.  A plan
- *                whose layout is refused is not kept.
+ *                block_kt / VW lanes per slot, each gathering VW adjacent
+ *                columns of the slot's row of B in one 16-byte load (VW 2
+ *                for 8-byte B, 4 for 4-byte B; 1, walking each chunk in VW
+ *                pieces, when B's leading dimension, the pass's width or
+ *                B's address do not allow it); chunks of
+ *                (1024 * VW / block_kt) * tile_items slots.  Its layout is
+ *                streamed with the nontemporal hint whatever the plan says,
+ *                and built when the plan is set.  A plan whose layout is
+ *                refused is not kept.
  *   tile_items   4, 8 or 16 (stream and fused-panel kernels); 8 or 16 (staged);
  *                1, 2 or 4 (sorted-block kernel)
  *   lanes        2, 4, 8, 16, 32 or 64 (vector kernel)
