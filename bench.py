@@ -103,28 +103,34 @@ def kappa_gpu(bytes_measured: float, flops: float, model_bytes: float) -> float:
 # ----------------------------------------------------------------------------
 
 def time_launches(fn, steps: int, warmup: int):
-    """Run fn() warmup times, then `steps` times with an event pair around
-    each call and around the whole run (all on torch's current stream, the
-    stream the library launches on).  Returns dict of ms figures."""
+    """Run fn() warmup times, then `steps` times between one event pair
+    (ms_per_step: nothing else is enqueued between the calls), then `steps`
+    more times with an event pair around each call for the per-call spread
+    (mean, p10, p50, p90).  Events on torch's current stream, the stream the
+    library launches on.  Returns dict of ms figures."""
     import torch
 
     s = torch.cuda.current_stream()
     for _ in range(warmup):
         fn()
-    torch.cuda.synchronize()
-    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     t0 = torch.cuda.Event(enable_timing=True)
     t1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     t0.record(s)
+    for _ in range(steps):
+        fn()
+    t1.record(s)
+    torch.cuda.synchronize()
+    total = t0.elapsed_time(t1)
+    # per-call events cost the runtime a little time of their own, so they
+    # stay out of the series above
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
     ev[0].record(s)
     for i in range(steps):
         fn()
         ev[i + 1].record(s)
-    t1.record(s)
     torch.cuda.synchronize()
     per = np.array([ev[i].elapsed_time(ev[i + 1]) for i in range(steps)])
-    total = t0.elapsed_time(t1)
     return {
         "ms_per_step": total / steps,
         "mean_ms": float(per.mean()),
