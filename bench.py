@@ -539,10 +539,12 @@ def split_paths(A, x, steps, warmup):
         "c_gflops": flops / (tc["p50_ms"] * 1e6),
         "split_model_bytes": mb + split_extra_bytes(info["n_nonlocal_rows"]),
         "split_model_penalty": split_extra_bytes(info["n_nonlocal_rows"]) / mb,
-        "split_kernel_penalty": tk["p50_ms"] / tu["p50_ms"] - 1.0,
+        # the split as the library runs it (the schedule spmv_tune chose),
+        # then each schedule on its own
+        "split_kernel_penalty": tkt["p50_ms"] / tu["p50_ms"] - 1.0,
+        "split_kernel_penalty_ordered": tk["p50_ms"] / tu["p50_ms"] - 1.0,
         "split_kernel_penalty_nonlocal_beside_local": tk1["p50_ms"] / tu["p50_ms"] - 1.0,
         "split_kernel_penalty_merged_tail": tk2["p50_ms"] / tu["p50_ms"] - 1.0,
-        "split_kernel_penalty_tuned_schedule": tkt["p50_ms"] / tu["p50_ms"] - 1.0,
         "c_tuned_gflops": flops / (tct["p50_ms"] * 1e6),
         "overlap_speedup_vs_a": ta["p50_ms"] / tc["p50_ms"],
         "overlap_speedup_vs_b": tb["p50_ms"] / tc["p50_ms"],
