@@ -204,7 +204,7 @@ const SortedSet *merged_tail_for(spmv_handle_s *h, int items) {
     Part &L = h->main, &N = h->nl;
     if (h->kind != SPMV_KIND_SPLIT || L.cut_row < 0 || N.n_rows == 0 || N.nnz == 0) return nullptr;
     const SortedSet &S = sorted_for(h, L, items);
-    const int R = S.R, Q = SB_WG * items, vb = val_bytes(h->prec);
+    const int R = S.R, Q = S.Q, vb = val_bytes(h->prec);
     const int64_t n_cu = cu_count(h), first = L.cut_row / R;
     // from the last whole round of blocks above the first nonlocal row
     const int64_t n = L.n_rows;
@@ -215,15 +215,10 @@ const SortedSet *merged_tail_for(spmv_handle_s *h, int items) {
     hip_ok(hipMemcpy(nl_rows.data(), N.row_ids.p, size_t(N.n_rows) * 4, hipMemcpyDeviceToHost),
            "nonlocal rows readback");
     const int64_t m_loc = int64_t(lrp[n]) - lrp[base], m = m_loc + N.nnz;
-    std::vector<int32_t> rp(size_t(n - base + 1), 0);
-    for (int64_t r = base; r < n; ++r) rp[size_t(r - base + 1)] = lrp[r + 1] - lrp[r];
     const int32_t *nrp = N.h_row_ptr.data();
-    for (int64_t i = 0; i < N.n_rows; ++i) {
-      const int64_t r = nl_rows[size_t(i)];
-      if (r < base || r >= n) fail(SPMV_ERR_STATE, "nonlocal row outside the local part's tail");
-      rp[size_t(r - base + 1)] += nrp[i + 1] - nrp[i];
-    }
-    for (size_t i = 1; i < rp.size(); ++i) rp[i] += rp[i - 1];
+    std::vector<int32_t> rp;
+    if (!merged_row_ptr(lrp, base, n, nl_rows.data(), nrp, N.n_rows, rp))
+      fail(SPMV_ERR_STATE, "nonlocal row outside the local part's tail");
     SortedSet T;
     bool refused = false;
     try {
@@ -249,21 +244,8 @@ const SortedSet *merged_tail_for(spmv_handle_s *h, int items) {
              "nonlocal val readback");
       std::vector<int32_t> hc(size_t(std::max<int64_t>(m, 1)));
       std::vector<unsigned char> hv(hc.size() * size_t(vb));
-      std::vector<int32_t> fill(rp.begin(), rp.end() - 1);
-      for (int64_t r = base; r < n; ++r) {
-        const size_t at = size_t(fill[size_t(r - base)]), k = size_t(lrp[r + 1] - lrp[r]);
-        const size_t from = size_t(lrp[r] - lrp[base]);
-        std::memcpy(&hc[at], &lc[from], k * 4);
-        std::memcpy(&hv[at * size_t(vb)], &lv[from * size_t(vb)], k * size_t(vb));
-        fill[size_t(r - base)] += int32_t(k);
-      }
-      for (int64_t i = 0; i < N.n_rows; ++i) {
-        const int64_t r = nl_rows[size_t(i)];
-        const size_t at = size_t(fill[size_t(r - base)]), k = size_t(nrp[i + 1] - nrp[i]);
-        std::memcpy(&hc[at], &nc[size_t(nrp[i])], k * 4);
-        std::memcpy(&hv[at * size_t(vb)], &nv[size_t(nrp[i]) * size_t(vb)], k * size_t(vb));
-        fill[size_t(r - base)] += int32_t(k);
-      }
+      merged_entries(lrp, base, n, lc.data(), lv.data(), nl_rows.data(), nrp, N.n_rows, nc.data(),
+                     nv.data(), vb, rp, hc.data(), hv.data());
       T = build_layout(rp.data(), hc.data(), hv.data(), vb, n, R, Q, cb, S.period);
       T.after_rounds = first >= n_cu;
     }

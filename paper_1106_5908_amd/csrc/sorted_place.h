@@ -1,9 +1,11 @@
-// Chunk placement of the sorted-block layout (host code, no HIP): plain
-// C++ so that it can be built and checked on its own.
+// Chunk placement of the sorted-block layout, and the rows its merged tail
+// is built from (host code, no HIP): plain C++ so that it can be built and
+// checked on its own.
 #pragma once
 
 #include <algorithm>
 #include <cstdint>
+#include <cstring>
 #include <numeric>
 #include <vector>
 
@@ -129,6 +131,53 @@ inline std::vector<int32_t> sorted_place_block(const int32_t *col, const int32_t
     out += Q;
   }
   return slots;
+}
+
+// Rows [base, n) of a split part with each row's local and nonlocal entries
+// (Sect. 3.4: a row's product is its local part's plus its nonlocal part's).
+// lrp: the local part's n + 1 row pointers; nl_rows (ascending) and nrp
+// (n_nl + 1 pointers): the nonlocal part's rows.  Fills rp with the merged
+// rows' n - base + 1 pointers, relative to row base; false if a nonlocal row
+// lies outside [base, n).
+inline bool merged_row_ptr(const int32_t *lrp, int64_t base, int64_t n, const int32_t *nl_rows,
+                           const int32_t *nrp, int64_t n_nl, std::vector<int32_t> &rp) {
+  rp.assign(static_cast<size_t>(n - base + 1), 0);
+  for (int64_t r = base; r < n; ++r) rp[size_t(r - base + 1)] = lrp[r + 1] - lrp[r];
+  for (int64_t i = 0; i < n_nl; ++i) {
+    const int64_t r = nl_rows[i];
+    if (r < base || r >= n) return false;
+    rp[size_t(r - base + 1)] += nrp[i + 1] - nrp[i];
+  }
+  for (size_t i = 1; i < rp.size(); ++i) rp[i] += rp[i - 1];
+  return true;
+}
+
+// The merged rows' entries in the layout rp describes: each row's local
+// entries (lc / lv: those of rows base.., lrp[base] first) in their order,
+// then its nonlocal ones (nc / nv, in nrp order); vb bytes per value.
+inline void merged_entries(const int32_t *lrp, int64_t base, int64_t n, const int32_t *lc,
+                           const unsigned char *lv, const int32_t *nl_rows, const int32_t *nrp,
+                           int64_t n_nl, const int32_t *nc, const unsigned char *nv, int vb,
+                           const std::vector<int32_t> &rp, int32_t *hc, unsigned char *hv) {
+  std::vector<int32_t> fill(rp.begin(), rp.end() - 1);
+  for (int64_t r = base; r < n; ++r) {
+    const size_t at = size_t(fill[size_t(r - base)]), k = size_t(lrp[r + 1] - lrp[r]);
+    const size_t from = size_t(lrp[r] - lrp[base]);
+    if (k) {
+      std::memcpy(&hc[at], &lc[from], k * 4);
+      std::memcpy(&hv[at * size_t(vb)], &lv[from * size_t(vb)], k * size_t(vb));
+    }
+    fill[size_t(r - base)] += int32_t(k);
+  }
+  for (int64_t i = 0; i < n_nl; ++i) {
+    const int64_t r = nl_rows[i];
+    const size_t at = size_t(fill[size_t(r - base)]), k = size_t(nrp[i + 1] - nrp[i]);
+    if (k) {
+      std::memcpy(&hc[at], &nc[size_t(nrp[i])], k * 4);
+      std::memcpy(&hv[at * size_t(vb)], &nv[size_t(nrp[i]) * size_t(vb)], k * size_t(vb));
+    }
+    fill[size_t(r - base)] += int32_t(k);
+  }
 }
 
 }  // namespace rt
