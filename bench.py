@@ -1631,6 +1631,14 @@ def main():
         r3.update(traffic_report(read_traffic(r3["plan"], "irregular8M"), r3["model_bytes"],
                                  2.0 * A3.nnz))
         paths["irregular8M_f64"] = r3
+        # the stream kernel's best plan on this matrix (4 diagonal panels), the
+        # reference the sorted-block kernel replaced and a second baseline for
+        # the block products
+        rs, _, _ = run_spmv_path(A3, x3, "f64", args.steps, args.warmup, "irregular8M stream",
+                                 ref3, den3, plan=dict(kernel=1, tile_items=8, panels=4))
+        r3["stream_panels4_ms_per_step"] = rs["ms_per_step"]
+        r3["stream_panels4_gflops"] = rs["gflops"]
+        r3["speedup_vs_stream_panels4"] = rs["ms_per_step"] / r3["ms_per_step"]
         p3 = []
         for prec in ("f32", "bf16", "f32f64"):
             r, _, _ = run_spmv_path(A3, x3, prec, args.steps, args.warmup, "irregular8M", ref3, den3)
@@ -1642,6 +1650,8 @@ def main():
         paths["split_irregular8M"] = sp
         paths["overlap_probe"] = overlap_probe()
         paths["block_irregular8M"] = block_paths(A3, max(10, args.steps // 4), 3, r3["ms_per_step"])
+        for b in paths["block_irregular8M"]:
+            b["speedup_vs_k_fp64_stream_calls"] = b["k"] * rs["ms_per_step"] / b["ms_per_step"]
         paths["gather_ceiling_irregular8M"] = gather_ceiling(
             A3, r3["plan"], r3["ms_per_step"],
             [(b["k"], b["plan"], b["ms_per_step"]) for b in paths["block_irregular8M"] if b["prec"] == "f64"])
